@@ -1,0 +1,192 @@
+/*
+ * flexis.h — C ABI of the MI355X (gfx950) support-counting library for
+ * FLEXIS-style frequent subgraph mining (Sharma, Reinehr, Mehta, Wu,
+ * "FLEXIS: FLExible Frequent Subgraph Mining using Maximal Independent
+ * Sets", arXiv 2404.01585).
+ *
+ * One call answers the paper's metric step for one candidate pattern
+ * (Algorithm 5, the matcher loop, and its per-candidate matcher of
+ * Section 3.2.2): enumerate the embeddings of a labeled pattern in a
+ * labeled data graph, take the greedy maximal independent set (mIS) of
+ * those embeddings, and compare its size with the threshold tau of the
+ * tau equation (Section 3.1.1).
+ *
+ * Conventions for every entry point:
+ *   - Return value: FX_OK (0) or a negative fx_status.  On error the
+ *     outputs are left untouched and fx_last_error() describes the cause.
+ *   - Host pointers are only read during the call; the caller keeps
+ *     ownership.  Device memory the library needs is allocated by the
+ *     library and released by the matching destroy call.
+ *   - All device work runs on the stream given in fx_ctx_opts (the
+ *     caller's HIP stream, e.g. torch.cuda.current_stream().cuda_stream),
+ *     and every call returns only after its results are on the host.
+ *   - A context (and the graphs loaded into it) is used by one thread at a
+ *     time; the server entry points are the exception and are thread-safe.
+ *   - Vertex ids are the caller's ids 0..nv-1.  Labels are any int32 >= 0;
+ *     the library maps them to a dense range internally.
+ */
+#ifndef FLEXIS_H
+#define FLEXIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fx_status;
+enum {
+    FX_OK = 0,
+    FX_EINVAL = -1,   /* bad argument (NULL pointer, sigma <= 0, lambda outside [0,1], ...) */
+    FX_EGRAPH = -2,   /* malformed data graph (see fx_graph_desc) */
+    FX_EPATTERN = -3, /* malformed pattern (see fx_pattern) */
+    FX_ENOMEM = -4,   /* device or host allocation failed */
+    FX_EDEVICE = -5,  /* a HIP runtime call failed */
+    FX_EBUSY = -6,    /* object still in use (destroy order) */
+    FX_ETIMEOUT = -7, /* server wait timed out */
+    FX_ELIMIT = -8    /* a size limit was exceeded (pattern > 16 vertices, > 65535 labels, ...) */
+};
+
+/* Result modes (Section 3.1.1, early termination at tau). */
+enum {
+    FX_MODE_FULL = 0,   /* exact support, verdict, embedding count and digest */
+    FX_MODE_VERDICT = 1 /* verdict only; the search stops as soon as it is decided */
+};
+
+#define FX_MAX_PATTERN_VERTICES 16
+
+typedef struct fx_ctx fx_ctx;
+typedef struct fx_graph fx_graph;
+typedef struct fx_server fx_server;
+
+/* Context options.
+ *   device            HIP device ordinal.
+ *   hip_stream        hipStream_t to run on; NULL means the null stream.
+ *   slice_rows        rows of partial embeddings processed per expansion step
+ *                     (0 = default 2^20).  Bounds the device workspace:
+ *                     about slice_rows * (4 n + 40) bytes per pattern level.
+ *   count_cap         saturation cap of the embedding count (0 = 2^62).
+ *   flags             reserved, must be 0. */
+typedef struct {
+    int32_t device;
+    void *hip_stream;
+    int64_t slice_rows;
+    int64_t count_cap;
+    uint32_t flags;
+} fx_ctx_opts;
+
+fx_status fx_ctx_create(const fx_ctx_opts *opts, fx_ctx **out);
+/* Fails with FX_EBUSY while graphs loaded into the context still exist. */
+fx_status fx_ctx_destroy(fx_ctx *ctx);
+
+/* Data graph: an undirected simple labeled graph as symmetric CSR (the
+ * paper loads its data graphs undirected, Section 4.1; vertex labels as in
+ * Section 2.1.4, edge labels as in Section 2.3.4).
+ *   num_vertices      nv >= 1.
+ *   num_adj           2|E| adjacency entries.
+ *   offset_bytes      4 (int32 row_ptr) or 8 (int64 row_ptr).
+ *   row_ptr           [nv+1], row_ptr[0] = 0, non-decreasing, row_ptr[nv] = num_adj.
+ *   col               [num_adj] int32 neighbour ids; each row strictly ascending,
+ *                     no self-loops; (u,v) present iff (v,u) present.
+ *   vlabel            [nv] int32 >= 0.
+ *   elabel            [num_adj] int32 >= 0, or NULL for all-zero; the label of
+ *                     (u,v) must equal the label of (v,u).
+ *   on_device         0: the arrays are host memory; 1: device memory.  Either
+ *                     way the library validates and builds its own copy, so the
+ *                     arrays may be freed after the call.
+ * Errors: FX_EGRAPH for any violation above, FX_ELIMIT for more than 65535
+ * distinct vertex or edge labels or more than 2^31-1 vertices. */
+typedef struct {
+    int64_t num_vertices;
+    int64_t num_adj;
+    int32_t offset_bytes;
+    const void *row_ptr;
+    const int32_t *col;
+    const int32_t *vlabel;
+    const int32_t *elabel;
+    int32_t on_device;
+} fx_graph_desc;
+
+fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *desc, fx_graph **out);
+fx_status fx_graph_destroy(fx_graph *g);
+
+/* Pattern: a connected simple labeled graph with 1 <= n <= 16 vertices,
+ * numbered 0..n-1 as submitted (the numbering fixes the greedy order, see
+ * fx_support).  edges holds m pairs (a, b), elabel m labels or NULL for all
+ * zero.  The pattern is copied at call time.
+ * Errors: FX_EPATTERN (disconnected, loops, repeated edges, bad endpoints),
+ * FX_ELIMIT (n > 16). */
+typedef struct {
+    int32_t n, m;
+    const int32_t *vlabel;
+    const int32_t *edges;
+    const int32_t *elabel;
+} fx_pattern;
+
+/* Per-pattern result.
+ *   tau               threshold of the tau equation (Section 3.1.1) computed in
+ *                     exact integer arithmetic with lambda rounded to parts per
+ *                     million; the verdict uses max(tau, 1).
+ *   support           FULL: size of the greedy mIS.  VERDICT: tau if frequent, else -1.
+ *   frequent          1 iff support >= max(tau, 1).
+ *   count_saturated   FULL: 1 iff |M| >= count_cap.
+ *   embedding_count   FULL: min(|M|, count_cap).  VERDICT: -1.
+ *   digest            FULL and not saturated: (sum mod 2^64, xor) of the
+ *                     SplitMix64 hash chain of every embedding tuple (seeds
+ *                     0x243f6a8885a308d3 and 0x13198a2e03707344); else 0.
+ *   steps             expansion steps executed on the device.
+ *   rounds            parallel greedy rounds executed on the device.
+ *   device_ms         time between the first and last device event of the query.
+ *   alg_bytes         algorithmic bytes the query moves (see the design notes). */
+typedef struct {
+    int64_t tau;
+    int64_t support;
+    int32_t frequent;
+    int32_t count_saturated;
+    int64_t embedding_count;
+    uint64_t digest[2];
+    int32_t steps;
+    int32_t rounds;
+    double device_ms;
+    uint64_t alg_bytes;
+} fx_result;
+
+/* tau of the tau equation (Section 3.1.1):
+ *   tau = floor(sigma * ((n-1) * lambda + 1) / n),
+ * with lambda rounded to parts per million first.  Errors: FX_EINVAL for
+ * sigma < 0, lambda outside [0,1] or n < 1. */
+fx_status fx_tau(int64_t sigma, double lambda, int32_t n, int64_t *tau_out);
+
+/* Support of one pattern (Algorithm 5 for a single candidate; Section 3.2.2).
+ * Embeddings are the injective, label- and edge-label-preserving maps of
+ * Section 2.1.4 (non-induced).  They are ranked lexicographically by
+ * (f(0), ..., f(n-1)) and the greedy keeps every embedding that shares no
+ * data vertex with an earlier kept one; support is the number kept.
+ *   sigma >= 1, 0 <= lambda <= 1, mode FX_MODE_FULL or FX_MODE_VERDICT.
+ *   selected (optional, host, [selected_cap * n] int32): FULL mode receives the
+ *   first min(support, selected_cap) kept embeddings in rank order. */
+fx_status fx_support(fx_graph *g, const fx_pattern *p, int64_t sigma, double lambda, int32_t mode,
+                     fx_result *out, int32_t *selected, int64_t selected_cap);
+
+/* All embeddings of a pattern in rank order (Section 2.4, the mapping set M).
+ * Writes the first min(|M|, cap) tuples ([cap * n] int32, host) and sets
+ * *count_out = |M| (exact, not capped by the context's count_cap). */
+fx_status fx_enumerate(fx_graph *g, const fx_pattern *p, int32_t *rows, int64_t cap, int64_t *count_out);
+
+/* A batch of patterns (one mining level, Algorithm 1's candidate set) in one
+ * device pass.  Each pattern gets its own sigma[i], lambda[i]; results equal
+ * those of fx_support called one by one. */
+fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, const int64_t *sigma,
+                           const double *lambda, int32_t mode, fx_result *out);
+
+/* Thread-local description of the last error. */
+const char *fx_last_error(void);
+
+/* Library version string. */
+const char *fx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLEXIS_H */

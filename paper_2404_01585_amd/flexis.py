@@ -1,0 +1,267 @@
+"""Python binding of the C ABI in include/flexis.h (argument marshalling only).
+
+Every step of the support computation runs in the HIP library
+``libflexis.so``; this module only converts numpy arrays / torch tensors and
+patterns into the C structs and back.  PyTorch is used for the HIP stream
+(``torch.cuda.current_stream()``) and, optionally, device-resident input
+arrays.  If the library is not built, importing works but every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libflexis.so")
+
+FX_OK = 0
+FX_EINVAL = -1
+FX_EGRAPH = -2
+FX_EPATTERN = -3
+FX_ENOMEM = -4
+FX_EDEVICE = -5
+FX_EBUSY = -6
+FX_ETIMEOUT = -7
+FX_ELIMIT = -8
+
+MODE_FULL = 0
+MODE_VERDICT = 1
+
+_STATUS_NAMES = {0: "FX_OK", -1: "FX_EINVAL", -2: "FX_EGRAPH", -3: "FX_EPATTERN", -4: "FX_ENOMEM",
+                 -5: "FX_EDEVICE", -6: "FX_EBUSY", -7: "FX_ETIMEOUT", -8: "FX_ELIMIT"}
+
+# Every symbol include/flexis.h declares.
+EXPORTS = ["fx_ctx_create", "fx_ctx_destroy", "fx_graph_load", "fx_graph_destroy", "fx_tau", "fx_support",
+           "fx_enumerate", "fx_support_batch", "fx_last_error", "fx_version"]
+
+
+class FxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("hip_stream", ctypes.c_void_p), ("slice_rows", ctypes.c_int64),
+                ("count_cap", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("num_vertices", ctypes.c_int64), ("num_adj", ctypes.c_int64), ("offset_bytes", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("vlabel", ctypes.c_void_p),
+                ("elabel", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+
+
+class PatternC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("vlabel", ctypes.c_void_p),
+                ("edges", ctypes.c_void_p), ("elabel", ctypes.c_void_p)]
+
+
+class ResultC(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_int64), ("support", ctypes.c_int64), ("frequent", ctypes.c_int32),
+                ("count_saturated", ctypes.c_int32), ("embedding_count", ctypes.c_int64),
+                ("digest", ctypes.c_uint64 * 2), ("steps", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("device_ms", ctypes.c_double), ("alg_bytes", ctypes.c_uint64)]
+
+    def to_dict(self) -> Dict:
+        return dict(tau=self.tau, support=self.support, frequent=self.frequent,
+                    count_saturated=self.count_saturated, embedding_count=self.embedding_count,
+                    digest=(int(self.digest[0]), int(self.digest[1])), steps=self.steps, rounds=self.rounds,
+                    device_ms=self.device_ms, alg_bytes=int(self.alg_bytes))
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load_library():
+    """Loads libflexis.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run paper_2404_01585_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.fx_last_error.restype = ctypes.c_char_p
+    lib.fx_last_error.argtypes = []
+    lib.fx_version.restype = ctypes.c_char_p
+    lib.fx_version.argtypes = []
+    lib.fx_tau.restype = ctypes.c_int32
+    lib.fx_tau.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P]
+    lib.fx_ctx_create.restype = ctypes.c_int32
+    lib.fx_ctx_create.argtypes = [P, P]
+    lib.fx_ctx_destroy.restype = ctypes.c_int32
+    lib.fx_ctx_destroy.argtypes = [P]
+    lib.fx_graph_load.restype = ctypes.c_int32
+    lib.fx_graph_load.argtypes = [P, P, P]
+    lib.fx_graph_destroy.restype = ctypes.c_int32
+    lib.fx_graph_destroy.argtypes = [P]
+    lib.fx_support.restype = ctypes.c_int32
+    lib.fx_support.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P, P, ctypes.c_int64]
+    lib.fx_enumerate.restype = ctypes.c_int32
+    lib.fx_enumerate.argtypes = [P, P, P, ctypes.c_int64, P]
+    lib.fx_support_batch.restype = ctypes.c_int32
+    lib.fx_support_batch.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_int32, P]
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != FX_OK:
+        raise FxError(status, load_library().fx_last_error().decode(errors="replace"))
+
+
+def last_error() -> str:
+    return load_library().fx_last_error().decode(errors="replace")
+
+
+def tau(sigma: int, lam: float, n: int) -> int:
+    out = ctypes.c_int64(0)
+    _check(load_library().fx_tau(int(sigma), float(lam), int(n), ctypes.byref(out)))
+    return int(out.value)
+
+
+class _PatternHolder:
+    """Keeps the numpy arrays of a pattern alive while C holds pointers to them."""
+
+    def __init__(self, vlabel: Sequence[int], edges: Sequence[Tuple[int, int]], elabel: Optional[Sequence[int]]):
+        self.vl = np.ascontiguousarray(vlabel, dtype=np.int32)
+        self.ed = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1), dtype=np.int32)
+        m = self.ed.shape[0] // 2
+        self.el = (np.zeros(m, dtype=np.int32) if elabel is None
+                   else np.ascontiguousarray(elabel, dtype=np.int32))
+        self.c = PatternC(self.vl.shape[0], m, self.vl.ctypes.data, self.ed.ctypes.data if m else None,
+                          self.el.ctypes.data if m else None)
+
+    @classmethod
+    def of(cls, p) -> "_PatternHolder":
+        return cls(p.vlabel, p.edges, p.elabel)
+
+
+def _current_stream() -> int:
+    import torch
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """fx_ctx: a device, a stream, and the workspace sizing."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None, slice_rows: int = 0, count_cap: int = 0):
+        lib = load_library()
+        if stream is None:
+            import torch
+            torch.cuda.set_device(device)
+            stream = _current_stream()
+        self._opts = CtxOpts(device, stream or None, slice_rows, count_cap, 0)
+        self._h = ctypes.c_void_p()
+        _check(lib.fx_ctx_create(ctypes.byref(self._opts), ctypes.byref(self._h)))
+        self.count_cap = count_cap if count_cap > 0 else (1 << 62)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def load_graph(self, g, on_device: bool = False) -> "DeviceGraph":
+        return DeviceGraph(self, g, on_device=on_device)
+
+    def close(self):
+        if self._h:
+            _check(load_library().fx_ctx_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class DeviceGraph:
+    """fx_graph: a data graph resident on the device."""
+
+    def __init__(self, ctx: Context, g, on_device: bool = False):
+        lib = load_library()
+        self.ctx = ctx
+        self.nv = int(g.row_ptr.shape[0] - 1)
+        if on_device:
+            import torch
+            rp = g.row_ptr if isinstance(g.row_ptr, torch.Tensor) else torch.from_numpy(np.asarray(g.row_ptr))
+            keep = [None if t is None else (t.contiguous() if t.is_cuda else t.contiguous().cuda())
+                    for t in (rp, _t(g.col), _t(g.vlabel), _t(g.elabel))]
+            self._keep = keep
+            ob = keep[0].element_size()
+            desc = GraphDesc(self.nv, int(keep[1].numel()), ob, keep[0].data_ptr(), keep[1].data_ptr(),
+                             keep[2].data_ptr(), None if keep[3] is None else keep[3].data_ptr(), 1)
+        else:
+            rp = np.ascontiguousarray(g.row_ptr)
+            if rp.dtype not in (np.int32, np.int64):
+                rp = rp.astype(np.int64)
+            col = np.ascontiguousarray(g.col, dtype=np.int32)
+            vl = np.ascontiguousarray(g.vlabel, dtype=np.int32)
+            el = None if g.elabel is None else np.ascontiguousarray(g.elabel, dtype=np.int32)
+            self._keep = [rp, col, vl, el]
+            desc = GraphDesc(self.nv, int(col.shape[0]), rp.dtype.itemsize, rp.ctypes.data,
+                             col.ctypes.data if col.shape[0] else None, vl.ctypes.data,
+                             el.ctypes.data if (el is not None and el.shape[0]) else None, 0)
+        self._h = ctypes.c_void_p()
+        _check(lib.fx_graph_load(ctx.handle, ctypes.byref(desc), ctypes.byref(self._h)))
+        self._keep = None
+
+    def support(self, p, sigma: int, lam: float, mode: int = MODE_FULL, selected_cap: int = 0) -> Dict:
+        """fx_support for one pattern; returns the fx_result fields (+ 'selected')."""
+        ph = _PatternHolder.of(p)
+        res = ResultC()
+        sel = np.zeros((max(selected_cap, 1), ph.vl.shape[0]), dtype=np.int32)
+        _check(load_library().fx_support(self._h, ctypes.byref(ph.c), int(sigma), float(lam), int(mode),
+                                         ctypes.byref(res), sel.ctypes.data if selected_cap else None,
+                                         int(selected_cap)))
+        d = res.to_dict()
+        if selected_cap and mode == MODE_FULL:
+            d["selected"] = sel[:min(selected_cap, max(res.support, 0))]
+        return d
+
+    def enumerate(self, p, cap: int) -> Tuple[int, np.ndarray]:
+        """fx_enumerate: |M| and the first `cap` embeddings in rank order."""
+        ph = _PatternHolder.of(p)
+        rows = np.zeros((max(cap, 1), ph.vl.shape[0]), dtype=np.int32)
+        cnt = ctypes.c_int64(0)
+        _check(load_library().fx_enumerate(self._h, ctypes.byref(ph.c), rows.ctypes.data if cap else None,
+                                           int(cap), ctypes.byref(cnt)))
+        return int(cnt.value), rows[:min(cap, cnt.value)]
+
+    def support_batch(self, patterns: List, sigma: Sequence[int], lam: Sequence[float],
+                      mode: int = MODE_FULL) -> List[Dict]:
+        holders = [_PatternHolder.of(p) for p in patterns]
+        arr = (PatternC * max(len(holders), 1))(*[h.c for h in holders])
+        sg = np.ascontiguousarray(sigma, dtype=np.int64)
+        lm = np.ascontiguousarray(lam, dtype=np.float64)
+        res = (ResultC * max(len(holders), 1))()
+        _check(load_library().fx_support_batch(self._h, len(holders), arr, sg.ctypes.data, lm.ctypes.data,
+                                               int(mode), res))
+        return [res[i].to_dict() for i in range(len(holders))]
+
+    def close(self):
+        if self._h:
+            _check(load_library().fx_graph_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _t(a):
+    import torch
+    if a is None:
+        return None
+    return a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))

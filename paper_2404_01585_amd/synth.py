@@ -301,6 +301,8 @@ def sample_pattern(g: Graph, rng: np.random.Generator, k: int, shape: str,
     one embedding.  Vertices are numbered in BFS order from the vertex with the
     rarest label, which makes every prefix connected.
     """
+    if shape == "cycle" and k < 3:
+        shape = "tree"  # a simple cycle needs three vertices
     nv = g.num_vertices
     deg = g.degree()
     vcount = np.bincount(g.vlabel, minlength=int(g.vlabel.max()) + 1)

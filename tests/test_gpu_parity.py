@@ -1,0 +1,220 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer results must match exactly: support, verdict, tau, embedding count,
+saturation flag, digest of the embedding set, the selected embeddings in
+rank order, and the full embedding list where it is listed."""
+
+import numpy as np
+import pytest
+
+from helpers import load_fixture, relabel_all
+from oracle import oracle as O
+from paper_2404_01585_amd import flexis as fx
+from paper_2404_01585_amd.synth import (Graph, Pattern, csr_from_edges, random_connected_pattern, sample_patterns,
+                                        tiny_random_graph, workload_graph)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_cuda):
+    c = fx.Context(device=0)
+    yield c
+
+
+@pytest.fixture(scope="module")
+def ctx_small(torch_cuda):
+    # tiny slices: every level is cut into many slices with ragged tails
+    c = fx.Context(device=0, slice_rows=64)
+    yield c
+
+
+def full_match(dg, g, p, sigma, lam, count_cap=1 << 62, sel=True):
+    want = O.query(g, p, sigma, lam, O.FULL, count_cap=count_cap)
+    got = dg.support(p, sigma, lam, fx.MODE_FULL, selected_cap=(g.num_vertices if sel else 0))
+    for k in ("tau", "support", "frequent", "embedding_count", "count_saturated", "digest"):
+        assert got[k] == want[k], (k, got[k], want[k])
+    if sel:
+        assert np.array_equal(got["selected"], want["selected"]), (got["selected"], want["selected"])
+    return got
+
+
+def verdict_match(dg, g, p, sigma, lam):
+    want = O.query(g, p, sigma, lam, O.VERDICT)
+    got = dg.support(p, sigma, lam, fx.MODE_VERDICT)
+    for k in ("tau", "support", "frequent", "embedding_count"):
+        assert got[k] == want[k], (k, got[k], want[k])
+
+
+def list_match(dg, g, p, cap=1 << 16):
+    cnt_w, rows_w = O.enumerate_embeddings(g, p, cap=cap)
+    cnt_g, rows_g = dg.enumerate(p, cap)
+    assert cnt_g == cnt_w
+    assert np.array_equal(rows_g, rows_w)
+
+
+# ---------------------------------------------------------------------------
+
+def test_running_example(ctx, ctx_small):
+    fx1 = load_fixture("running_example.txt")
+    fx2 = load_fixture("tight_bound.txt")
+    D, Dm = fx1["D"], fx2["Dm"]
+    tri = Pattern([0, 0, 0], [(0, 1), (1, 2), (0, 2)], [0, 0, 0])
+    for c in (ctx, ctx_small):
+        with c.load_graph(D) as dg:
+            for name in ("P1", "P2"):
+                _say("running example", name)
+                p = fx1[name]
+                got = full_match(dg, D, p, 2, 1.0)
+                list_match(dg, D, p)
+                for sigma, lam in ((3, 1.0), (2, 1.0), (2, 0.25), (7, 1.0)):
+                    full_match(dg, D, p, sigma, lam)
+                    verdict_match(dg, D, p, sigma, lam)
+            assert got["support"] == 1
+        Du = relabel_all(D)
+        with c.load_graph(Du) as dg:
+            _say("unlabeled triangle")
+            got = full_match(dg, Du, tri, 2, 1.0)
+            assert got["embedding_count"] == 30 and got["support"] == 2
+            list_match(dg, Du, tri)
+        with c.load_graph(Dm) as dg:
+            _say("tight bound example")
+            got = full_match(dg, Dm, fx2["Pm"], 1, 1.0)
+            assert got["support"] == 1 and got["embedding_count"] == 48
+            list_match(dg, Dm, fx2["Pm"])
+
+
+def _tiny_cases(n_cases, seed):
+    rng = np.random.default_rng(seed)
+    for idx in range(n_cases):
+        nv = int(rng.integers(4, 40))
+        g = tiny_random_graph(rng, nv, float(rng.uniform(0.08, 0.5)), int(rng.integers(1, 4)), int(rng.integers(1, 3)))
+        n = int(rng.integers(1, 6))
+        p = random_connected_pattern(rng, n, int(g.vlabel.max()) + 1, int(g.elabel.max()) + 1 if g.num_adj else 1,
+                                     extra_edge_p=0.3, prefix_connected=bool(rng.random() < 0.75))
+        yield idx, g, p
+
+
+@pytest.mark.parametrize("which", ["default", "small"])
+def test_random_tiny(ctx, ctx_small, which):
+    c = ctx if which == "default" else ctx_small
+    for idx, g, p in _tiny_cases(150, 99 if which == "default" else 98):
+        _say("tiny", which, idx, "nv", g.num_vertices, "n", p.n)
+        with c.load_graph(g) as dg:
+            full_match(dg, g, p, 2, 1.0)
+            list_match(dg, g, p)
+            for sigma in (1, 2, 3, 5):
+                verdict_match(dg, g, p, sigma, 0.5)
+
+
+@pytest.fixture(scope="module")
+def er1k():
+    return workload_graph("er1k")
+
+
+def test_er1k_sampled_patterns(ctx, ctx_small, er1k):
+    g = er1k
+    pats = sample_patterns(g, 40, seed=7, kmin=2, kmax=6)
+    with ctx.load_graph(g) as dg, ctx_small.load_graph(g) as ds:
+        for i, p in enumerate(pats):
+            _say("er1k pattern", i, "n", p.n, "m", p.m)
+            a = full_match(dg, g, p, 20, 1.0)
+            b = full_match(ds, g, p, 20, 1.0)
+            assert a["support"] == b["support"]
+            verdict_match(dg, g, p, 20, 1.0)
+            verdict_match(ds, g, p, 20, 0.3)
+
+
+def test_er1k_listing(ctx, er1k):
+    g = er1k
+    pats = sample_patterns(g, 6, seed=8, kmin=3, kmax=4)
+    with ctx.load_graph(g) as dg:
+        for i, p in enumerate(pats):
+            _say("er1k listing", i)
+            list_match(dg, g, p, cap=1 << 20)
+
+
+def test_count_cap_saturation(torch_cuda, er1k):
+    g = er1k
+    star = Pattern([0, 1, 1, 1], [(0, 1), (0, 2), (0, 3)], [0, 0, 0])
+    total = O.count(g, star, 1 << 62)[0]
+    assert total > 100
+    for cap in (1, 7, total // 3, total, total + 1):
+        _say("count cap", cap)
+        c = fx.Context(device=0, slice_rows=128, count_cap=cap)
+        with c.load_graph(g) as dg:
+            full_match(dg, g, star, 20, 1.0, count_cap=cap)
+        c.close()
+
+
+def test_edge_cases(ctx):
+    # isolated vertices, an empty adjacency, single-vertex patterns, absent labels
+    g = csr_from_edges(6, [0, 1], [1, 2], [0, 0], [0, 0, 1, 1, 2, 2])
+    single = Pattern([1], [], [])
+    absent = Pattern([0, 9], [(0, 1)], [0])
+    absent_el = Pattern([0, 0], [(0, 1)], [5])
+    with ctx.load_graph(g) as dg:
+        _say("edge cases")
+        got = full_match(dg, g, single, 1, 1.0)
+        assert got["support"] == 2
+        for p in (absent, absent_el):
+            r = dg.support(p, 1, 1.0, fx.MODE_FULL)
+            assert r["support"] == 0 and r["embedding_count"] == 0 and r["frequent"] == 0
+            assert dg.support(p, 1, 1.0, fx.MODE_VERDICT)["frequent"] == 0
+    empty = csr_from_edges(5, [], [], [], [0, 0, 0, 1, 1])
+    with ctx.load_graph(empty) as dg:
+        full_match(dg, empty, Pattern([0], [], []), 3, 1.0)
+        full_match(dg, empty, Pattern([0, 0], [(0, 1)], [0]), 1, 1.0)
+    # the largest pattern: a 16-vertex path in a 40-vertex path graph
+    chain = csr_from_edges(40, list(range(39)), list(range(1, 40)), [0] * 39, [0] * 40)
+    path16 = Pattern([0] * 16, [(i, i + 1) for i in range(15)], [0] * 15)
+    with ctx.load_graph(chain) as dg:
+        _say("path16")
+        got = full_match(dg, chain, path16, 2, 1.0)
+        assert got["embedding_count"] == 2 * (40 - 15)
+        list_match(dg, chain, path16)
+
+
+def test_errors(ctx):
+    bad = Graph(row_ptr=np.array([0, 1, 1], dtype=np.int64), col=np.array([1], dtype=np.int32),
+                vlabel=np.array([0, 0], dtype=np.int32), elabel=np.array([0], dtype=np.int32))
+    with pytest.raises(fx.FxError) as e:
+        ctx.load_graph(bad)
+    assert e.value.status == fx.FX_EGRAPH
+    g = csr_from_edges(4, [0, 1, 2], [1, 2, 3], [0, 0, 0], [0, 0, 0, 0])
+    with ctx.load_graph(g) as dg:
+        with pytest.raises(fx.FxError) as e:
+            dg.support(Pattern([0, 0, 0], [(0, 1)], [0]), 1, 1.0)
+        assert e.value.status == fx.FX_EPATTERN
+        with pytest.raises(fx.FxError) as e:
+            dg.support(Pattern([0] * 17, [(i, i + 1) for i in range(16)], [0] * 16), 1, 1.0)
+        assert e.value.status == fx.FX_ELIMIT
+        with pytest.raises(fx.FxError) as e:
+            dg.support(Pattern([0, 0], [(0, 1)], [0]), 0, 1.0)
+        assert e.value.status == fx.FX_EINVAL
+        with pytest.raises(fx.FxError) as e:
+            dg.support(Pattern([0, 0], [(0, 1)], [0]), 1, 1.5)
+        assert e.value.status == fx.FX_EINVAL
+
+
+def test_device_resident_input(ctx, er1k):
+    import torch
+    g = er1k
+    gd = Graph(row_ptr=torch.from_numpy(g.row_ptr).cuda(), col=torch.from_numpy(g.col).cuda(),
+               vlabel=torch.from_numpy(g.vlabel).cuda(), elabel=torch.from_numpy(g.elabel).cuda())
+    p = Pattern([0, 1, 2], [(0, 1), (1, 2)], [0, 0])
+    _say("device resident graph")
+    with ctx.load_graph(gd, on_device=True) as dg:
+        full_match(dg, g, p, 20, 1.0)
