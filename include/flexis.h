@@ -62,16 +62,25 @@ typedef struct fx_server fx_server;
 /* Context options.
  *   device            HIP device ordinal.
  *   hip_stream        hipStream_t to run on; NULL means the null stream.
- *   slice_rows        rows of partial embeddings processed per expansion step
- *                     (0 = default 2^20).  Bounds the device workspace:
- *                     about slice_rows * (4 n + 40) bytes per pattern level.
+ *   slice_rows        capacity, in partial embeddings, of each level of a
+ *                     pattern's slice stack (0 = default 2^17): one step
+ *                     expands at most this many candidates of a level.  A
+ *                     pattern's stack takes about slice_rows * (4 l + 25)
+ *                     bytes per level l.
  *   count_cap         saturation cap of the embedding count (0 = 2^62).
- *   flags             reserved, must be 0. */
+ *   mem_budget_bytes  device memory the per-pattern stacks of one batch may
+ *                     hold at once (0 = 64 GiB); patterns are admitted while
+ *                     their projected stack bytes fit.
+ *   flags             0, or FX_CTX_KERNEL_TIMING: bracket the kernels of every
+ *                     step with HIP events on the context's stream and
+ *                     accumulate their durations (see fx_ctx_stats). */
+#define FX_CTX_KERNEL_TIMING 1u
 typedef struct {
     int32_t device;
     void *hip_stream;
     int64_t slice_rows;
     int64_t count_cap;
+    int64_t mem_budget_bytes;
     uint32_t flags;
 } fx_ctx_opts;
 
@@ -137,7 +146,8 @@ typedef struct {
  *   steps             expansion steps executed on the device.
  *   rounds            parallel greedy rounds executed on the device.
  *   device_ms         time between the first and last device event of the query.
- *   alg_bytes         algorithmic bytes the query moves (see the design notes). */
+ *   alg_bytes         algorithmic bytes of the query's expansion kernels (as in
+ *                     fx_stats: probe plus scatter). */
 typedef struct {
     int64_t tau;
     int64_t support;
@@ -178,6 +188,34 @@ fx_status fx_enumerate(fx_graph *g, const fx_pattern *p, int32_t *rows, int64_t 
  * those of fx_support called one by one. */
 fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, const int64_t *sigma,
                            const double *lambda, int32_t mode, fx_result *out);
+
+/* Accumulated device statistics of a context (since creation or the last
+ * reset).  Durations are only collected with FX_CTX_KERNEL_TIMING.
+ *   probe_*     the expansion test kernel (one launch per step)
+ *   scatter_*   the ordered write of surviving candidates (one launch per step)
+ *   greedy_*    the greedy mIS kernels (hash build and rounds)
+ *   *_alg_bytes algorithmic bytes: bytes the operation must move at minimum
+ *               on this layout (8-byte packed adjacency entries, 4-byte ids),
+ *               counted on the device: candidate entries, partial rows and
+ *               their run descriptors, every binary-search step of an
+ *               adjacency test (8 bytes) and the used-set words read.
+ *   steps, syncs, queries   host-side counts. */
+typedef struct {
+    uint64_t probe_launches;
+    double probe_ms;
+    uint64_t probe_alg_bytes;
+    uint64_t scatter_launches;
+    double scatter_ms;
+    uint64_t scatter_alg_bytes;
+    uint64_t greedy_launches;
+    double greedy_ms;
+    uint64_t steps;
+    uint64_t syncs;
+    uint64_t queries;
+} fx_stats;
+
+/* Copies the context's statistics into *out; reset != 0 zeroes them after. */
+fx_status fx_ctx_stats(fx_ctx *ctx, fx_stats *out, int32_t reset);
 
 /* Thread-local description of the last error. */
 const char *fx_last_error(void);

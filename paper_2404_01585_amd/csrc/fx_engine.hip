@@ -1,0 +1,566 @@
+// Pattern plans and the multi-query engine.
+//
+// A query's slice stack holds, for every level l (l pattern vertices
+// matched), the partial embeddings of the current slice of level l-1 and
+// each one's candidate run for pattern vertex l.  A step expands one slice
+// of the deepest level that still has unexpanded candidates, so complete
+// embeddings appear in rank order (lexicographic in submitted vertex order,
+// ascending ids).  Every step serves all active queries at once: each
+// contributes one segment to the same kernel launches, and the host reads
+// all their counters with one copy and one synchronisation.
+//
+// Phases of a query:
+//   support  partial embeddings and candidates that meet the used-vertex set
+//            U are dropped (the bitmap of the matcher in Section 3.2.2); the
+//            complete embeddings of each slice go through the greedy, which
+//            extends U.  In VERDICT mode the query ends as soon as the
+//            support reaches tau (the early termination of Section 3.1.1).
+//   count    (FULL mode) every embedding is enumerated again without U and
+//            counted and hashed at the last vertex, up to the count cap.
+//   list     (fx_enumerate) every complete embedding is written out.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "fx_host.h"
+
+// ---------------------------------------------------------------------------
+// Pattern plan
+// ---------------------------------------------------------------------------
+
+fx_status fx_check_pattern(const fx_pattern *p)
+{
+    if (!p) return fx_fail(FX_EINVAL, "pattern is NULL");
+    if (p->n > FX_MAXN) return fx_fail(FX_ELIMIT, "pattern has %d vertices; at most %d", p->n, FX_MAXN);
+    if (p->n < 1 || p->m < 0) return fx_fail(FX_EPATTERN, "pattern needs n >= 1 and m >= 0");
+    if (!p->vlabel || (p->m > 0 && !p->edges)) return fx_fail(FX_EINVAL, "pattern arrays are NULL");
+    const int n = p->n;
+    bool adj[FX_MAXN][FX_MAXN] = {};
+    for (int k = 0; k < p->m; k++) {
+        int a = p->edges[2 * k], b = p->edges[2 * k + 1];
+        if (a < 0 || b < 0 || a >= n || b >= n) return fx_fail(FX_EPATTERN, "edge %d has an endpoint out of range", k);
+        if (a == b) return fx_fail(FX_EPATTERN, "edge %d is a loop", k);
+        if (adj[a][b]) return fx_fail(FX_EPATTERN, "edge %d repeats an edge", k);
+        if (p->elabel && p->elabel[k] < 0) return fx_fail(FX_EPATTERN, "edge %d has a negative label", k);
+        adj[a][b] = adj[b][a] = true;
+    }
+    for (int i = 0; i < n; i++)
+        if (p->vlabel[i] < 0) return fx_fail(FX_EPATTERN, "vertex %d has a negative label", i);
+    bool seen[FX_MAXN] = {};
+    int stack[FX_MAXN], top = 0, cnt = 1;
+    seen[0] = true;
+    stack[top++] = 0;
+    while (top) {
+        int x = stack[--top];
+        for (int y = 0; y < n; y++)
+            if (adj[x][y] && !seen[y]) {
+                seen[y] = true;
+                cnt++;
+                stack[top++] = y;
+            }
+    }
+    if (cnt != n) return fx_fail(FX_EPATTERN, "pattern is not connected");
+    return FX_OK;
+}
+
+fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
+{
+    FX_TRY(fx_check_pattern(p));
+    const int n = p->n;
+    FxPlan &P = hp.plan;
+    memset(&P, 0, sizeof(P));
+    P.n = n;
+    int32_t el[FX_MAXN][FX_MAXN];
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++) el[a][b] = -1;
+    for (int i = 0; i < n; i++) {
+        auto it = G->vl_map.find(p->vlabel[i]);
+        if (it == G->vl_map.end()) hp.empty = true;
+        else P.vl[i] = it->second;
+    }
+    for (int k = 0; k < p->m; k++) {
+        int a = p->edges[2 * k], b = p->edges[2 * k + 1];
+        int32_t lab = p->elabel ? p->elabel[k] : 0;
+        auto it = G->el_map.find(lab);
+        if (it == G->el_map.end()) {
+            hp.empty = true;
+            el[a][b] = el[b][a] = 0;
+        } else {
+            el[a][b] = el[b][a] = (int32_t)it->second;
+        }
+    }
+    for (int i = 0; i < n; i++) {
+        P.nback[i] = 0;
+        for (int b = 0; b < i; b++)
+            if (el[b][i] >= 0) {
+                P.back[i][P.nback[i]] = b;
+                P.bel[i][P.nback[i]] = (uint32_t)el[b][i];
+                P.nback[i]++;
+            }
+        // neighbour-label filter over later neighbours: worthwhile for the
+        // root and for vertices that need two or more later neighbours
+        std::vector<std::pair<uint64_t, int>> need;
+        int later = 0;
+        for (int j = i + 1; j < n; j++)
+            if (el[i][j] >= 0) {
+                later++;
+                uint64_t key = ((uint64_t)P.vl[j] << 48) | ((uint64_t)el[i][j] << 32);
+                bool found = false;
+                for (auto &q : need)
+                    if (q.first == key) {
+                        q.second++;
+                        found = true;
+                    }
+                if (!found) need.push_back({key, 1});
+            }
+        P.nnlf[i] = 0;
+        if (i < n - 1 && (i == 0 || later >= 2)) {
+            std::sort(need.begin(), need.end(), [](auto &x, auto &y) { return x.second > y.second; });
+            for (auto &q : need) {
+                if (P.nnlf[i] == FX_NLF) break;
+                P.nlf_key[i][P.nnlf[i]] = q.first;
+                P.nlf_need[i][P.nnlf[i]] = q.second;
+                P.nnlf[i]++;
+            }
+        }
+    }
+    // upper bound on any independent set: disjoint images (bound of Section 3.1.2)
+    int64_t ub = G->nv / n;
+    if (!hp.empty) {
+        std::unordered_map<uint32_t, int> cnt;
+        for (int i = 0; i < n; i++) cnt[P.vl[i]]++;
+        for (auto &kv : cnt) {
+            int64_t sz = G->bptr[kv.first + 1] - G->bptr[kv.first];
+            ub = std::min<int64_t>(ub, sz / kv.second);
+        }
+    } else {
+        ub = 0;
+    }
+    hp.upper_bound = ub;
+    return FX_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr uint32_t kLastSpanMin = 1024;
+constexpr uint32_t kLastSpanInit = 4096;
+constexpr uint64_t kCountSpan = 1ull << 22;  // last-vertex candidates per counting step
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+enum { PH_SUPPORT = 0, PH_COUNT = 1, PH_LIST = 2 };
+
+struct Query {
+    FxRequest *req = nullptr;
+    HostPlan hp;
+    int n = 0;
+    int64_t tau = 0, tau_eff = 1;
+    int phase = PH_SUPPORT;
+    int slot = -1;
+    void *region = nullptr;
+    size_t region_bytes = 0;
+    int64_t cap = 0;
+    FxLevelDev lev[FX_MAXN + 1]{};
+    uint32_t *U = nullptr;
+    FxPlan *plan = nullptr;
+    int32_t *sel_rows = nullptr;
+    int64_t *sel_rank = nullptr;
+    uint64_t T[FX_MAXN + 1]{}, cur[FX_MAXN + 1]{};
+    int64_t nparts[FX_MAXN + 1]{};
+    int64_t rank_base = 0;
+    uint32_t last_span = kLastSpanInit;
+    int32_t steps = 0;
+    int64_t listed = 0;
+    // the segment of the current step
+    int seg_l = -1, seg_kind = 0;
+    uint64_t seg_t0 = 0;
+    uint32_t seg_span = 0;
+};
+
+bool wants_selection(const FxRequest &r) { return r.kind == FX_Q_FULL && r.selected && r.selected_cap > 0; }
+
+size_t region_size(const Query &q, int64_t nv)
+{
+    const int n = q.n;
+    const size_t C = (size_t)q.cap;
+    size_t b = 0;
+    b += align256(8) + align256(4) + align256(1) + align256(16);  // level 0
+    for (int l = 1; l < n; l++)
+        b += align256(C * l * 4) + align256(C * 8) + align256(C * 4) + align256(C) + align256((C + 1) * 8);
+    b += align256(C * n * 4);  // complete embeddings
+    b += align256(((size_t)nv + 31) / 32 * 4) + align256(sizeof(FxPlan));
+    if (wants_selection(*q.req)) {
+        const size_t k = (size_t)nv / n + 1;
+        b += align256(k * n * 4) + align256(k * 8);
+    }
+    return b;
+}
+
+void carve(Query &q, int64_t nv)
+{
+    char *p = (char *)q.region;
+    auto take = [&](size_t bytes) {
+        void *r = p;
+        p += align256(bytes);
+        return r;
+    };
+    const int n = q.n;
+    const size_t C = (size_t)q.cap;
+    q.lev[0].lo = (int64_t *)take(8);
+    q.lev[0].len = (int32_t *)take(4);
+    q.lev[0].anc = (int8_t *)take(1);
+    q.lev[0].off = (int64_t *)take(16);
+    q.lev[0].rows = nullptr;
+    for (int l = 1; l < n; l++) {
+        q.lev[l].rows = (int32_t *)take(C * l * 4);
+        q.lev[l].lo = (int64_t *)take(C * 8);
+        q.lev[l].len = (int32_t *)take(C * 4);
+        q.lev[l].anc = (int8_t *)take(C);
+        q.lev[l].off = (int64_t *)take((C + 1) * 8);
+    }
+    q.lev[n] = FxLevelDev{};
+    q.lev[n].rows = (int32_t *)take(C * n * 4);
+    q.U = (uint32_t *)take(((size_t)nv + 31) / 32 * 4);
+    q.plan = (FxPlan *)take(sizeof(FxPlan));
+    q.sel_rows = nullptr;
+    q.sel_rank = nullptr;
+    if (wants_selection(*q.req)) {
+        const size_t k = (size_t)nv / n + 1;
+        q.sel_rows = (int32_t *)take(k * n * 4);
+        q.sel_rank = (int64_t *)take(k * 8);
+    }
+}
+
+int deepest_open_level(const Query &q)
+{
+    for (int l = q.n - 1; l >= 0; l--)
+        if (q.cur[l] < q.T[l]) return l;
+    return -1;
+}
+
+void restart_stack(Query &q, const fx_graph *G)
+{
+    const uint32_t vl0 = q.hp.plan.vl[0];
+    for (int l = 0; l <= q.n; l++) q.T[l] = q.cur[l] = 0, q.nparts[l] = 0;
+    q.T[0] = (uint64_t)(G->bptr[vl0 + 1] - G->bptr[vl0]);
+    q.nparts[0] = 1;
+}
+
+fx_result base_result(const Query &q)
+{
+    fx_result r{};
+    r.tau = q.tau;
+    return r;
+}
+
+}  // namespace
+
+fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active)
+{
+    fx_ctx *c = G->ctx;
+    hipStream_t s = c->stream;
+    const int64_t nv = G->nv;
+    if (max_active < 1) max_active = 1;
+
+    std::vector<Query> qs;
+    qs.reserve(reqs.size());
+    std::deque<int> pending;
+    for (auto &r : reqs) {
+        Query q;
+        q.req = &r;
+        r.status = fx_build_plan(G, r.pattern, q.hp);
+        if (r.status != FX_OK) continue;
+        q.n = r.pattern->n;
+        if (r.kind != FX_Q_LIST) {
+            r.status = fx_tau_checked(r.sigma, r.lambda, q.n, &q.tau);
+            if (r.status != FX_OK) continue;
+            q.tau_eff = std::max<int64_t>(q.tau, 1);
+        }
+        if (q.hp.empty) {  // some label never occurs: M is empty
+            if (r.kind == FX_Q_LIST) {
+                *r.list_count = 0;
+            } else {
+                fx_result res = base_result(q);
+                res.support = r.kind == FX_Q_VERDICT ? -1 : 0;
+                res.embedding_count = r.kind == FX_Q_VERDICT ? -1 : 0;
+                *r.out = res;
+            }
+            continue;
+        }
+        if (r.kind == FX_Q_VERDICT && q.hp.upper_bound < q.tau_eff) {  // support can never reach tau
+            fx_result res = base_result(q);
+            res.support = -1;
+            res.embedding_count = -1;
+            *r.out = res;
+            continue;
+        }
+        q.phase = r.kind == FX_Q_LIST ? PH_LIST : PH_SUPPORT;
+        q.cap = c->slice_rows;
+        q.last_span = (uint32_t)std::min<int64_t>(kLastSpanInit, q.cap);
+        qs.push_back(q);
+        pending.push_back((int)qs.size() - 1);
+    }
+    if (qs.empty()) return FX_OK;
+    max_active = std::min<int32_t>(max_active, (int32_t)qs.size());
+
+    // step buffers
+    const uint64_t max_blocks = (c->step_candidates + FX_BS - 1) / FX_BS + (uint64_t)max_active;
+    FX_TRY(c->flag.ensure(max_blocks * FX_BS));
+    FX_TRY(c->bcnt.ensure(max_blocks * 4));
+    FX_TRY(c->boff.ensure((max_blocks + 1) * 8));
+    FX_TRY(c->segs_d.ensure((size_t)max_active * sizeof(FxSeg)));
+    FX_TRY(c->segs_h.ensure((size_t)max_active * sizeof(FxSeg)));
+    FX_TRY(c->blk0_d.ensure(((size_t)max_active + 1) * 4));
+    FX_TRY(c->blk0_h.ensure(((size_t)max_active + 1) * 4));
+    FX_TRY(c->inits_d.ensure((size_t)max_active * sizeof(FxInit)));
+    FX_TRY(c->inits_h.ensure((size_t)max_active * sizeof(FxInit)));
+    FX_TRY(c->sums_d.ensure((size_t)max_active * sizeof(FxSummary)));
+    FX_TRY(c->sums_h.ensure((size_t)max_active * sizeof(FxSummary)));
+    FxSummary *sums_d = c->sums_d.as<FxSummary>();
+    FxSummary *sums_h = c->sums_h.as<FxSummary>();
+
+    std::vector<int> active;
+    std::vector<int> free_slots;
+    for (int k = max_active - 1; k >= 0; k--) free_slots.push_back(k);
+    size_t rot = 0;
+    const uint64_t u_words = ((uint64_t)nv + 31) / 32;
+
+    auto finish = [&](Query &q) -> fx_status {
+        FxRequest &r = *q.req;
+        const FxSummary &S = sums_h[q.slot];
+        if (q.phase == PH_LIST) {
+            *r.list_count = (int64_t)S.count;
+        } else {
+            fx_result res = base_result(q);
+            res.steps = q.steps;
+            res.rounds = (int32_t)S.rounds;
+            res.alg_bytes = S.alg_probe + S.alg_scatter;
+            if (r.kind == FX_Q_VERDICT) {
+                res.frequent = (int64_t)S.support >= q.tau_eff;
+                res.support = res.frequent ? q.tau : -1;
+                res.embedding_count = -1;
+            } else {
+                res.support = (int64_t)S.support;
+                res.frequent = res.support >= q.tau_eff;
+                const bool sat = (int64_t)S.count >= c->count_cap;
+                res.count_saturated = sat;
+                res.embedding_count = sat ? c->count_cap : (int64_t)S.count;
+                if (!sat) {
+                    res.digest[0] = S.digest0;
+                    res.digest[1] = S.digest1;
+                }
+                if (wants_selection(r) && S.support > 0) {
+                    const int64_t k = (int64_t)S.support;
+                    std::vector<int32_t> rows((size_t)k * q.n);
+                    std::vector<int64_t> rank(k);
+                    FX_HIP(hipMemcpy(rows.data(), q.sel_rows, rows.size() * 4, hipMemcpyDeviceToHost));
+                    FX_HIP(hipMemcpy(rank.data(), q.sel_rank, rank.size() * 8, hipMemcpyDeviceToHost));
+                    std::vector<int64_t> idx(k);
+                    std::iota(idx.begin(), idx.end(), 0);
+                    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return rank[a] < rank[b]; });
+                    const int64_t w = std::min<int64_t>(k, r.selected_cap);
+                    for (int64_t i = 0; i < w; i++)
+                        memcpy(r.selected + i * q.n, rows.data() + idx[i] * q.n, (size_t)q.n * 4);
+                }
+            }
+            *r.out = res;
+        }
+        c->stats.probe_alg_bytes += S.alg_probe;
+        c->stats.scatter_alg_bytes += S.alg_scatter;
+        c->stats.queries++;
+        c->pool.give(q.region, q.region_bytes);
+        q.region = nullptr;
+        free_slots.push_back(q.slot);
+        q.slot = -1;
+        return FX_OK;
+    };
+
+    while (!pending.empty() || !active.empty()) {
+        // ---- admission: as many pending queries as slots and memory allow
+        int ninit = 0;
+        FxInit *inits = c->inits_h.as<FxInit>();
+        while (!pending.empty() && !free_slots.empty()) {
+            Query &q = qs[pending.front()];
+            const size_t bytes = region_size(q, nv);
+            if (!c->pool.fits(bytes) && !active.empty()) break;  // wait until running queries free memory
+            fx_status st = c->pool.take(bytes, &q.region);
+            if (st != FX_OK) {
+                if (!active.empty()) break;
+                return st;
+            }
+            q.region_bytes = bytes;
+            carve(q, nv);
+            q.slot = free_slots.back();
+            free_slots.pop_back();
+            FX_HIP(hipMemcpyAsync(q.plan, &q.hp.plan, sizeof(FxPlan), hipMemcpyHostToDevice, s));
+            FxInit &I = inits[ninit++];
+            I.lev0 = q.lev[0];
+            I.plan = q.plan;
+            I.U = q.U;
+            I.sum = sums_d + q.slot;
+            I.u_words = u_words;
+            I.clear_u = 1;
+            I.clear_sum = 1;
+            restart_stack(q, G);
+            active.push_back(pending.front());
+            pending.pop_front();
+        }
+        if (ninit) {
+            FX_HIP(hipMemcpyAsync(c->inits_d.p, inits, (size_t)ninit * sizeof(FxInit), hipMemcpyHostToDevice, s));
+            FX_HIP(fx_launch_init(s, G->dev, c->inits_d.as<FxInit>(), ninit));
+        }
+
+        // ---- one segment per active query, within the step's candidate budget
+        FxSeg *segs = c->segs_h.as<FxSeg>();
+        uint32_t *blk0 = c->blk0_h.as<uint32_t>();
+        int nsegs = 0;
+        uint64_t budget = c->step_candidates;
+        uint32_t nblocks = 0;
+        int any_inner = 0, any_greedy = 0, any_write = 0;
+        std::vector<int> segq;
+        const size_t A = active.size();
+        for (size_t k = 0; k < A && budget > 0; k++) {
+            Query &q = qs[active[(rot + k) % A]];
+            const int l = deepest_open_level(q);
+            if (l < 0) continue;
+            const bool last = (l == q.n - 1);
+            int kind, flags = 0;
+            uint64_t cap;
+            if (q.phase == PH_SUPPORT) {
+                flags = FX_PROBE_UFILTER;
+                kind = last ? FX_SEG_GREEDY : FX_SEG_INNER;
+                cap = last ? std::min<uint64_t>(q.last_span, (uint64_t)q.cap) : (uint64_t)q.cap;
+            } else if (q.phase == PH_COUNT) {
+                flags = last ? FX_PROBE_COUNT : 0;
+                kind = last ? FX_SEG_COUNT : FX_SEG_INNER;
+                cap = last ? kCountSpan : (uint64_t)q.cap;
+            } else {
+                flags = last ? FX_PROBE_COUNT : 0;
+                kind = last ? FX_SEG_LIST : FX_SEG_INNER;
+                cap = (uint64_t)q.cap;
+            }
+            const uint64_t span = std::min<uint64_t>(std::min<uint64_t>(q.T[l] - q.cur[l], cap), budget);
+            if (span == 0) continue;
+            // every passing candidate of a writing segment takes one row of level l+1
+            if (kind != FX_SEG_COUNT && span > (uint64_t)q.cap)
+                return fx_fail(FX_EDEVICE, "internal: slice of %llu candidates exceeds the level capacity %lld",
+                               (unsigned long long)span, (long long)q.cap);
+            FxSeg &S = segs[nsegs];
+            S.in = q.lev[l];
+            S.out = q.lev[l + 1];
+            S.plan = q.plan;
+            S.U = q.U;
+            S.sum = sums_d + q.slot;
+            S.sel_rows = q.sel_rows;
+            S.sel_rank = q.sel_rank;
+            S.nparts = q.nparts[l];
+            S.t0 = q.cur[l];
+            S.rank_base = q.rank_base;
+            S.span = (uint32_t)span;
+            S.blk0 = nblocks;
+            S.n = q.n;
+            S.l = l;
+            S.flags = flags;
+            S.kind = kind;
+            blk0[nsegs] = nblocks;
+            nblocks += (uint32_t)((span + FX_BS - 1) / FX_BS);
+            budget -= span;
+            q.seg_l = l;
+            q.seg_kind = kind;
+            q.seg_t0 = q.cur[l];
+            q.seg_span = (uint32_t)span;
+            any_inner |= kind == FX_SEG_INNER;
+            any_greedy |= kind == FX_SEG_GREEDY;
+            any_write |= kind != FX_SEG_COUNT;
+            segq.push_back(active[(rot + k) % A]);
+            nsegs++;
+        }
+        rot++;
+        if (nsegs == 0) return fx_fail(FX_EDEVICE, "engine stalled with %zu active queries", active.size());
+        blk0[nsegs] = nblocks;
+        FX_HIP(hipMemcpyAsync(c->segs_d.p, segs, (size_t)nsegs * sizeof(FxSeg), hipMemcpyHostToDevice, s));
+        FX_HIP(hipMemcpyAsync(c->blk0_d.p, blk0, ((size_t)nsegs + 1) * 4, hipMemcpyHostToDevice, s));
+        hipEvent_t *ev = c->timing ? c->evk : nullptr;
+        FX_HIP(fx_launch_step(s, G->dev, c->segs_d.as<FxSeg>(), c->blk0_d.as<uint32_t>(), nsegs, nblocks,
+                              c->flag.as<uint8_t>(), c->bcnt.as<uint32_t>(), c->boff.as<uint64_t>(),
+                              ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, ev ? ev[2] : nullptr,
+                              ev ? ev[3] : nullptr, ev ? ev[4] : nullptr, ev ? ev[5] : nullptr, any_inner,
+                              any_greedy, any_write));
+        int hi = 0;
+        for (int qi : active) hi = std::max(hi, qs[qi].slot + 1);
+        FX_HIP(hipMemcpyAsync(sums_h, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, s));
+        FX_HIP(hipStreamSynchronize(s));
+        c->stats.steps++;
+        c->stats.syncs++;
+        c->stats.probe_launches++;
+        c->stats.scatter_launches++;
+        if (any_greedy) c->stats.greedy_launches++;
+        if (c->timing) {
+            float ms = 0;
+            FX_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            c->stats.probe_ms += ms;
+            FX_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+            c->stats.scatter_ms += ms;
+            FX_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
+            c->stats.greedy_ms += ms;
+        }
+
+        // ---- advance every query that took part
+        for (int qi : segq) {
+            Query &q = qs[qi];
+            const FxSummary &S = sums_h[q.slot];
+            if (S.error) return fx_fail(FX_EDEVICE, "device consistency check failed (greedy round limit)");
+            const int l = q.seg_l;
+            q.cur[l] = q.seg_t0 + q.seg_span;
+            q.steps++;
+            const uint64_t N = S.total_out;
+            if (q.seg_kind == FX_SEG_INNER) {
+                q.nparts[l + 1] = (int64_t)N;
+                q.T[l + 1] = S.t_next;
+                q.cur[l + 1] = 0;
+            } else if (q.seg_kind == FX_SEG_GREEDY) {
+                q.rank_base += (int64_t)N;
+                // keep the greedy's slices near a few thousand embeddings
+                if (N * 8 < q.seg_span) q.last_span = (uint32_t)std::min<int64_t>(2 * (int64_t)q.last_span, q.cap);
+                else if (N > 8192) q.last_span = std::max<uint32_t>(q.last_span / 2, kLastSpanMin);
+                q.last_span = (uint32_t)std::min<int64_t>(q.last_span, q.cap);
+            } else if (q.seg_kind == FX_SEG_LIST) {
+                FxRequest &r = *q.req;
+                const int64_t take = std::min<int64_t>((int64_t)N, std::max<int64_t>(0, r.list_cap - q.listed));
+                if (take > 0)
+                    FX_HIP(hipMemcpy(r.list_rows + q.listed * q.n, q.lev[q.n].rows, (size_t)take * q.n * 4,
+                                     hipMemcpyDeviceToHost));
+                q.listed += (int64_t)N;
+            }
+        }
+        // ---- retire finished queries, move FULL queries to their counting phase
+        for (size_t k = 0; k < active.size();) {
+            Query &q = qs[active[k]];
+            const FxSummary &S = sums_h[q.slot];
+            bool done = false;
+            if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_VERDICT && (int64_t)S.support >= q.tau_eff) done = true;
+            if (q.phase == PH_COUNT && (int64_t)S.count >= c->count_cap) done = true;
+            if (!done && deepest_open_level(q) < 0) {
+                if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_FULL) {
+                    q.phase = PH_COUNT;  // level 0 is unchanged; restart the cursors
+                    restart_stack(q, G);
+                } else {
+                    done = true;
+                }
+            }
+            if (done) {
+                FX_TRY(finish(q));
+                active[k] = active.back();
+                active.pop_back();
+            } else {
+                k++;
+            }
+        }
+    }
+    return FX_OK;
+}

@@ -1,0 +1,131 @@
+// Host-side objects of the library (context, resident graph, query engine).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <cstdint>
+#include <deque>
+#include <functional>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/flexis.h"
+#include "fx_internal.h"
+
+fx_status fx_fail(fx_status code, const char *fmt, ...);
+
+#define FX_HIP(call)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) return fx_fail(FX_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define FX_TRY(call)                \
+    do {                            \
+        fx_status s_ = (call);      \
+        if (s_ != FX_OK) return s_; \
+    } while (0)
+
+// Device allocation that remembers its size.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release();
+    fx_status ensure(size_t want);
+    template <class T>
+    T *as() const { return (T *)p; }
+};
+
+// Pinned host allocation.
+struct HostBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf() { release(); }
+    void release();
+    fx_status ensure(size_t want);
+    template <class T>
+    T *as() const { return (T *)p; }
+};
+
+// Device regions reused by size class (per-query stacks), with a byte budget:
+// admission control of the engine is "does this query's region fit".
+struct RegionPool {
+    std::map<size_t, std::vector<void *>> free_;
+    size_t in_use = 0, held = 0, budget = 0;
+    ~RegionPool();
+    bool fits(size_t bytes) const { return in_use + bytes <= budget; }
+    fx_status take(size_t bytes, void **out);
+    void give(void *p, size_t bytes);
+    void trim();
+};
+
+struct fx_ctx {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    int64_t slice_rows = 1 << 17;         // level capacity of one query's stack
+    int64_t count_cap = (int64_t)1 << 62;
+    uint64_t step_candidates = 1ull << 25; // flattened candidates per step, all queries together
+    int32_t max_active = 4096;            // queries in flight in a batch
+    std::atomic<int> graphs{0};
+    bool timing = false;
+    fx_stats stats{};
+
+    RegionPool pool;
+    DevBuf flag, bcnt, boff, segs_d, blk0_d, inits_d, sums_d;
+    HostBuf segs_h, blk0_h, inits_h, sums_h;
+    hipEvent_t evk[6] = {};
+};
+
+struct fx_graph {
+    fx_ctx *ctx = nullptr;
+    int64_t nv = 0, nadj = 0;
+    std::vector<int32_t> vl_values, el_values;  // dense id -> caller's label
+    std::unordered_map<int32_t, uint32_t> vl_map, el_map;
+    std::vector<int64_t> bptr;                  // host copy of the label buckets' offsets
+    DevBuf rowp, adj, bucket, bptr_d;
+    FxGraphDev dev{};
+};
+
+// Matching plan of one pattern.
+struct HostPlan {
+    FxPlan plan{};
+    bool empty = false;       // a label of the pattern does not occur in the graph
+    int64_t upper_bound = 0;  // support <= min(nv / n, min_l |V_l| / cnt_l)
+};
+
+fx_status fx_check_pattern(const fx_pattern *p);
+fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp);
+fx_status fx_tau_checked(int64_t sigma, double lambda, int32_t n, int64_t *tau_out);
+
+// One request to the engine.
+enum FxQueryKind { FX_Q_FULL = 0, FX_Q_VERDICT = 1, FX_Q_LIST = 2 };
+
+struct FxRequest {
+    const fx_pattern *pattern = nullptr;
+    int64_t sigma = 1;
+    double lambda = 1.0;
+    int32_t kind = FX_Q_FULL;
+    fx_result *out = nullptr;            // result (FULL / VERDICT)
+    int32_t *selected = nullptr;         // optional selected embeddings (FULL)
+    int64_t selected_cap = 0;
+    int32_t *list_rows = nullptr;        // listing output (LIST)
+    int64_t list_cap = 0;
+    int64_t *list_count = nullptr;
+    fx_status status = FX_OK;            // per-request validation status
+};
+
+// Runs every request to completion, many at a time (at most max_active in
+// flight).  Requests that fail validation get their status set and are
+// skipped; any device error aborts the whole run.
+fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active);

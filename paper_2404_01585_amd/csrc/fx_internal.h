@@ -15,6 +15,10 @@
 // A pattern plan fixes, for every pattern vertex i (in submitted order), its
 // dense label, its earlier neighbours b < i with the edge label of (b, i),
 // and a neighbour-label filter for its later neighbours.
+//
+// Every expansion step runs over a list of segments: one per active query,
+// each a contiguous range of the flattened candidate space of one level of
+// that query's slice stack.  Workgroups never straddle two segments.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,9 +26,9 @@
 
 #define FX_MAXN 16
 #define FX_NLF 4
-#define FX_BS 256           // threads per workgroup for the streaming kernels
-#define FX_SCAN_ITEMS 4     // items per thread in the span scan
-#define FX_RMAX 4096        // greedy rounds tracked per clear of the round counters
+#define FX_BS 256            // threads per workgroup for the streaming kernels
+#define FX_GREEDY_H 4096     // LDS hash slots of the per-query greedy
+#define FX_GREEDY_VN 2048    // embedding-vertices per greedy chunk (<= H / 2)
 
 struct FxPlan {
     int32_t n;
@@ -48,20 +52,22 @@ struct FxGraphDev {
     int32_t nel;   // dense edge labels
 };
 
-// Device-side counters of one query.  Written by kernels, read by the host
-// once per step.
+// Device-side counters of one query, read by the host once per step.
 struct FxSummary {
-    unsigned long long total_out;   // rows materialised by the last expansion
+    unsigned long long total_out;   // rows materialised by the query's last segment
     unsigned long long t_next;      // candidate-space size of the new level
     unsigned long long count;       // embeddings counted so far
     unsigned long long digest0;     // sum of hashes (mod 2^64)
     unsigned long long digest1;     // xor of hashes
     unsigned long long support;     // embeddings selected so far
-    unsigned long long hsize;       // hash-table size of the current greedy
-    unsigned long long pad;
+    unsigned long long rounds;      // greedy rounds run so far
+    unsigned long long alg_probe;   // algorithmic bytes of the probe launches
+    unsigned long long alg_scatter; // algorithmic bytes of the scatter launches
+    unsigned long long error;       // nonzero: a device-side consistency check failed
+    unsigned long long pad[6];
 };
 
-// One level of the slice stack: partial embeddings with l matched vertices
+// One level of a slice stack: partial embeddings with l matched vertices
 // and, for each, the candidate run of pattern vertex l.
 struct FxLevelDev {
     int32_t *rows;   // [cap * l]
@@ -71,31 +77,52 @@ struct FxLevelDev {
     int64_t *off;    // exclusive prefix of len, [cap + 1]
 };
 
-// Probe modes
+// What a segment does with the candidates that pass.
 enum : int32_t {
-    FX_PROBE_UFILTER = 1,   // materialise only candidates disjoint from the used set U
+    FX_SEG_INNER = 0,    // write them to level l+1 (with their next candidate run)
+    FX_SEG_GREEDY = 1,   // last vertex: write the complete embeddings, then run the greedy
+    FX_SEG_COUNT = 2,    // last vertex: count and hash them only
+    FX_SEG_LIST = 3,     // last vertex: write the complete embeddings (listing)
+};
+
+// Probe flags
+enum : int32_t {
+    FX_PROBE_UFILTER = 1,   // pass only candidates whose partial and vertex avoid the used set U
     FX_PROBE_COUNT = 2,     // count (and hash) every valid candidate of the last vertex
 };
 
-struct FxWork;  // host-side workspace (fx_api.hip)
+struct FxSeg {
+    FxLevelDev in;          // level l of the query
+    FxLevelDev out;         // level l+1 of the query
+    const FxPlan *plan;
+    uint32_t *U;            // used-vertex bitmap of the query
+    FxSummary *sum;
+    int32_t *sel_rows;      // selected embeddings (append)
+    int64_t *sel_rank;      // their ranks
+    int64_t nparts;         // rows in level l
+    uint64_t t0;            // first flattened candidate of the slice
+    int64_t rank_base;      // rank of the first complete embedding this step writes
+    uint32_t span;          // candidates in the slice
+    uint32_t blk0;          // first workgroup of this segment in the launch
+    int32_t n, l;
+    int32_t flags;          // FX_PROBE_*
+    int32_t kind;           // FX_SEG_*
+};
 
-// Launchers (fx_kernels.hip).  All return hipError_t of the launch.
-hipError_t fx_launch_probe(hipStream_t s, const FxGraphDev &g, const FxPlan *plan, int32_t n, int32_t l,
-                           const FxLevelDev &in, int64_t nparts, uint64_t t0, uint64_t t1, int32_t flags,
-                           const uint32_t *U, uint8_t *flag, uint32_t *bcnt, FxSummary *sum);
-hipError_t fx_launch_scan_blocks(hipStream_t s, const uint32_t *bcnt, uint32_t nblocks, uint64_t *boff,
-                                 FxSummary *sum);
-hipError_t fx_launch_scatter(hipStream_t s, const FxGraphDev &g, const FxPlan *plan, int32_t n, int32_t l,
-                             const FxLevelDev &in, int64_t nparts, uint64_t t0, uint64_t t1,
-                             const uint8_t *flag, const uint64_t *boff, const FxLevelDev &out);
-hipError_t fx_launch_scan_len(hipStream_t s, const FxLevelDev &lev, uint64_t max_rows, int64_t *bsum,
-                              FxSummary *sum);
-hipError_t fx_launch_greedy_init(hipStream_t s, const int32_t *rows, int32_t n, uint64_t nrows,
-                                 int32_t *hkey, unsigned long long *hval, uint64_t hsize, int32_t *slot,
-                                 uint8_t *state, uint32_t *rem, FxSummary *sum);
-hipError_t fx_launch_greedy_round(hipStream_t s, const int32_t *rows, int32_t n, uint64_t nrows,
-                                  unsigned long long *hval, const int32_t *slot, uint8_t *state, uint32_t *rem,
-                                  uint32_t round, uint32_t *U, int32_t *sel_rows, int64_t *sel_rank,
-                                  int64_t rank_base, FxSummary *sum);
-hipError_t fx_launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t v);
-hipError_t fx_launch_level0(hipStream_t s, const FxGraphDev &g, const FxPlan *plan, FxLevelDev lev0);
+// Per-query initialisation (admission or a new phase).
+struct FxInit {
+    FxLevelDev lev0;
+    const FxPlan *plan;
+    uint32_t *U;            // cleared when clear_u != 0
+    FxSummary *sum;         // cleared when clear_sum != 0
+    uint64_t u_words;
+    int32_t clear_u, clear_sum;
+};
+
+// Launchers (fx_kernels.hip).  All return the hipError_t of the launches.
+hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *inits, int32_t ninit);
+hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
+                          int32_t nsegs, uint32_t nblocks, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
+                          hipEvent_t probe_begin, hipEvent_t probe_end, hipEvent_t scatter_begin,
+                          hipEvent_t scatter_end, hipEvent_t greedy_begin, hipEvent_t greedy_end,
+                          int32_t any_inner, int32_t any_greedy, int32_t any_write);

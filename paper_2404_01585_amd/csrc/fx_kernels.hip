@@ -35,11 +35,14 @@ __device__ __forceinline__ uint64_t run_key(uint32_t vl, uint32_t el)
     return ((uint64_t)vl << 48) | ((uint64_t)el << 32);
 }
 
-// First index in adj[lo, hi) whose value is >= key.
-__device__ __forceinline__ int64_t lower_bound64(const uint64_t *__restrict__ a, int64_t lo, int64_t hi, uint64_t key)
+// First index in adj[lo, hi) whose value is >= key.  `bytes` grows by the 8
+// bytes of every entry the search reads (its algorithmic traffic).
+__device__ __forceinline__ int64_t lower_bound64(const uint64_t *__restrict__ a, int64_t lo, int64_t hi, uint64_t key,
+                                                 uint32_t &bytes)
 {
     while (lo < hi) {
         int64_t mid = lo + ((hi - lo) >> 1);
+        bytes += 8;
         if (a[mid] < key) lo = mid + 1;
         else hi = mid;
     }
@@ -47,19 +50,22 @@ __device__ __forceinline__ int64_t lower_bound64(const uint64_t *__restrict__ a,
 }
 
 // Does the row of u contain the packed entry (label, elabel, id)?
-__device__ __forceinline__ bool has_entry(const FxGraphDev &g, int32_t u, uint64_t entry)
+__device__ __forceinline__ bool has_entry(const FxGraphDev &g, int32_t u, uint64_t entry, uint32_t &bytes)
 {
     int64_t lo = g.rowp[u], hi = g.rowp[u + 1];
-    int64_t k = lower_bound64(g.adj, lo, hi, entry);
+    bytes += 16;
+    int64_t k = lower_bound64(g.adj, lo, hi, entry, bytes);
     return k < hi && g.adj[k] == entry;
 }
 
 // The run of neighbours of u with the given (label, elabel) key.
-__device__ __forceinline__ void run_of(const FxGraphDev &g, int32_t u, uint64_t key, int64_t &lo, int32_t &len)
+__device__ __forceinline__ void run_of(const FxGraphDev &g, int32_t u, uint64_t key, int64_t &lo, int32_t &len,
+                                       uint32_t &bytes)
 {
     int64_t a = g.rowp[u], b = g.rowp[u + 1];
-    int64_t s = lower_bound64(g.adj, a, b, key);
-    int64_t e = lower_bound64(g.adj, s, b, key + (1ULL << 32));
+    bytes += 16;
+    int64_t s = lower_bound64(g.adj, a, b, key, bytes);
+    int64_t e = lower_bound64(g.adj, s, b, key + (1ULL << 32), bytes);
     lo = s;
     len = (int32_t)(e - s);
 }
@@ -85,6 +91,7 @@ struct Cand {
     int32_t v[FX_MAXN];  // the partial row (first l entries)
     int32_t c;           // candidate for pattern vertex l
     int32_t anc;         // pattern vertex whose run produced c (-1: bucket)
+    bool first;          // first candidate of its partial
 };
 
 // Loads the partial and the candidate behind flattened index t.
@@ -98,6 +105,7 @@ __device__ __forceinline__ void load_cand(const FxGraphDev &g, const FxLevelDev 
     for (int k = 0; k < FX_MAXN; k++)
         x.v[k] = (k < l) ? row[k] : -1;
     x.anc = in.anc[p];
+    x.first = (j == 0);
     int64_t base = in.lo[p];
     x.c = x.anc >= 0 ? (int32_t)(uint32_t)(g.adj[base + j] & 0xffffffffULL) : g.bucket[base + j];
 }
@@ -113,7 +121,7 @@ __device__ __forceinline__ int32_t pick(const int32_t (&v)[FX_MAXN], int32_t b)
 
 // Candidate test of Section 2.1.4 for pattern vertex i = l.
 __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__restrict__ plan, int32_t n, int32_t l,
-                                         const Cand &x)
+                                         const Cand &x, uint32_t &bytes)
 {
 #pragma unroll
     for (int k = 0; k < FX_MAXN; k++)
@@ -125,14 +133,14 @@ __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__re
         int32_t b = plan->back[i][kk];
         if (b == x.anc) continue;  // the run it came from already matches
         uint64_t entry = run_key(vl, plan->bel[i][kk]) | (uint32_t)x.c;
-        if (!has_entry(g, pick(x.v, b), entry)) return false;
+        if (!has_entry(g, pick(x.v, b), entry, bytes)) return false;
     }
     if (i < n - 1) {  // neighbour-label filter for the later neighbours of i
         const int32_t nf = plan->nnlf[i];
         for (int k = 0; k < nf; k++) {
             int64_t lo;
             int32_t len;
-            run_of(g, x.c, plan->nlf_key[i][k], lo, len);
+            run_of(g, x.c, plan->nlf_key[i][k], lo, len, bytes);
             if (len < plan->nlf_need[i][k]) return false;
         }
     }
@@ -158,47 +166,74 @@ __device__ __forceinline__ uint64_t lanemask_lt()
 // Expansion: probe (test + per-block counts) and scatter (ordered write).
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxPlan *__restrict__ plan, int32_t n, int32_t l,
-                                                 FxLevelDev in, int64_t nparts, uint64_t t0, uint32_t span,
-                                                 int32_t flags, const uint32_t *__restrict__ U, uint8_t *flag,
-                                                 uint32_t *bcnt, FxSummary *sum)
+// Segment of workgroup b: the last s with blk0s[s] <= b.  The result is
+// uniform across the workgroup.
+__device__ __forceinline__ int32_t seg_of(const uint32_t *__restrict__ blk0s, int32_t nsegs, uint32_t b)
+{
+    int32_t lo = 0, hi = nsegs;
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (blk0s[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+__device__ __forceinline__ void tuple_hash(const Cand &x, int32_t l, uint64_t &h1, uint64_t &h2)
+{
+    uint64_t a = kSeed1, b = kSeed2;
+#pragma unroll
+    for (int k = 0; k < FX_MAXN; k++) {
+        if (k < l) {
+            a = mix64(a ^ (uint64_t)(uint32_t)x.v[k]);
+            b = mix64(b ^ (uint64_t)(uint32_t)x.v[k]);
+        }
+    }
+    h1 = mix64(a ^ (uint64_t)(uint32_t)x.c);
+    h2 = mix64(b ^ (uint64_t)(uint32_t)x.c);
+}
+
+// Test every candidate of every segment; one thread per candidate.  Writes
+// a pass flag per candidate and the number of passes per workgroup.
+__global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__restrict__ segs,
+                                                 const uint32_t *__restrict__ blk0s, int32_t nsegs, uint8_t *flag,
+                                                 uint32_t *bcnt)
 {
     __shared__ uint32_t wcnt[FX_BS / 64];
-    const uint32_t tl = blockIdx.x * FX_BS + threadIdx.x;
+    const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
+    const FxSeg &S = segs[si];
+    const int32_t l = S.l, n = S.n, flags = S.flags;
+    const uint32_t tl = (blockIdx.x - S.blk0) * FX_BS + threadIdx.x;
     bool mat = false, cnt = false;
     uint64_t h1 = 0, h2 = 0;
-    if (tl < span) {
+    uint32_t bytes = 0;
+    if (tl < S.span) {
         Cand x;
-        load_cand(g, in, l, nparts, t0 + tl, x);
+        load_cand(g, S.in, l, S.nparts, S.t0 + tl, x);
         const bool ufilter = (flags & FX_PROBE_UFILTER) != 0;
         const bool count = (flags & FX_PROBE_COUNT) != 0;
+        // candidate entry + flag; the partial row and its run descriptor once
+        bytes = (x.anc >= 0 ? 8u : 4u) + 1u;
+        if (x.first || tl == 0) bytes += 4u * (uint32_t)l + 21u;
         bool ok = true;
-        bool used = false;
-        if (ufilter) used = touches_used(U, x, l);
-        if (ufilter && !count && used) ok = false;  // nothing to count: prune early
-        if (ok) ok = feasible(g, plan, n, l, x);
+        if (ufilter) {
+            ok = !touches_used(S.U, x, l);
+            bytes += 4u * (uint32_t)(l + 1);
+        }
+        if (ok) ok = feasible(g, S.plan, n, l, x, bytes);
         if (ok) {
-            mat = !(ufilter && used);
             if (count) {
                 cnt = true;
-                uint64_t a = kSeed1, b = kSeed2;
-#pragma unroll
-                for (int k = 0; k < FX_MAXN; k++) {
-                    if (k < l) {
-                        a = mix64(a ^ (uint64_t)(uint32_t)x.v[k]);
-                        b = mix64(b ^ (uint64_t)(uint32_t)x.v[k]);
-                    }
-                }
-                h1 = mix64(a ^ (uint64_t)(uint32_t)x.c);
-                h2 = mix64(b ^ (uint64_t)(uint32_t)x.c);
+                tuple_hash(x, l, h1, h2);
             }
+            mat = S.kind != FX_SEG_COUNT;
         }
-        flag[tl] = mat ? 1 : 0;
+        flag[(uint64_t)blockIdx.x * FX_BS + threadIdx.x] = mat ? 1 : 0;
     }
     const uint64_t bal = __ballot(mat);
     const uint32_t wave = threadIdx.x >> 6;
     if (__lane_id() == 0) wcnt[wave] = (uint32_t)__popcll(bal);
-    if (flags & FX_PROBE_COUNT) {
+    if (flags & FX_PROBE_COUNT) {  // uniform across the workgroup
         unsigned long long c = cnt ? 1ULL : 0ULL;
         unsigned long long s1 = h1, s2 = h2;
 #pragma unroll
@@ -208,23 +243,25 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxPlan *__r
             s2 ^= __shfl_xor(s2, o);
         }
         if (__lane_id() == 0 && c) {
-            atomicAdd(&sum->count, c);
-            atomicAdd(&sum->digest0, s1);
-            atomicXor(&sum->digest1, s2);
+            atomicAdd(&S.sum->count, c);
+            atomicAdd(&S.sum->digest0, s1);
+            atomicXor(&S.sum->digest1, s2);
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
+    {
+        unsigned long long b = bytes;
 #pragma unroll
-        for (int w = 0; w < FX_BS / 64; w++) s += wcnt[w];
-        bcnt[blockIdx.x] = s;
+        for (int o = 32; o >= 1; o >>= 1) b += __shfl_xor(b, o);
+        if (__lane_id() == 0 && b) atomicAdd(&S.sum->alg_probe, b);
     }
+    __syncthreads();
+    if (threadIdx.x == 0) bcnt[blockIdx.x] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
 }
 
-// Exclusive scan of the per-block counts (one workgroup of 1024 threads).
+// Exclusive scan of the per-workgroup pass counts over the whole launch (one
+// workgroup of 1024 threads); boff[nblocks] receives the total.
 __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t *__restrict__ bcnt, uint32_t nblocks,
-                                                      uint64_t *boff, FxSummary *sum)
+                                                      uint64_t *boff)
 {
     __shared__ uint64_t part[1024];
     const uint32_t per = (nblocks + 1023) / 1024;
@@ -246,106 +283,101 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t *__restrict
             boff[beg + k] = run;
             run += bcnt[beg + k];
         }
-    if (threadIdx.x == 1023) sum->total_out = part[1023];
+    if (threadIdx.x == 1023) boff[nblocks] = part[1023];
 }
 
-__global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxPlan *__restrict__ plan, int32_t n, int32_t l,
-                                                   FxLevelDev in, int64_t nparts, uint64_t t0, uint32_t span,
-                                                   const uint8_t *__restrict__ flag, const uint64_t *__restrict__ boff,
-                                                   FxLevelDev out)
+// Ordered write of the passing candidates of each segment into its level l+1
+// (position = passes before it in the segment), with the candidate run of
+// the next pattern vertex for inner levels.
+__global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
+                                                   const uint32_t *__restrict__ blk0s, int32_t nsegs,
+                                                   const uint8_t *__restrict__ flag,
+                                                   const uint64_t *__restrict__ boff)
 {
     __shared__ uint32_t wcnt[FX_BS / 64];
-    const uint32_t tl = blockIdx.x * FX_BS + threadIdx.x;
-    const bool f = tl < span && flag[tl];
+    const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
+    const FxSeg &S = segs[si];
+    const int32_t l = S.l, n = S.n;
+    const uint32_t tl = (blockIdx.x - S.blk0) * FX_BS + threadIdx.x;
+    const uint64_t seg_base = boff[S.blk0];
+    if (blockIdx.x == S.blk0 && threadIdx.x == 0) {
+        const uint32_t nblk = (S.span + FX_BS - 1) / FX_BS;
+        S.sum->total_out = boff[S.blk0 + nblk] - seg_base;
+    }
+    if (S.kind == FX_SEG_COUNT) return;  // nothing is written for a counting segment
+    const bool f = tl < S.span && flag[(uint64_t)blockIdx.x * FX_BS + threadIdx.x];
     const uint64_t bal = __ballot(f);
     const uint32_t wave = threadIdx.x >> 6;
     if (__lane_id() == 0) wcnt[wave] = (uint32_t)__popcll(bal);
     __syncthreads();
-    if (!f) return;
-    uint64_t pos = boff[blockIdx.x] + (uint64_t)__popcll(bal & lanemask_lt());
-    for (uint32_t w = 0; w < wave; w++) pos += wcnt[w];
-
-    Cand x;
-    load_cand(g, in, l, nparts, t0 + tl, x);
     const int32_t w1 = l + 1;
-    int32_t *dst = out.rows + pos * w1;
+    // flag read per candidate; row and run descriptor written per survivor
+    uint32_t bytes = (tl < S.span ? 1u : 0u) + (f ? 4u * (uint32_t)w1 : 0u) + ((f && w1 < n) ? 13u : 0u);
+    if (f) {
+        uint64_t pos = boff[blockIdx.x] - seg_base + (uint64_t)__popcll(bal & lanemask_lt());
+        for (uint32_t w = 0; w < wave; w++) pos += wcnt[w];
+        Cand x;
+        load_cand(g, S.in, l, S.nparts, S.t0 + tl, x);
+        int32_t *dst = S.out.rows + pos * w1;
 #pragma unroll
-    for (int k = 0; k < FX_MAXN; k++)
-        if (k < l) dst[k] = x.v[k];
-    dst[l] = x.c;
-    if (w1 < n) {
-        // candidate run of the next pattern vertex i2 = l + 1: the shortest
-        // run among its earlier neighbours, or its label bucket.
-        const int32_t i2 = w1;
-        const uint32_t vl = plan->vl[i2];
-        const int32_t nb = plan->nback[i2];
-        int64_t best_lo = 0;
-        int32_t best_len = 0;
-        int32_t best_anc = -1;
-        if (nb == 0) {
-            best_lo = g.bptr[vl];
-            best_len = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
-        } else {
-            best_len = 0x7fffffff;
-            for (int kk = 0; kk < nb; kk++) {
-                int32_t b = plan->back[i2][kk];
-                int32_t u = (b == l) ? x.c : pick(x.v, b);
-                int64_t lo;
-                int32_t len;
-                run_of(g, u, run_key(vl, plan->bel[i2][kk]), lo, len);
-                if (len < best_len) {
-                    best_len = len;
-                    best_lo = lo;
-                    best_anc = b;
+        for (int k = 0; k < FX_MAXN; k++)
+            if (k < l) dst[k] = x.v[k];
+        dst[l] = x.c;
+        if (w1 < n) {
+            // candidate run of the next pattern vertex i2 = l + 1: the shortest
+            // run among its earlier neighbours, or its label bucket.
+            const FxPlan *plan = S.plan;
+            const int32_t i2 = w1;
+            const uint32_t vl = plan->vl[i2];
+            const int32_t nb = plan->nback[i2];
+            int64_t best_lo = 0;
+            int32_t best_len = 0;
+            int32_t best_anc = -1;
+            if (nb == 0) {
+                best_lo = g.bptr[vl];
+                best_len = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
+            } else {
+                best_len = 0x7fffffff;
+                for (int kk = 0; kk < nb; kk++) {
+                    int32_t b = plan->back[i2][kk];
+                    int32_t u = (b == l) ? x.c : pick(x.v, b);
+                    int64_t lo;
+                    int32_t len;
+                    run_of(g, u, run_key(vl, plan->bel[i2][kk]), lo, len, bytes);
+                    if (len < best_len) {
+                        best_len = len;
+                        best_lo = lo;
+                        best_anc = b;
+                    }
                 }
             }
+            S.out.lo[pos] = best_lo;
+            S.out.len[pos] = best_len;
+            S.out.anc[pos] = (int8_t)best_anc;
         }
-        out.lo[pos] = best_lo;
-        out.len[pos] = best_len;
-        out.anc[pos] = (int8_t)best_anc;
     }
-}
-
-// ---------------------------------------------------------------------------
-// Exclusive scan of the run lengths of a new level (three passes).
-// ---------------------------------------------------------------------------
-
-constexpr uint32_t kScanTile = FX_BS * FX_SCAN_ITEMS;
-
-__global__ __launch_bounds__(FX_BS) void k_scan_len_a(FxLevelDev lev, const FxSummary *sum, int64_t *bsum)
-{
-    __shared__ int64_t red[FX_BS];
-    const uint64_t N = sum->total_out;
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-    if (base >= N) return;
-    int64_t s = 0;
+    unsigned long long b = bytes;
 #pragma unroll
-    for (int k = 0; k < FX_SCAN_ITEMS; k++) {
-        uint64_t i = base + threadIdx.x * FX_SCAN_ITEMS + k;
-        if (i < N) s += lev.len[i];
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (uint32_t o = FX_BS / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+    for (int o = 32; o >= 1; o >>= 1) b += __shfl_xor(b, o);
+    if (__lane_id() == 0 && b) atomicAdd(&S.sum->alg_scatter, b);
 }
 
-__global__ __launch_bounds__(1024) void k_scan_len_b(int64_t *bsum, FxSummary *sum)
+// Exclusive scan of the run lengths of each inner segment's new level (one
+// workgroup per segment); writes off[0..N] and the level's candidate total.
+__global__ __launch_bounds__(FX_BS) void k_scan_len(const FxSeg *__restrict__ segs)
 {
-    __shared__ int64_t part[1024];
-    const uint64_t N = sum->total_out;
-    const uint64_t nb = (N + kScanTile - 1) / kScanTile;
-    const uint64_t per = (nb + 1023) / 1024;
-    const uint64_t beg = threadIdx.x * per;
+    __shared__ int64_t part[FX_BS];
+    const FxSeg &S = segs[blockIdx.x];
+    if (S.kind != FX_SEG_INNER) return;
+    const uint64_t N = S.sum->total_out;
+    const uint64_t per = (N + FX_BS - 1) / FX_BS;
+    const uint64_t beg = (uint64_t)threadIdx.x * per;
     int64_t s = 0;
     for (uint64_t k = 0; k < per; k++)
-        if (beg + k < nb) s += bsum[beg + k];
+        if (beg + k < N) s += S.out.len[beg + k];
     part[threadIdx.x] = s;
     __syncthreads();
-    for (uint32_t o = 1; o < 1024; o <<= 1) {
+    for (uint32_t o = 1; o < FX_BS; o <<= 1) {
         int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
         __syncthreads();
         part[threadIdx.x] += v;
@@ -353,144 +385,151 @@ __global__ __launch_bounds__(1024) void k_scan_len_b(int64_t *bsum, FxSummary *s
     }
     int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
     for (uint64_t k = 0; k < per; k++)
-        if (beg + k < nb) {
-            int64_t v = bsum[beg + k];
-            bsum[beg + k] = run;
-            run += v;
+        if (beg + k < N) {
+            S.out.off[beg + k] = run;
+            run += S.out.len[beg + k];
         }
-    if (threadIdx.x == 1023) sum->t_next = (unsigned long long)part[1023];
-}
-
-__global__ __launch_bounds__(FX_BS) void k_scan_len_c(FxLevelDev lev, const FxSummary *sum, const int64_t *bsum)
-{
-    __shared__ int64_t part[FX_BS];
-    const uint64_t N = sum->total_out;
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-    if (blockIdx.x == 0 && threadIdx.x == 0) lev.off[N] = (int64_t)sum->t_next;
-    if (base >= N) return;
-    int64_t v[FX_SCAN_ITEMS];
-    int64_t s = 0;
-#pragma unroll
-    for (int k = 0; k < FX_SCAN_ITEMS; k++) {
-        uint64_t i = base + threadIdx.x * FX_SCAN_ITEMS + k;
-        v[k] = i < N ? lev.len[i] : 0;
-        s += v[k];
-    }
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (uint32_t o = 1; o < FX_BS; o <<= 1) {
-        int64_t t = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += t;
-        __syncthreads();
-    }
-    int64_t run = bsum[blockIdx.x] + (threadIdx.x ? part[threadIdx.x - 1] : 0);
-#pragma unroll
-    for (int k = 0; k < FX_SCAN_ITEMS; k++) {
-        uint64_t i = base + threadIdx.x * FX_SCAN_ITEMS + k;
-        if (i < N) lev.off[i] = run;
-        run += v[k];
+    if (threadIdx.x == FX_BS - 1) {
+        S.out.off[N] = part[FX_BS - 1];
+        S.sum->t_next = (unsigned long long)part[FX_BS - 1];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Greedy maximal independent set over one slice of complete embeddings.
-// Slot value: min over contending embeddings of ((~round) << 32 | rank); a
-// later round's keys are smaller than every stale key, so slots need no reset
-// between rounds.  Value 0 marks a slot taken by a selected embedding.
+// Greedy maximal independent set of one query's complete embeddings of this
+// step, in rank order, one workgroup per query (Section 2.4.3; the used set U
+// is the bitmap of Section 3.2.2).  Embeddings are taken in chunks of at most
+// FX_GREEDY_VN vertices.  Per chunk: drop embeddings that meet U, hash their
+// data vertices into LDS slots (the overlap structure), then run rounds: every
+// undecided embedding writes ((~round) << 32 | rank) into its slots with an
+// atomic min, and is selected when it holds the minimum of all its slots --
+// i.e. it ranks below every undecided embedding it overlaps.  Slot value 0
+// marks a slot taken by a selected embedding; an undecided embedding that
+// meets one is dropped.  The lowest-ranked undecided embedding always wins
+// its round, so a chunk ends after at most (embeddings) rounds, and the
+// selection equals the sequential greedy's.
 // ---------------------------------------------------------------------------
 
-// Fibonacci hashing: the top log2(size) bits of v * 2^64/phi.
-__device__ __forceinline__ uint64_t hash_slot(int32_t v, uint64_t mask)
+__device__ __forceinline__ uint32_t lds_hash(int32_t v)
 {
-    const uint32_t bits = (uint32_t)__popcll(mask);
-    return ((uint64_t)(uint32_t)v * 0x9e3779b97f4a7c15ULL) >> (64 - bits);
+    return (uint32_t)(((uint64_t)(uint32_t)v * 0x9e3779b97f4a7c15ULL) >> 52);  // top 12 bits: FX_GREEDY_H = 4096
 }
 
-__global__ __launch_bounds__(FX_BS) void k_greedy_init(const int32_t *__restrict__ rows, int32_t n, uint64_t nrows,
-                                                       int32_t *hkey, uint64_t hmask, int32_t *slot,
-                                                       uint8_t *state)
+__device__ __forceinline__ bool used_coherent(const uint32_t *U, int32_t v)
 {
-    const uint64_t e = (uint64_t)blockIdx.x * FX_BS + threadIdx.x;
-    if (e >= nrows) return;
-    for (int j = 0; j < n; j++) {
-        const int32_t v = rows[e * n + j];
-        uint64_t h = hash_slot(v, hmask);
-        while (true) {  // linear probing; the table has >= 2x as many slots as keys
-            int32_t prev = atomicCAS(&hkey[h], -1, v);
-            if (prev == -1 || prev == v) break;
-            h = (h + 1) & hmask;
+    // bypass the per-CU cache: this workgroup sets bits of U while it runs
+    const uint32_t w = __hip_atomic_load(&U[(uint32_t)v >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (w >> ((uint32_t)v & 31u)) & 1u;
+}
+
+__global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs)
+{
+    static_assert(FX_GREEDY_H == 4096, "lds_hash takes the top 12 bits");
+    __shared__ int32_t hkey[FX_GREEDY_H];
+    __shared__ unsigned long long hval[FX_GREEDY_H];
+    __shared__ uint16_t slot[FX_GREEDY_VN];
+    __shared__ uint8_t state[FX_GREEDY_VN];  // 0 undecided, 1 selected, 2 out
+    __shared__ uint32_t undecided;
+    const FxSeg &S = segs[blockIdx.x];
+    if (S.kind != FX_SEG_GREEDY) return;
+    const int32_t n = S.n;
+    const uint64_t N = S.sum->total_out;
+    const int32_t *rows = S.out.rows;
+    const uint32_t B = FX_GREEDY_VN / (uint32_t)n;  // embeddings per chunk
+    uint32_t rounds_total = 0;
+    for (uint64_t c0 = 0; c0 < N; c0 += B) {
+        const uint32_t nb = (uint32_t)((N - c0) < B ? (N - c0) : B);
+        for (uint32_t k = threadIdx.x; k < FX_GREEDY_H; k += FX_BS) {
+            hkey[k] = -1;
+            hval[k] = ~0ULL;
         }
-        slot[e * n + j] = (int32_t)h;
-    }
-    state[e] = 0;
-}
-
-__global__ __launch_bounds__(FX_BS) void k_greedy_min(int32_t n, uint64_t nrows, unsigned long long *hval,
-                                                      const int32_t *__restrict__ slot, uint8_t *state,
-                                                      const uint32_t *rem, uint32_t round)
-{
-    if ((round % FX_RMAX) != 0 && rem[(round - 1) % FX_RMAX] == 0) return;
-    const uint64_t e = (uint64_t)blockIdx.x * FX_BS + threadIdx.x;
-    if (e >= nrows || state[e] != 0) return;
-    for (int j = 0; j < n; j++)
-        if (hval[slot[e * n + j]] == 0ULL) {  // meets a selected embedding
-            state[e] = 2;
-            return;
-        }
-    const unsigned long long key = ((unsigned long long)(0xffffffffu - round) << 32) | (uint32_t)e;
-    for (int j = 0; j < n; j++) atomicMin(&hval[slot[e * n + j]], key);
-}
-
-__global__ __launch_bounds__(FX_BS) void k_greedy_sel(const int32_t *__restrict__ rows, int32_t n, uint64_t nrows,
-                                                      unsigned long long *hval, const int32_t *__restrict__ slot,
-                                                      uint8_t *state, uint32_t *rem, uint32_t round, uint32_t *U,
-                                                      int32_t *sel_rows, int64_t *sel_rank, int64_t rank_base,
-                                                      FxSummary *sum)
-{
-    if ((round % FX_RMAX) != 0 && rem[(round - 1) % FX_RMAX] == 0) return;
-    const uint64_t e = (uint64_t)blockIdx.x * FX_BS + threadIdx.x;
-    bool still = false;
-    if (e < nrows && state[e] == 0) {
-        const unsigned long long key = ((unsigned long long)(0xffffffffu - round) << 32) | (uint32_t)e;
-        bool mine = true;
-        for (int j = 0; j < n; j++) mine = mine && (hval[slot[e * n + j]] == key);
-        if (mine) {
-            state[e] = 1;
-            for (int j = 0; j < n; j++) {
-                hval[slot[e * n + j]] = 0ULL;
-                const uint32_t v = (uint32_t)rows[e * n + j];
-                atomicOr(&U[v >> 5], 1u << (v & 31u));
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < nb; e += FX_BS) {
+            const int32_t *row = rows + (c0 + e) * n;
+            bool out = false;
+            for (int j = 0; j < n; j++) out = out || used_coherent(S.U, row[j]);
+            state[e] = out ? 2 : 0;
+            if (!out) {
+                for (int j = 0; j < n; j++) {
+                    const int32_t v = row[j];
+                    uint32_t h = lds_hash(v);
+                    while (true) {  // linear probing; at most H/2 keys per chunk
+                        const int32_t prev = atomicCAS(&hkey[h], -1, v);
+                        if (prev == -1 || prev == v) break;
+                        h = (h + 1) & (FX_GREEDY_H - 1);
+                    }
+                    slot[e * n + j] = (uint16_t)h;
+                }
             }
-            const unsigned long long pos = atomicAdd(&sum->support, 1ULL);
-            for (int j = 0; j < n; j++) sel_rows[pos * n + j] = rows[e * n + j];
-            sel_rank[pos] = rank_base + (int64_t)e;
-        } else {
-            still = true;
         }
+        __syncthreads();
+        for (uint32_t r = 0; r <= nb; r++) {  // a chunk needs at most nb rounds
+            if (threadIdx.x == 0) undecided = 0;
+            for (uint32_t e = threadIdx.x; e < nb; e += FX_BS) {
+                if (state[e] != 0) continue;
+                bool out = false;
+                for (int j = 0; j < n; j++) out = out || (hval[slot[e * n + j]] == 0ULL);
+                if (out) {
+                    state[e] = 2;
+                    continue;
+                }
+                const unsigned long long key = ((unsigned long long)(0xffffffffu - r) << 32) | e;
+                for (int j = 0; j < n; j++) atomicMin(&hval[slot[e * n + j]], key);
+            }
+            __syncthreads();
+            uint32_t mine_undecided = 0;
+            for (uint32_t e = threadIdx.x; e < nb; e += FX_BS) {
+                if (state[e] != 0) continue;
+                const unsigned long long key = ((unsigned long long)(0xffffffffu - r) << 32) | e;
+                bool mine = true;
+                for (int j = 0; j < n; j++) mine = mine && (hval[slot[e * n + j]] == key);
+                if (mine) {
+                    state[e] = 1;
+                    const int32_t *row = rows + (c0 + e) * n;
+                    for (int j = 0; j < n; j++) {
+                        hval[slot[e * n + j]] = 0ULL;
+                        const uint32_t v = (uint32_t)row[j];
+                        atomicOr(&S.U[v >> 5], 1u << (v & 31u));
+                    }
+                    const unsigned long long pos = atomicAdd(&S.sum->support, 1ULL);
+                    if (S.sel_rows) {  // selections are kept only when the caller asked for them
+                        for (int j = 0; j < n; j++) S.sel_rows[pos * n + j] = row[j];
+                        S.sel_rank[pos] = S.rank_base + (int64_t)(c0 + e);
+                    }
+                } else {
+                    mine_undecided++;
+                }
+            }
+            if (mine_undecided) atomicAdd(&undecided, mine_undecided);
+            __syncthreads();
+            const uint32_t und = undecided;
+            rounds_total++;
+            __syncthreads();  // everyone has read `undecided` before it is reset
+            if (und == 0) break;
+            if (r == nb && threadIdx.x == 0) atomicAdd(&S.sum->error, 1ULL);  // cannot happen
+        }
+        __syncthreads();
     }
-    const uint64_t bal = __ballot(still);
-    if (__lane_id() == 0 && bal) atomicAdd(&rem[round % FX_RMAX], (uint32_t)__popcll(bal));
+    if (threadIdx.x == 0) atomicAdd(&S.sum->rounds, (unsigned long long)rounds_total);
 }
 
-__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+// Admission / phase start of queries: level 0 is the single empty partial
+// whose candidate run is the label bucket of pattern vertex 0.
+__global__ void k_init(FxGraphDev g, const FxInit *__restrict__ inits)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+    const FxInit &I = inits[blockIdx.x];
+    if (I.clear_u)
+        for (uint64_t k = threadIdx.x; k < I.u_words; k += blockDim.x) I.U[k] = 0u;
+    if (I.clear_sum && threadIdx.x < sizeof(FxSummary) / 8) ((unsigned long long *)I.sum)[threadIdx.x] = 0ULL;
+    if (threadIdx.x == 0) {
+        const uint32_t vl = I.plan->vl[0];
+        I.lev0.lo[0] = g.bptr[vl];
+        I.lev0.len[0] = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
+        I.lev0.anc[0] = -1;
+        I.lev0.off[0] = 0;
+        I.lev0.off[1] = g.bptr[vl + 1] - g.bptr[vl];
+    }
 }
-
-__global__ void k_level0(FxGraphDev g, const FxPlan *__restrict__ plan, FxLevelDev lev)
-{
-    if (threadIdx.x != 0) return;
-    const uint32_t vl = plan->vl[0];
-    lev.lo[0] = g.bptr[vl];
-    lev.len[0] = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
-    lev.anc[0] = -1;
-    lev.off[0] = 0;
-    lev.off[1] = g.bptr[vl + 1] - g.bptr[vl];
-}
-
-inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs - 1) / bs); }
 
 }  // namespace
 
@@ -498,78 +537,31 @@ inline uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs 
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t fx_launch_probe(hipStream_t s, const FxGraphDev &g, const FxPlan *plan, int32_t n, int32_t l,
-                           const FxLevelDev &in, int64_t nparts, uint64_t t0, uint64_t t1, int32_t flags,
-                           const uint32_t *U, uint8_t *flag, uint32_t *bcnt, FxSummary *sum)
+hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *inits, int32_t ninit)
 {
-    const uint32_t span = (uint32_t)(t1 - t0);
-    hipLaunchKernelGGL(k_probe, dim3(blocks_for(span, FX_BS)), dim3(FX_BS), 0, s, g, plan, n, l, in, nparts, t0, span,
-                       flags, U, flag, bcnt, sum);
+    if (ninit <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init, dim3(ninit), dim3(256), 0, s, g, inits);
     return hipGetLastError();
 }
 
-hipError_t fx_launch_scan_blocks(hipStream_t s, const uint32_t *bcnt, uint32_t nblocks, uint64_t *boff,
-                                 FxSummary *sum)
+hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
+                          int32_t nsegs, uint32_t nblocks, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
+                          hipEvent_t probe_begin, hipEvent_t probe_end, hipEvent_t scatter_begin,
+                          hipEvent_t scatter_end, hipEvent_t greedy_begin, hipEvent_t greedy_end,
+                          int32_t any_inner, int32_t any_greedy, int32_t any_write)
 {
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bcnt, nblocks, boff, sum);
-    return hipGetLastError();
-}
-
-hipError_t fx_launch_scatter(hipStream_t s, const FxGraphDev &g, const FxPlan *plan, int32_t n, int32_t l,
-                             const FxLevelDev &in, int64_t nparts, uint64_t t0, uint64_t t1,
-                             const uint8_t *flag, const uint64_t *boff, const FxLevelDev &out)
-{
-    const uint32_t span = (uint32_t)(t1 - t0);
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(span, FX_BS)), dim3(FX_BS), 0, s, g, plan, n, l, in, nparts, t0,
-                       span, flag, boff, out);
-    return hipGetLastError();
-}
-
-hipError_t fx_launch_scan_len(hipStream_t s, const FxLevelDev &lev, uint64_t max_rows, int64_t *bsum,
-                              FxSummary *sum)
-{
-    const uint32_t nb = blocks_for(max_rows > 0 ? max_rows : 1, kScanTile);
-    hipLaunchKernelGGL(k_scan_len_a, dim3(nb), dim3(FX_BS), 0, s, lev, sum, bsum);
-    hipLaunchKernelGGL(k_scan_len_b, dim3(1), dim3(1024), 0, s, bsum, sum);
-    hipLaunchKernelGGL(k_scan_len_c, dim3(nb), dim3(FX_BS), 0, s, lev, sum, bsum);
-    return hipGetLastError();
-}
-
-hipError_t fx_launch_greedy_init(hipStream_t s, const int32_t *rows, int32_t n, uint64_t nrows, int32_t *hkey,
-                                 unsigned long long *hval, uint64_t hsize, int32_t *slot, uint8_t *state,
-                                 uint32_t *rem, FxSummary *sum)
-{
-    (void)sum;
-    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, (uint32_t *)hkey, hsize, 0xffffffffu);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, (uint32_t *)hval, 2 * hsize, 0xffffffffu);
-    hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(256), 0, s, rem, (uint64_t)FX_RMAX, 0u);
-    hipLaunchKernelGGL(k_greedy_init, dim3(blocks_for(nrows, FX_BS)), dim3(FX_BS), 0, s, rows, n, nrows, hkey,
-                       hsize - 1, slot, state);
-    return hipGetLastError();
-}
-
-hipError_t fx_launch_greedy_round(hipStream_t s, const int32_t *rows, int32_t n, uint64_t nrows,
-                                  unsigned long long *hval, const int32_t *slot, uint8_t *state, uint32_t *rem,
-                                  uint32_t round, uint32_t *U, int32_t *sel_rows, int64_t *sel_rank,
-                                  int64_t rank_base, FxSummary *sum)
-{
-    const uint32_t nb = blocks_for(nrows, FX_BS);
-    if (round != 0 && (round % FX_RMAX) == 0)
-        hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(256), 0, s, rem, (uint64_t)FX_RMAX, 0u);
-    hipLaunchKernelGGL(k_greedy_min, dim3(nb), dim3(FX_BS), 0, s, n, nrows, hval, slot, state, rem, round);
-    hipLaunchKernelGGL(k_greedy_sel, dim3(nb), dim3(FX_BS), 0, s, rows, n, nrows, hval, slot, state, rem, round, U,
-                       sel_rows, sel_rank, rank_base, sum);
-    return hipGetLastError();
-}
-
-hipError_t fx_launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t v)
-{
-    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, p, n, v);
-    return hipGetLastError();
-}
-
-hipError_t fx_launch_level0(hipStream_t s, const FxGraphDev &g, const FxPlan *plan, FxLevelDev lev0)
-{
-    hipLaunchKernelGGL(k_level0, dim3(1), dim3(64), 0, s, g, plan, lev0);
+    hipError_t e;
+    if (probe_begin && (e = hipEventRecord(probe_begin, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_probe, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, bcnt);
+    if (probe_end && (e = hipEventRecord(probe_end, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bcnt, nblocks, boff);
+    if (scatter_begin && (e = hipEventRecord(scatter_begin, s)) != hipSuccess) return e;
+    (void)any_write;
+    hipLaunchKernelGGL(k_scatter, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, boff);
+    if (scatter_end && (e = hipEventRecord(scatter_end, s)) != hipSuccess) return e;
+    if (any_inner) hipLaunchKernelGGL(k_scan_len, dim3(nsegs), dim3(FX_BS), 0, s, segs);
+    if (greedy_begin && (e = hipEventRecord(greedy_begin, s)) != hipSuccess) return e;
+    if (any_greedy) hipLaunchKernelGGL(k_greedy, dim3(nsegs), dim3(FX_BS), 0, s, segs);
+    if (greedy_end && (e = hipEventRecord(greedy_end, s)) != hipSuccess) return e;
     return hipGetLastError();
 }

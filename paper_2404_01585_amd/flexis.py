@@ -36,7 +36,9 @@ _STATUS_NAMES = {0: "FX_OK", -1: "FX_EINVAL", -2: "FX_EGRAPH", -3: "FX_EPATTERN"
 
 # Every symbol include/flexis.h declares.
 EXPORTS = ["fx_ctx_create", "fx_ctx_destroy", "fx_graph_load", "fx_graph_destroy", "fx_tau", "fx_support",
-           "fx_enumerate", "fx_support_batch", "fx_last_error", "fx_version"]
+           "fx_enumerate", "fx_support_batch", "fx_ctx_stats", "fx_last_error", "fx_version"]
+
+CTX_KERNEL_TIMING = 1
 
 
 class FxError(RuntimeError):
@@ -47,7 +49,7 @@ class FxError(RuntimeError):
 
 class CtxOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("hip_stream", ctypes.c_void_p), ("slice_rows", ctypes.c_int64),
-                ("count_cap", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+                ("count_cap", ctypes.c_int64), ("mem_budget_bytes", ctypes.c_int64), ("flags", ctypes.c_uint32)]
 
 
 class GraphDesc(ctypes.Structure):
@@ -59,6 +61,17 @@ class GraphDesc(ctypes.Structure):
 class PatternC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("vlabel", ctypes.c_void_p),
                 ("edges", ctypes.c_void_p), ("elabel", ctypes.c_void_p)]
+
+
+class StatsC(ctypes.Structure):
+    _fields_ = [("probe_launches", ctypes.c_uint64), ("probe_ms", ctypes.c_double),
+                ("probe_alg_bytes", ctypes.c_uint64), ("scatter_launches", ctypes.c_uint64),
+                ("scatter_ms", ctypes.c_double), ("scatter_alg_bytes", ctypes.c_uint64),
+                ("greedy_launches", ctypes.c_uint64), ("greedy_ms", ctypes.c_double), ("steps", ctypes.c_uint64),
+                ("syncs", ctypes.c_uint64), ("queries", ctypes.c_uint64)]
+
+    def to_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ResultC(ctypes.Structure):
@@ -108,6 +121,8 @@ def load_library():
     lib.fx_support.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P, P, ctypes.c_int64]
     lib.fx_enumerate.restype = ctypes.c_int32
     lib.fx_enumerate.argtypes = [P, P, P, ctypes.c_int64, P]
+    lib.fx_ctx_stats.restype = ctypes.c_int32
+    lib.fx_ctx_stats.argtypes = [P, P, ctypes.c_int32]
     lib.fx_support_batch.restype = ctypes.c_int32
     lib.fx_support_batch.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_int32, P]
     _lib = lib
@@ -154,13 +169,16 @@ def _current_stream() -> int:
 class Context:
     """fx_ctx: a device, a stream, and the workspace sizing."""
 
-    def __init__(self, device: int = 0, stream: Optional[int] = None, slice_rows: int = 0, count_cap: int = 0):
+    def __init__(self, device: int = 0, stream: Optional[int] = None, slice_rows: int = 0, count_cap: int = 0,
+                 kernel_timing: bool = False, mem_budget_bytes: int = 0):
         lib = load_library()
         if stream is None:
             import torch
             torch.cuda.set_device(device)
             stream = _current_stream()
-        self._opts = CtxOpts(device, stream or None, slice_rows, count_cap, 0)
+        self.stream = stream
+        self._opts = CtxOpts(device, stream or None, slice_rows, count_cap, mem_budget_bytes,
+                             CTX_KERNEL_TIMING if kernel_timing else 0)
         self._h = ctypes.c_void_p()
         _check(lib.fx_ctx_create(ctypes.byref(self._opts), ctypes.byref(self._h)))
         self.count_cap = count_cap if count_cap > 0 else (1 << 62)
@@ -168,6 +186,11 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def stats(self, reset: bool = False) -> Dict:
+        st = StatsC()
+        _check(load_library().fx_ctx_stats(self._h, ctypes.byref(st), 1 if reset else 0))
+        return st.to_dict()
 
     def load_graph(self, g, on_device: bool = False) -> "DeviceGraph":
         return DeviceGraph(self, g, on_device=on_device)

@@ -218,3 +218,56 @@ def test_device_resident_input(ctx, er1k):
     _say("device resident graph")
     with ctx.load_graph(gd, on_device=True) as dg:
         full_match(dg, g, p, 20, 1.0)
+
+
+def _mining_candidates(g, sigma, lam, levels):
+    from paper_2404_01585_amd import mining
+
+    def ev(ps, s, l):
+        return [O.query(g, p, s, l, mode=O.VERDICT) for p in ps]
+
+    r = mining.mine(g, sigma, lam, levels, ev, tau_fn=O.tau)
+    return [p for lvl in r["levels"] for p in lvl]
+
+
+def test_er1k_mining_batch(ctx, er1k):
+    """Every candidate of the first three mining levels on the 1K-vertex graph,
+    as one batch, FULL and VERDICT, against the oracle pattern by pattern."""
+    g = er1k
+    cands = _mining_candidates(g, 20, 1.0, 3)
+    assert len(cands) > 500
+    with ctx.load_graph(g) as dg:
+        for lam in (1.0, 0.3):
+            _say("er1k batch FULL lambda", lam, "patterns", len(cands))
+            got = dg.support_batch(cands, [20] * len(cands), [lam] * len(cands), fx.MODE_FULL)
+            for p, r in zip(cands, got):
+                want = O.query(g, p, 20, lam, O.FULL)
+                for k in ("tau", "support", "frequent", "embedding_count", "count_saturated", "digest"):
+                    assert r[k] == want[k], (p, k, r[k], want[k])
+            _say("er1k batch VERDICT lambda", lam)
+            got = dg.support_batch(cands, [20] * len(cands), [lam] * len(cands), fx.MODE_VERDICT)
+            for p, r in zip(cands, got):
+                want = O.query(g, p, 20, lam, O.VERDICT)
+                for k in ("tau", "support", "frequent", "embedding_count"):
+                    assert r[k] == want[k], (p, k, r[k], want[k])
+
+
+def test_alone_equals_in_the_mix(ctx, ctx_small, er1k):
+    """A pattern's result does not depend on what else is in the batch, on the
+    batch order, or on the slice capacity (tolerance 0: all results are integers)."""
+    g = er1k
+    pats = sample_patterns(g, 60, seed=31, kmin=2, kmax=5)
+    rng = np.random.default_rng(5)
+    with ctx.load_graph(g) as dg, ctx_small.load_graph(g) as ds:
+        alone = [dg.support(p, 20, 0.5, fx.MODE_FULL) for p in pats]
+        mix = dg.support_batch(pats, [20] * len(pats), [0.5] * len(pats), fx.MODE_FULL)
+        perm = rng.permutation(len(pats))
+        mix2 = ds.support_batch([pats[i] for i in perm], [20] * len(pats), [0.5] * len(pats), fx.MODE_FULL)
+        keys = ("tau", "support", "frequent", "embedding_count", "count_saturated", "digest")
+        for i in range(len(pats)):
+            _say("mix", i)
+            for k in keys:
+                assert alone[i][k] == mix[i][k], (i, k)
+        for j, i in enumerate(perm):
+            for k in keys:
+                assert alone[i][k] == mix2[j][k], (i, k)
