@@ -38,6 +38,9 @@ WORKLOADS = {
     "cl100k-l2": dict(graph="cl100k", sigma=200, lam=1.0, levels=2,
                       desc="Chung-Lu 100K vertices / 500K edges (gamma 2.1), 20 Zipf(1.2) vertex labels, "
                            "3 edge labels; all candidates of mining levels 1-2 at sigma=200, lambda=1.0"),
+    "cl100k-l3": dict(graph="cl100k", sigma=200, lam=1.0, levels=3,
+                      desc="Chung-Lu 100K vertices / 500K edges (gamma 2.1), 20 Zipf(1.2) vertex labels, "
+                           "3 edge labels; all candidates of mining levels 1-3 at sigma=200, lambda=1.0"),
     "cl100k-l2-l03": dict(graph="cl100k", sigma=200, lam=0.3, levels=2,
                           desc="as cl100k-l2 with lambda=0.3"),
     "er1k-l4": dict(graph="er1k", sigma=20, lam=1.0, levels=4,
@@ -143,16 +146,17 @@ def main():
     mode = fx.MODE_FULL if args.mode == "full" else fx.MODE_VERDICT
     sig = [spec["sigma"]] * len(cands)
     lam = [spec["lam"]] * len(cands)
+    batch = fx.PatternBatch(cands)
 
     for w in range(args.warmup):
-        dg.support_batch(cands, sig, lam, mode)
+        dg.support_batch_array(batch, spec["sigma"], spec["lam"], mode)
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     ctx.stats(reset=True)
     results = None
     t0 = time.perf_counter()
     for k in range(args.steps):
-        results = dg.support_batch(cands, sig, lam, mode)
+        results = dg.support_batch_array(batch, spec["sigma"], spec["lam"], mode)
         log(f"[bench] step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -160,9 +164,10 @@ def main():
 
     P = len(cands)
     value = P * args.steps / dt
-    emb = sum(r["embedding_count"] for r in results if r["embedding_count"] > 0 and not r["count_saturated"])
-    qms = np.array([r["device_ms"] for r in results])
-    frequent = sum(r["frequent"] for r in results)
+    ok = (results["embedding_count"] > 0) & (results["count_saturated"] == 0)
+    emb = int(results["embedding_count"][ok].sum())
+    qms = results["device_ms"]
+    frequent = int(results["frequent"].sum())
 
     roofline = None
     if st["probe_launches"] and st["probe_ms"] > 0:

@@ -145,7 +145,8 @@ typedef struct {
  *                     0x243f6a8885a308d3 and 0x13198a2e03707344); else 0.
  *   steps             expansion steps executed on the device.
  *   rounds            parallel greedy rounds executed on the device.
- *   device_ms         time between the first and last device event of the query.
+ *   device_ms         wall time from the start of the call (fx_support) or of the
+ *                     batch (fx_support_batch) until the pattern's result was final.
  *   alg_bytes         algorithmic bytes of the query's expansion kernels (as in
  *                     fx_stats: probe plus scatter). */
 typedef struct {

@@ -19,6 +19,7 @@
 //            counted and hashed at the last vertex, up to the count cap.
 //   list     (fx_enumerate) every complete embedding is written out.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <numeric>
 
@@ -309,8 +310,8 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
     max_active = std::min<int32_t>(max_active, (int32_t)qs.size());
 
     // step buffers
-    const uint64_t max_blocks = (c->step_candidates + FX_BS - 1) / FX_BS + (uint64_t)max_active;
-    FX_TRY(c->flag.ensure(max_blocks * FX_BS));
+    const uint64_t max_blocks = (c->step_candidates + FX_TILE - 1) / FX_TILE + (uint64_t)max_active;
+    FX_TRY(c->flag.ensure(max_blocks * FX_TILE));
     FX_TRY(c->bcnt.ensure(max_blocks * 4));
     FX_TRY(c->boff.ensure((max_blocks + 1) * 8));
     FX_TRY(c->segs_d.ensure((size_t)max_active * sizeof(FxSeg)));
@@ -324,6 +325,7 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
     FxSummary *sums_d = c->sums_d.as<FxSummary>();
     FxSummary *sums_h = c->sums_h.as<FxSummary>();
 
+    const auto t_start = std::chrono::steady_clock::now();
     std::vector<int> active;
     std::vector<int> free_slots;
     for (int k = max_active - 1; k >= 0; k--) free_slots.push_back(k);
@@ -338,6 +340,7 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
         } else {
             fx_result res = base_result(q);
             res.steps = q.steps;
+            res.device_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
             res.rounds = (int32_t)S.rounds;
             res.alg_bytes = S.alg_probe + S.alg_scatter;
             if (r.kind == FX_Q_VERDICT) {
@@ -397,10 +400,10 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
             carve(q, nv);
             q.slot = free_slots.back();
             free_slots.pop_back();
-            FX_HIP(hipMemcpyAsync(q.plan, &q.hp.plan, sizeof(FxPlan), hipMemcpyHostToDevice, s));
             FxInit &I = inits[ninit++];
+            I.plan = q.hp.plan;
+            I.plan_dst = q.plan;
             I.lev0 = q.lev[0];
-            I.plan = q.plan;
             I.U = q.U;
             I.sum = sums_d + q.slot;
             I.u_words = u_words;
@@ -468,7 +471,7 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
             S.flags = flags;
             S.kind = kind;
             blk0[nsegs] = nblocks;
-            nblocks += (uint32_t)((span + FX_BS - 1) / FX_BS);
+            nblocks += (uint32_t)((span + FX_TILE - 1) / FX_TILE);
             budget -= span;
             q.seg_l = l;
             q.seg_kind = kind;

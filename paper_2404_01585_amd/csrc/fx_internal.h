@@ -27,6 +27,9 @@
 #define FX_MAXN 16
 #define FX_NLF 4
 #define FX_BS 256            // threads per workgroup for the streaming kernels
+#define FX_ITEMS 4           // candidates per thread in the expansion kernels
+#define FX_TILE (FX_BS * FX_ITEMS)  // candidates per expansion workgroup
+#define FX_LDSP 1024         // partial offsets a workgroup stages in LDS
 #define FX_GREEDY_H 4096     // LDS hash slots of the per-query greedy
 #define FX_GREEDY_VN 2048    // embedding-vertices per greedy chunk (<= H / 2)
 
@@ -103,16 +106,18 @@ struct FxSeg {
     uint64_t t0;            // first flattened candidate of the slice
     int64_t rank_base;      // rank of the first complete embedding this step writes
     uint32_t span;          // candidates in the slice
-    uint32_t blk0;          // first workgroup of this segment in the launch
+    uint32_t blk0;          // first workgroup of this segment in the launch (FX_TILE candidates each)
     int32_t n, l;
     int32_t flags;          // FX_PROBE_*
     int32_t kind;           // FX_SEG_*
 };
 
-// Per-query initialisation (admission or a new phase).
+// Per-query initialisation at admission: plan upload, U and counters cleared,
+// level 0 set up.
 struct FxInit {
+    FxPlan plan;            // copied to plan_dst
+    FxPlan *plan_dst;
     FxLevelDev lev0;
-    const FxPlan *plan;
     uint32_t *U;            // cleared when clear_u != 0
     FxSummary *sum;         // cleared when clear_sum != 0
     uint64_t u_words;

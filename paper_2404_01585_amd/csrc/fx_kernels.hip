@@ -94,11 +94,57 @@ struct Cand {
     bool first;          // first candidate of its partial
 };
 
-// Loads the partial and the candidate behind flattened index t.
-__device__ __forceinline__ void load_cand(const FxGraphDev &g, const FxLevelDev &in, int32_t l, int64_t nparts,
+// The partials a workgroup's tile of candidates [tfirst, tlast] touches:
+// [p0, p0 + np).  When they are few, their offsets are staged in LDS so each
+// thread finds its partial with an LDS search.  Called by every thread.
+struct TileMap {
+    int64_t p0;
+    int64_t np;
+    bool staged;
+};
+
+__device__ __forceinline__ TileMap map_tile(const int64_t *__restrict__ off, int64_t nparts, uint64_t tfirst,
+                                            uint64_t tlast, int64_t *s_off, int64_t *s_meta)
+{
+    if (threadIdx.x == 0) s_meta[0] = find_part(off, nparts, tfirst);
+    if (threadIdx.x == 64) s_meta[1] = find_part(off, nparts, tlast);
+    __syncthreads();
+    TileMap m;
+    m.p0 = s_meta[0];
+    m.np = s_meta[1] - m.p0 + 1;
+    m.staged = m.np + 1 <= FX_LDSP;
+    if (m.staged) {
+        for (int64_t k = threadIdx.x; k <= m.np; k += FX_BS) s_off[k] = off[m.p0 + k];  // off[p1 + 1] exists
+    }
+    __syncthreads();
+    return m;
+}
+
+// Partial of flattened candidate t (t inside the tile of m).
+__device__ __forceinline__ int64_t tile_part(const TileMap &m, const int64_t *__restrict__ off, const int64_t *s_off,
+                                             uint64_t t)
+{
+    int64_t lo = 0, hi = m.np;  // largest k with offset[p0 + k] <= t
+    if (m.staged) {
+        while (hi - lo > 1) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((uint64_t)s_off[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+    } else {
+        while (hi - lo > 1) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((uint64_t)off[m.p0 + mid] <= t) lo = mid;
+            else hi = mid;
+        }
+    }
+    return m.p0 + lo;
+}
+
+// Loads partial p and its candidate at flattened index t.
+__device__ __forceinline__ void load_cand(const FxGraphDev &g, const FxLevelDev &in, int32_t l, int64_t p,
                                           uint64_t t, Cand &x)
 {
-    int64_t p = find_part(in.off, nparts, t);
     int64_t j = (int64_t)(t - (uint64_t)in.off[p]);
     const int32_t *row = in.rows + p * l;
 #pragma unroll
@@ -193,48 +239,59 @@ __device__ __forceinline__ void tuple_hash(const Cand &x, int32_t l, uint64_t &h
     h2 = mix64(b ^ (uint64_t)(uint32_t)x.c);
 }
 
-// Test every candidate of every segment; one thread per candidate.  Writes
-// a pass flag per candidate and the number of passes per workgroup.
+// Test every candidate of every segment (FX_ITEMS per thread, strided by
+// the workgroup size so each item pass covers consecutive candidates).
+// Writes a pass flag per candidate and the number of passes per workgroup.
 __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__restrict__ segs,
                                                  const uint32_t *__restrict__ blk0s, int32_t nsegs, uint8_t *flag,
                                                  uint32_t *bcnt)
 {
+    __shared__ int64_t s_off[FX_LDSP + 1];
+    __shared__ int64_t s_meta[2];
     __shared__ uint32_t wcnt[FX_BS / 64];
     const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
     const FxSeg &S = segs[si];
     const int32_t l = S.l, n = S.n, flags = S.flags;
-    const uint32_t tl = (blockIdx.x - S.blk0) * FX_BS + threadIdx.x;
-    bool mat = false, cnt = false;
+    const uint32_t tile0 = (blockIdx.x - S.blk0) * FX_TILE;
+    const uint32_t tile_n = min((uint32_t)FX_TILE, S.span - tile0);
+    const TileMap m = map_tile(S.in.off, S.nparts, S.t0 + tile0, S.t0 + tile0 + tile_n - 1, s_off, s_meta);
+    const bool ufilter = (flags & FX_PROBE_UFILTER) != 0;
+    const bool count = (flags & FX_PROBE_COUNT) != 0;
+    uint32_t passed = 0, cnt = 0, bytes = 0;
     uint64_t h1 = 0, h2 = 0;
-    uint32_t bytes = 0;
-    if (tl < S.span) {
-        Cand x;
-        load_cand(g, S.in, l, S.nparts, S.t0 + tl, x);
-        const bool ufilter = (flags & FX_PROBE_UFILTER) != 0;
-        const bool count = (flags & FX_PROBE_COUNT) != 0;
-        // candidate entry + flag; the partial row and its run descriptor once
-        bytes = (x.anc >= 0 ? 8u : 4u) + 1u;
-        if (x.first || tl == 0) bytes += 4u * (uint32_t)l + 21u;
-        bool ok = true;
-        if (ufilter) {
-            ok = !touches_used(S.U, x, l);
-            bytes += 4u * (uint32_t)(l + 1);
-        }
-        if (ok) ok = feasible(g, S.plan, n, l, x, bytes);
-        if (ok) {
-            if (count) {
-                cnt = true;
-                tuple_hash(x, l, h1, h2);
+#pragma unroll
+    for (int it = 0; it < FX_ITEMS; it++) {
+        const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
+        bool mat = false;
+        if (tl < S.span) {
+            const uint64_t t = S.t0 + tl;
+            Cand x;
+            load_cand(g, S.in, l, tile_part(m, S.in.off, s_off, t), t, x);
+            // candidate entry + flag; the partial row and its run descriptor once
+            bytes += (x.anc >= 0 ? 8u : 4u) + 1u;
+            if (x.first || tl == tile0) bytes += 4u * (uint32_t)l + 21u;
+            bool ok = true;
+            if (ufilter) {
+                ok = !touches_used(S.U, x, l);
+                bytes += 4u * (uint32_t)(l + 1);
             }
-            mat = S.kind != FX_SEG_COUNT;
+            if (ok) ok = feasible(g, S.plan, n, l, x, bytes);
+            if (ok) {
+                if (count) {
+                    uint64_t a, b;
+                    tuple_hash(x, l, a, b);
+                    cnt++;
+                    h1 += a;
+                    h2 ^= b;
+                }
+                mat = S.kind != FX_SEG_COUNT;
+            }
+            flag[(uint64_t)blockIdx.x * FX_TILE + it * FX_BS + threadIdx.x] = mat ? 1 : 0;
         }
-        flag[(uint64_t)blockIdx.x * FX_BS + threadIdx.x] = mat ? 1 : 0;
+        passed += mat ? 1u : 0u;
     }
-    const uint64_t bal = __ballot(mat);
-    const uint32_t wave = threadIdx.x >> 6;
-    if (__lane_id() == 0) wcnt[wave] = (uint32_t)__popcll(bal);
-    if (flags & FX_PROBE_COUNT) {  // uniform across the workgroup
-        unsigned long long c = cnt ? 1ULL : 0ULL;
+    if (count) {  // uniform across the workgroup
+        unsigned long long c = cnt;
         unsigned long long s1 = h1, s2 = h2;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
@@ -250,9 +307,16 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
     }
     {
         unsigned long long b = bytes;
+        uint32_t pc = passed;
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) b += __shfl_xor(b, o);
-        if (__lane_id() == 0 && b) atomicAdd(&S.sum->alg_probe, b);
+        for (int o = 32; o >= 1; o >>= 1) {
+            b += __shfl_xor(b, o);
+            pc += __shfl_xor(pc, o);
+        }
+        if (__lane_id() == 0) {
+            if (b) atomicAdd(&S.sum->alg_probe, b);
+            wcnt[threadIdx.x >> 6] = pc;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) bcnt[blockIdx.x] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
@@ -287,74 +351,91 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t *__restrict
 }
 
 // Ordered write of the passing candidates of each segment into its level l+1
-// (position = passes before it in the segment), with the candidate run of
-// the next pattern vertex for inner levels.
+// (position = passes before it in the segment, in candidate order), with the
+// candidate run of the next pattern vertex for inner levels.
 __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
                                                    const uint32_t *__restrict__ blk0s, int32_t nsegs,
                                                    const uint8_t *__restrict__ flag,
                                                    const uint64_t *__restrict__ boff)
 {
-    __shared__ uint32_t wcnt[FX_BS / 64];
+    __shared__ int64_t s_off[FX_LDSP + 1];
+    __shared__ int64_t s_meta[2];
+    __shared__ uint32_t wcnt[FX_ITEMS][FX_BS / 64];
     const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
     const FxSeg &S = segs[si];
     const int32_t l = S.l, n = S.n;
-    const uint32_t tl = (blockIdx.x - S.blk0) * FX_BS + threadIdx.x;
     const uint64_t seg_base = boff[S.blk0];
     if (blockIdx.x == S.blk0 && threadIdx.x == 0) {
-        const uint32_t nblk = (S.span + FX_BS - 1) / FX_BS;
+        const uint32_t nblk = (S.span + FX_TILE - 1) / FX_TILE;
         S.sum->total_out = boff[S.blk0 + nblk] - seg_base;
     }
     if (S.kind == FX_SEG_COUNT) return;  // nothing is written for a counting segment
-    const bool f = tl < S.span && flag[(uint64_t)blockIdx.x * FX_BS + threadIdx.x];
-    const uint64_t bal = __ballot(f);
+    const uint32_t tile0 = (blockIdx.x - S.blk0) * FX_TILE;
     const uint32_t wave = threadIdx.x >> 6;
-    if (__lane_id() == 0) wcnt[wave] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    const int32_t w1 = l + 1;
-    // flag read per candidate; row and run descriptor written per survivor
-    uint32_t bytes = (tl < S.span ? 1u : 0u) + (f ? 4u * (uint32_t)w1 : 0u) + ((f && w1 < n) ? 13u : 0u);
-    if (f) {
-        uint64_t pos = boff[blockIdx.x] - seg_base + (uint64_t)__popcll(bal & lanemask_lt());
-        for (uint32_t w = 0; w < wave; w++) pos += wcnt[w];
-        Cand x;
-        load_cand(g, S.in, l, S.nparts, S.t0 + tl, x);
-        int32_t *dst = S.out.rows + pos * w1;
+    uint64_t bal[FX_ITEMS];
+    bool f[FX_ITEMS];
 #pragma unroll
-        for (int k = 0; k < FX_MAXN; k++)
-            if (k < l) dst[k] = x.v[k];
-        dst[l] = x.c;
-        if (w1 < n) {
-            // candidate run of the next pattern vertex i2 = l + 1: the shortest
-            // run among its earlier neighbours, or its label bucket.
-            const FxPlan *plan = S.plan;
-            const int32_t i2 = w1;
-            const uint32_t vl = plan->vl[i2];
-            const int32_t nb = plan->nback[i2];
-            int64_t best_lo = 0;
-            int32_t best_len = 0;
-            int32_t best_anc = -1;
-            if (nb == 0) {
-                best_lo = g.bptr[vl];
-                best_len = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
-            } else {
-                best_len = 0x7fffffff;
-                for (int kk = 0; kk < nb; kk++) {
-                    int32_t b = plan->back[i2][kk];
-                    int32_t u = (b == l) ? x.c : pick(x.v, b);
-                    int64_t lo;
-                    int32_t len;
-                    run_of(g, u, run_key(vl, plan->bel[i2][kk]), lo, len, bytes);
-                    if (len < best_len) {
-                        best_len = len;
-                        best_lo = lo;
-                        best_anc = b;
+    for (int it = 0; it < FX_ITEMS; it++) {
+        const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
+        f[it] = tl < S.span && flag[(uint64_t)blockIdx.x * FX_TILE + it * FX_BS + threadIdx.x];
+        bal[it] = __ballot(f[it]);
+        if (__lane_id() == 0) wcnt[it][wave] = (uint32_t)__popcll(bal[it]);
+    }
+    const uint32_t tile_n = min((uint32_t)FX_TILE, S.span - tile0);
+    const TileMap m = map_tile(S.in.off, S.nparts, S.t0 + tile0, S.t0 + tile0 + tile_n - 1, s_off, s_meta);
+    const int32_t w1 = l + 1;
+    uint32_t bytes = 0;
+    uint64_t pos = boff[blockIdx.x] - seg_base;
+#pragma unroll
+    for (int it = 0; it < FX_ITEMS; it++) {
+        const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
+        // flag read per candidate; row and run descriptor written per survivor
+        bytes += (tl < S.span ? 1u : 0u) + (f[it] ? 4u * (uint32_t)w1 : 0u) + ((f[it] && w1 < n) ? 13u : 0u);
+        if (f[it]) {
+            uint64_t p_out = pos + (uint64_t)__popcll(bal[it] & lanemask_lt());
+            for (uint32_t w = 0; w < wave; w++) p_out += wcnt[it][w];
+            const uint64_t t = S.t0 + tl;
+            Cand x;
+            load_cand(g, S.in, l, tile_part(m, S.in.off, s_off, t), t, x);
+            int32_t *dst = S.out.rows + p_out * w1;
+#pragma unroll
+            for (int k = 0; k < FX_MAXN; k++)
+                if (k < l) dst[k] = x.v[k];
+            dst[l] = x.c;
+            if (w1 < n) {
+                // candidate run of the next pattern vertex i2 = l + 1: the
+                // shortest run among its earlier neighbours, or its label bucket.
+                const FxPlan *plan = S.plan;
+                const int32_t i2 = w1;
+                const uint32_t vl = plan->vl[i2];
+                const int32_t nb = plan->nback[i2];
+                int64_t best_lo = 0;
+                int32_t best_len = 0;
+                int32_t best_anc = -1;
+                if (nb == 0) {
+                    best_lo = g.bptr[vl];
+                    best_len = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
+                } else {
+                    best_len = 0x7fffffff;
+                    for (int kk = 0; kk < nb; kk++) {
+                        int32_t b = plan->back[i2][kk];
+                        int32_t u = (b == l) ? x.c : pick(x.v, b);
+                        int64_t lo;
+                        int32_t len;
+                        run_of(g, u, run_key(vl, plan->bel[i2][kk]), lo, len, bytes);
+                        if (len < best_len) {
+                            best_len = len;
+                            best_lo = lo;
+                            best_anc = b;
+                        }
                     }
                 }
+                S.out.lo[p_out] = best_lo;
+                S.out.len[p_out] = best_len;
+                S.out.anc[p_out] = (int8_t)best_anc;
             }
-            S.out.lo[pos] = best_lo;
-            S.out.len[pos] = best_len;
-            S.out.anc[pos] = (int8_t)best_anc;
         }
+        for (uint32_t w = 0; w < FX_BS / 64; w++) pos += wcnt[it][w];
     }
     unsigned long long b = bytes;
 #pragma unroll
@@ -363,35 +444,41 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
 }
 
 // Exclusive scan of the run lengths of each inner segment's new level (one
-// workgroup per segment); writes off[0..N] and the level's candidate total.
+// workgroup per segment, each wave a contiguous quarter read in coalesced
+// 64-wide tiles); writes off[0..N] and the level's candidate total.
 __global__ __launch_bounds__(FX_BS) void k_scan_len(const FxSeg *__restrict__ segs)
 {
-    __shared__ int64_t part[FX_BS];
+    __shared__ long long wsum[FX_BS / 64];
     const FxSeg &S = segs[blockIdx.x];
     if (S.kind != FX_SEG_INNER) return;
     const uint64_t N = S.sum->total_out;
-    const uint64_t per = (N + FX_BS - 1) / FX_BS;
-    const uint64_t beg = (uint64_t)threadIdx.x * per;
-    int64_t s = 0;
-    for (uint64_t k = 0; k < per; k++)
-        if (beg + k < N) s += S.out.len[beg + k];
-    part[threadIdx.x] = s;
+    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
+    const uint64_t quarter = ((N + 3) / 4 + 63) / 64 * 64;
+    const uint64_t beg = min((uint64_t)wave * quarter, N), end = min(beg + quarter, N);
+    long long s = 0;
+    for (uint64_t i = beg + lane; i < end; i += 64) s += S.out.len[i];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) wsum[wave] = s;
     __syncthreads();
-    for (uint32_t o = 1; o < FX_BS; o <<= 1) {
-        int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-    for (uint64_t k = 0; k < per; k++)
-        if (beg + k < N) {
-            S.out.off[beg + k] = run;
-            run += S.out.len[beg + k];
+    long long carry = 0;
+    for (uint32_t w = 0; w < wave; w++) carry += wsum[w];
+    for (uint64_t i0 = beg; i0 < end; i0 += 64) {
+        const uint64_t i = i0 + lane;
+        const long long v = i < end ? (long long)S.out.len[i] : 0;
+        long long inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const long long u = __shfl_up(inc, o);
+            if (lane >= (uint32_t)o) inc += u;
         }
+        if (i < end) S.out.off[i] = carry + inc - v;
+        carry += __shfl(inc, 63);
+    }
     if (threadIdx.x == FX_BS - 1) {
-        S.out.off[N] = part[FX_BS - 1];
-        S.sum->t_next = (unsigned long long)part[FX_BS - 1];
+        const long long total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        S.out.off[N] = total;
+        S.sum->t_next = (unsigned long long)total;
     }
 }
 
@@ -518,11 +605,17 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
 __global__ void k_init(FxGraphDev g, const FxInit *__restrict__ inits)
 {
     const FxInit &I = inits[blockIdx.x];
+    {
+        const uint32_t *src = (const uint32_t *)&I.plan;
+        uint32_t *dst = (uint32_t *)I.plan_dst;
+        for (uint32_t k = threadIdx.x; k < sizeof(FxPlan) / 4; k += blockDim.x) dst[k] = src[k];
+    }
+    __syncthreads();  // the plan is read below
     if (I.clear_u)
         for (uint64_t k = threadIdx.x; k < I.u_words; k += blockDim.x) I.U[k] = 0u;
     if (I.clear_sum && threadIdx.x < sizeof(FxSummary) / 8) ((unsigned long long *)I.sum)[threadIdx.x] = 0ULL;
     if (threadIdx.x == 0) {
-        const uint32_t vl = I.plan->vl[0];
+        const uint32_t vl = I.plan.vl[0];
         I.lev0.lo[0] = g.bptr[vl];
         I.lev0.len[0] = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
         I.lev0.anc[0] = -1;

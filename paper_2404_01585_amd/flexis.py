@@ -87,6 +87,47 @@ class ResultC(ctypes.Structure):
                     device_ms=self.device_ms, alg_bytes=int(self.alg_bytes))
 
 
+# numpy views of the C structs (same field order, offsets and sizes)
+PATTERN_DTYPE = np.dtype([("n", "<i4"), ("m", "<i4"), ("vlabel", "<u8"), ("edges", "<u8"), ("elabel", "<u8")])
+RESULT_DTYPE = np.dtype([("tau", "<i8"), ("support", "<i8"), ("frequent", "<i4"), ("count_saturated", "<i4"),
+                         ("embedding_count", "<i8"), ("digest", "<u8", (2,)), ("steps", "<i4"), ("rounds", "<i4"),
+                         ("device_ms", "<f8"), ("alg_bytes", "<u8")])
+assert PATTERN_DTYPE.itemsize == ctypes.sizeof(PatternC)
+assert RESULT_DTYPE.itemsize == ctypes.sizeof(ResultC)
+
+
+class PatternBatch:
+    """A list of patterns packed once into fx_pattern structs (for repeated batches)."""
+
+    def __init__(self, patterns):
+        self.patterns = list(patterns)
+        k = len(self.patterns)
+        n = np.array([len(p.vlabel) for p in self.patterns], dtype=np.int64)
+        m = np.array([len(p.edges) for p in self.patterns], dtype=np.int64)
+        self.vl = np.ascontiguousarray(np.concatenate([np.asarray(p.vlabel, dtype=np.int32) for p in self.patterns])
+                                       if k else np.zeros(1, np.int32), dtype=np.int32)
+        self.ed = np.ascontiguousarray(np.concatenate([np.asarray(p.edges, dtype=np.int32).reshape(-1)
+                                                       for p in self.patterns]) if k else np.zeros(1, np.int32),
+                                       dtype=np.int32)
+        self.el = np.ascontiguousarray(np.concatenate([np.asarray(p.elabel, dtype=np.int32) for p in self.patterns])
+                                       if k else np.zeros(1, np.int32), dtype=np.int32)
+        if self.ed.size == 0:
+            self.ed = np.zeros(1, np.int32)
+        if self.el.size == 0:
+            self.el = np.zeros(1, np.int32)
+        vo = np.concatenate([[0], np.cumsum(n)[:-1]]) if k else np.zeros(0, np.int64)
+        eo = np.concatenate([[0], np.cumsum(m)[:-1]]) if k else np.zeros(0, np.int64)
+        self.arr = np.zeros(max(k, 1), dtype=PATTERN_DTYPE)
+        self.arr["n"][:k] = n
+        self.arr["m"][:k] = m
+        self.arr["vlabel"][:k] = self.vl.ctypes.data + 4 * vo
+        self.arr["edges"][:k] = self.ed.ctypes.data + 8 * eo
+        self.arr["elabel"][:k] = self.el.ctypes.data + 4 * eo
+
+    def __len__(self):
+        return len(self.patterns)
+
+
 _lib = None
 
 
@@ -260,16 +301,25 @@ class DeviceGraph:
                                            int(cap), ctypes.byref(cnt)))
         return int(cnt.value), rows[:min(cap, cnt.value)]
 
+    def support_batch_array(self, batch: "PatternBatch", sigma, lam, mode: int = MODE_FULL) -> np.ndarray:
+        """fx_support_batch; results as a numpy array of RESULT_DTYPE."""
+        k = len(batch)
+        sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.int64), (k,)))
+        lm = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float64), (k,)))
+        res = np.zeros(max(k, 1), dtype=RESULT_DTYPE)
+        _check(load_library().fx_support_batch(self._h, k, batch.arr.ctypes.data, sg.ctypes.data, lm.ctypes.data,
+                                               int(mode), res.ctypes.data))
+        return res[:k]
+
     def support_batch(self, patterns: List, sigma: Sequence[int], lam: Sequence[float],
                       mode: int = MODE_FULL) -> List[Dict]:
-        holders = [_PatternHolder.of(p) for p in patterns]
-        arr = (PatternC * max(len(holders), 1))(*[h.c for h in holders])
-        sg = np.ascontiguousarray(sigma, dtype=np.int64)
-        lm = np.ascontiguousarray(lam, dtype=np.float64)
-        res = (ResultC * max(len(holders), 1))()
-        _check(load_library().fx_support_batch(self._h, len(holders), arr, sg.ctypes.data, lm.ctypes.data,
-                                               int(mode), res))
-        return [res[i].to_dict() for i in range(len(holders))]
+        res = self.support_batch_array(PatternBatch(patterns), sigma, lam, mode)
+        out = []
+        for r in res:
+            d = {k: (int(r[k]) if k != "device_ms" else float(r[k])) for k in RESULT_DTYPE.names if k != "digest"}
+            d["digest"] = (int(r["digest"][0]), int(r["digest"][1]))
+            out.append(d)
+        return out
 
     def close(self):
         if self._h:
