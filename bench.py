@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--digest", action="store_true",
+                    help="also hash every embedding (FULL-mode digest); counts are exact either way")
     ap.add_argument("--plain-seconds", type=float, default=5.0,
                     help="time the one-pattern-per-call form on a prefix of the batch for this long")
     args = ap.parse_args()
@@ -138,7 +140,7 @@ def main():
     log(f"[bench] graph {spec['graph']}: {g.num_vertices} vertices, {g.num_adj // 2} edges "
         f"({time.perf_counter() - t:.1f} s)")
     torch.cuda.set_device(0)
-    ctx = fx.Context(device=0, kernel_timing=not args.no_timing)
+    ctx = fx.Context(device=0, kernel_timing=not args.no_timing, no_digest=not args.digest)
     dg = ctx.load_graph(g)
     t = time.perf_counter()
     cands, per_level = build_candidates(dg, g, spec)
@@ -215,12 +217,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": spec["desc"], "patterns": P,
                    "patterns_per_level": per_level, "sigma": spec["sigma"], "lambda": spec["lam"],
-                   "mode": args.mode, "count_cap": ctx.count_cap,
+                   "mode": args.mode, "count_cap": ctx.count_cap, "digest": bool(args.digest),
                    "form": "batched (all candidates of the batch in flight, one segment each per step)"},
         "embeddings_per_s": round(emb * args.steps / dt, 1),
         "frequent": frequent,
         "query_device_ms_p50": round(float(np.percentile(qms, 50)), 4),
         "query_device_ms_p99": round(float(np.percentile(qms, 99)), 4),
+        "query_steps_p50_p99_max": [int(np.percentile(results["steps"], 50)), int(np.percentile(results["steps"], 99)),
+                                    int(results["steps"].max())],
+        "greedy_rounds_max": int(results["rounds"].max()),
         "syncs_per_step": st["syncs"] / args.steps,
         "device_steps_per_step": st["steps"] / args.steps,
         "plain_form": plain,

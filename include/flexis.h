@@ -71,10 +71,16 @@ typedef struct fx_server fx_server;
  *   mem_budget_bytes  device memory the per-pattern stacks of one batch may
  *                     hold at once (0 = 64 GiB); patterns are admitted while
  *                     their projected stack bytes fit.
- *   flags             0, or FX_CTX_KERNEL_TIMING: bracket the kernels of every
- *                     step with HIP events on the context's stream and
- *                     accumulate their durations (see fx_ctx_stats). */
+ *   flags             bitwise or of FX_CTX_KERNEL_TIMING (bracket the kernels of
+ *                     every step with HIP events on the context's stream and
+ *                     accumulate their durations, see fx_ctx_stats) and
+ *                     FX_CTX_NO_DIGEST (below). */
 #define FX_CTX_KERNEL_TIMING 1u
+/* FX_CTX_NO_DIGEST: FULL mode leaves digest at 0 and may count the embeddings
+ * of a pattern whose last vertex is a leaf in closed form (run length minus
+ * the already-matched vertices in the run) instead of one by one.  The count
+ * is exact either way. */
+#define FX_CTX_NO_DIGEST 2u
 typedef struct {
     int32_t device;
     void *hip_stream;

@@ -72,43 +72,69 @@ fx_status HostBuf::ensure(size_t want)
     return FX_OK;
 }
 
-RegionPool::~RegionPool() { trim(); }
+RegionPool::~RegionPool()
+{
+    for (auto &c : chunks)
+        if (c.base) (void)hipFree(c.base);
+}
 
 fx_status RegionPool::take(size_t bytes, void **out)
 {
-    auto it = free_.find(bytes);
-    if (it != free_.end() && !it->second.empty()) {
-        *out = it->second.back();
-        it->second.pop_back();
-        in_use += bytes;
-        return FX_OK;
+    bytes = (bytes + 255) & ~(size_t)255;
+    for (auto &c : chunks)
+        for (auto it = c.free_.begin(); it != c.free_.end(); ++it)
+            if (it->second >= bytes) {  // first fit
+                const size_t off = it->first, len = it->second;
+                c.free_.erase(it);
+                if (len > bytes) c.free_[off + bytes] = len - bytes;
+                *out = c.base + off;
+                in_use += bytes;
+                return FX_OK;
+            }
+    if (held + bytes > budget) {
+        *out = nullptr;
+        return fx_fail(FX_ENOMEM, "query region of %zu bytes does not fit in the %zu-byte budget", bytes, budget);
     }
-    if (held + bytes > budget) trim();  // drop cached regions of other sizes first
-    hipError_t e = hipMalloc(out, bytes);
+    Chunk c;
+    c.size = std::min(std::max(bytes, kChunk), budget - held);
+    hipError_t e = hipMalloc((void **)&c.base, c.size);
     if (e != hipSuccess) {
         *out = nullptr;
-        return fx_fail(FX_ENOMEM, "hipMalloc(%zu) for a query region failed: %s", bytes, hipGetErrorString(e));
+        return fx_fail(FX_ENOMEM, "hipMalloc(%zu) for query regions failed: %s", c.size, hipGetErrorString(e));
     }
+    held += c.size;
+    if (c.size > bytes) c.free_[bytes] = c.size - bytes;
+    *out = c.base;
     in_use += bytes;
-    held += bytes;
+    chunks.push_back(std::move(c));
     return FX_OK;
 }
 
 void RegionPool::give(void *p, size_t bytes)
 {
     if (!p) return;
-    free_[bytes].push_back(p);
-    in_use -= bytes;
-}
-
-void RegionPool::trim()
-{
-    for (auto &kv : free_)
-        for (void *p : kv.second) {
-            (void)hipFree(p);
-            held -= kv.first;
+    bytes = (bytes + 255) & ~(size_t)255;
+    for (auto &c : chunks) {
+        char *q = (char *)p;
+        if (q < c.base || q >= c.base + c.size) continue;
+        size_t off = (size_t)(q - c.base), len = bytes;
+        auto next = c.free_.lower_bound(off);
+        if (next != c.free_.end() && next->first == off + len) {  // merge with the following range
+            len += next->second;
+            next = c.free_.erase(next);
         }
-    free_.clear();
+        if (next != c.free_.begin()) {  // merge with the preceding range
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                off = prev->first;
+                len += prev->second;
+                c.free_.erase(prev);
+            }
+        }
+        c.free_[off] = len;
+        in_use -= bytes;
+        return;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -144,7 +170,8 @@ extern "C" fx_status fx_ctx_create(const fx_ctx_opts *opts, fx_ctx **out)
     if (!out) return fx_fail(FX_EINVAL, "out is NULL");
     fx_ctx_opts o{};
     if (opts) o = *opts;
-    if ((o.flags & ~FX_CTX_KERNEL_TIMING) != 0) return fx_fail(FX_EINVAL, "unknown flags 0x%x", o.flags);
+    if ((o.flags & ~(FX_CTX_KERNEL_TIMING | FX_CTX_NO_DIGEST)) != 0)
+        return fx_fail(FX_EINVAL, "unknown flags 0x%x", o.flags);
     if (o.slice_rows < 0 || o.count_cap < 0 || o.mem_budget_bytes < 0)
         return fx_fail(FX_EINVAL, "slice_rows, count_cap and mem_budget_bytes must be >= 0");
     int ndev = 0;
@@ -159,6 +186,7 @@ extern "C" fx_status fx_ctx_create(const fx_ctx_opts *opts, fx_ctx **out)
     if (o.count_cap > 0) c->count_cap = o.count_cap;
     c->pool.budget = o.mem_budget_bytes > 0 ? (size_t)o.mem_budget_bytes : ((size_t)64 << 30);
     c->timing = (o.flags & FX_CTX_KERNEL_TIMING) != 0;
+    c->no_digest = (o.flags & FX_CTX_NO_DIGEST) != 0;
     for (auto &e : c->evk)
         if (hipEventCreate(&e) != hipSuccess) {
             delete c;

@@ -314,6 +314,8 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
     FX_TRY(c->flag.ensure(max_blocks * FX_TILE));
     FX_TRY(c->bcnt.ensure(max_blocks * 4));
     FX_TRY(c->boff.ensure((max_blocks + 1) * 8));
+    FX_TRY(c->lsum.ensure(max_blocks * 8));
+    FX_TRY(c->loff.ensure((max_blocks + 1) * 8));
     FX_TRY(c->segs_d.ensure((size_t)max_active * sizeof(FxSeg)));
     FX_TRY(c->segs_h.ensure((size_t)max_active * sizeof(FxSeg)));
     FX_TRY(c->blk0_d.ensure(((size_t)max_active + 1) * 4));
@@ -353,7 +355,7 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
                 const bool sat = (int64_t)S.count >= c->count_cap;
                 res.count_saturated = sat;
                 res.embedding_count = sat ? c->count_cap : (int64_t)S.count;
-                if (!sat) {
+                if (!sat && !c->no_digest) {
                     res.digest[0] = S.digest0;
                     res.digest[1] = S.digest1;
                 }
@@ -390,10 +392,9 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
         while (!pending.empty() && !free_slots.empty()) {
             Query &q = qs[pending.front()];
             const size_t bytes = region_size(q, nv);
-            if (!c->pool.fits(bytes) && !active.empty()) break;  // wait until running queries free memory
             fx_status st = c->pool.take(bytes, &q.region);
             if (st != FX_OK) {
-                if (!active.empty()) break;
+                if (!active.empty()) break;  // wait until running queries free their regions
                 return st;
             }
             q.region_bytes = bytes;
@@ -439,9 +440,13 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
                 kind = last ? FX_SEG_GREEDY : FX_SEG_INNER;
                 cap = last ? std::min<uint64_t>(q.last_span, (uint64_t)q.cap) : (uint64_t)q.cap;
             } else if (q.phase == PH_COUNT) {
-                flags = last ? FX_PROBE_COUNT : 0;
-                kind = last ? FX_SEG_COUNT : FX_SEG_INNER;
-                cap = last ? kCountSpan : (uint64_t)q.cap;
+                // without a digest, a leaf last vertex is counted in closed form
+                // from the partials of vertex n-2 (level n-1 is never built)
+                const bool leaf = c->no_digest && q.n >= 2 && q.hp.plan.nback[q.n - 1] == 1;
+                const bool end = leaf ? (l == q.n - 2) : last;
+                flags = end ? (leaf ? FX_PROBE_LEAF : (FX_PROBE_COUNT | (c->no_digest ? 0 : FX_PROBE_HASH))) : 0;
+                kind = end ? FX_SEG_COUNT : FX_SEG_INNER;
+                cap = end ? kCountSpan : (uint64_t)q.cap;
             } else {
                 flags = last ? FX_PROBE_COUNT : 0;
                 kind = last ? FX_SEG_LIST : FX_SEG_INNER;
@@ -491,6 +496,7 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
         hipEvent_t *ev = c->timing ? c->evk : nullptr;
         FX_HIP(fx_launch_step(s, G->dev, c->segs_d.as<FxSeg>(), c->blk0_d.as<uint32_t>(), nsegs, nblocks,
                               c->flag.as<uint8_t>(), c->bcnt.as<uint32_t>(), c->boff.as<uint64_t>(),
+                              c->lsum.as<uint64_t>(), c->loff.as<uint64_t>(),
                               ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, ev ? ev[2] : nullptr,
                               ev ? ev[3] : nullptr, ev ? ev[4] : nullptr, ev ? ev[5] : nullptr, any_inner,
                               any_greedy, any_write));

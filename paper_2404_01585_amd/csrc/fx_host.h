@@ -58,16 +58,23 @@ struct HostBuf {
     T *as() const { return (T *)p; }
 };
 
-// Device regions reused by size class (per-query stacks), with a byte budget:
-// admission control of the engine is "does this query's region fit".
+// Device memory for the per-query stacks: chunks allocated once (up to a byte
+// budget) and carved first-fit, with freed ranges merged back.  Admission
+// control of the engine is "can this query's region be carved".  Nothing is
+// returned to the runtime before the context is destroyed, so steady-state
+// admission makes no allocation call (hipFree would synchronise the device).
 struct RegionPool {
-    std::map<size_t, std::vector<void *>> free_;
+    struct Chunk {
+        char *base = nullptr;
+        size_t size = 0;
+        std::map<size_t, size_t> free_;  // offset -> length, non-adjacent ranges
+    };
+    std::vector<Chunk> chunks;
     size_t in_use = 0, held = 0, budget = 0;
+    static constexpr size_t kChunk = (size_t)4 << 30;
     ~RegionPool();
-    bool fits(size_t bytes) const { return in_use + bytes <= budget; }
-    fx_status take(size_t bytes, void **out);
+    fx_status take(size_t bytes, void **out);  // FX_ENOMEM when nothing fits within the budget
     void give(void *p, size_t bytes);
-    void trim();
 };
 
 struct fx_ctx {
@@ -79,10 +86,11 @@ struct fx_ctx {
     int32_t max_active = 4096;            // queries in flight in a batch
     std::atomic<int> graphs{0};
     bool timing = false;
+    bool no_digest = false;
     fx_stats stats{};
 
     RegionPool pool;
-    DevBuf flag, bcnt, boff, segs_d, blk0_d, inits_d, sums_d;
+    DevBuf flag, bcnt, boff, lsum, loff, segs_d, blk0_d, inits_d, sums_d;
     HostBuf segs_h, blk0_h, inits_h, sums_h;
     hipEvent_t evk[6] = {};
 };

@@ -84,7 +84,7 @@ struct FxLevelDev {
 enum : int32_t {
     FX_SEG_INNER = 0,    // write them to level l+1 (with their next candidate run)
     FX_SEG_GREEDY = 1,   // last vertex: write the complete embeddings, then run the greedy
-    FX_SEG_COUNT = 2,    // last vertex: count and hash them only
+    FX_SEG_COUNT = 2,    // count (and hash) the complete embeddings they give; nothing is written
     FX_SEG_LIST = 3,     // last vertex: write the complete embeddings (listing)
 };
 
@@ -92,6 +92,9 @@ enum : int32_t {
 enum : int32_t {
     FX_PROBE_UFILTER = 1,   // pass only candidates whose partial and vertex avoid the used set U
     FX_PROBE_COUNT = 2,     // count (and hash) every valid candidate of the last vertex
+    FX_PROBE_LEAF = 4,      // candidates of vertex n-2: add the closed-form count of the last
+                            // vertex, a leaf with a single earlier neighbour (no hashing)
+    FX_PROBE_HASH = 8,      // with FX_PROBE_COUNT: also hash every counted embedding
 };
 
 struct FxSeg {
@@ -128,6 +131,7 @@ struct FxInit {
 hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *inits, int32_t ninit);
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
                           int32_t nsegs, uint32_t nblocks, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
+                          uint64_t *lsum, uint64_t *loff,
                           hipEvent_t probe_begin, hipEvent_t probe_end, hipEvent_t scatter_begin,
                           hipEvent_t scatter_end, hipEvent_t greedy_begin, hipEvent_t greedy_end,
                           int32_t any_inner, int32_t any_greedy, int32_t any_write);

@@ -239,6 +239,30 @@ __device__ __forceinline__ void tuple_hash(const Cand &x, int32_t l, uint64_t &h
     h2 = mix64(b ^ (uint64_t)(uint32_t)x.c);
 }
 
+// Embeddings completing the partial (x.v[0..l), x.c) when the last pattern
+// vertex i = l + 1 is a leaf whose only earlier neighbour is a: every vertex
+// of the run of a's image with i's (label, edge label) is a valid image,
+// except the already-matched vertices that lie in that run (injectivity).
+__device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan *__restrict__ plan, int32_t l,
+                                               const Cand &x, uint32_t &bytes)
+{
+    const int32_t i = l + 1;
+    const int32_t a = plan->back[i][0];
+    const uint32_t vl = plan->vl[i];
+    const uint64_t key = run_key(vl, plan->bel[i][0]);
+    const int32_t u = (a == l) ? x.c : pick(x.v, a);
+    int64_t lo;
+    int32_t len;
+    run_of(g, u, key, lo, len, bytes);
+    int64_t c = len;
+    for (int k = 0; k <= l; k++) {
+        if (k == a || plan->vl[k] != vl) continue;
+        const int32_t w = (k == l) ? x.c : pick(x.v, k);
+        if (has_entry(g, u, key | (uint32_t)w, bytes)) c--;
+    }
+    return (uint64_t)c;
+}
+
 // Test every candidate of every segment (FX_ITEMS per thread, strided by
 // the workgroup size so each item pass covers consecutive candidates).
 // Writes a pass flag per candidate and the number of passes per workgroup.
@@ -257,7 +281,10 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
     const TileMap m = map_tile(S.in.off, S.nparts, S.t0 + tile0, S.t0 + tile0 + tile_n - 1, s_off, s_meta);
     const bool ufilter = (flags & FX_PROBE_UFILTER) != 0;
     const bool count = (flags & FX_PROBE_COUNT) != 0;
-    uint32_t passed = 0, cnt = 0, bytes = 0;
+    const bool leaf = (flags & FX_PROBE_LEAF) != 0;
+    const bool hash = (flags & FX_PROBE_HASH) != 0;
+    uint32_t passed = 0, bytes = 0;
+    unsigned long long cnt = 0;
     uint64_t h1 = 0, h2 = 0;
 #pragma unroll
     for (int it = 0; it < FX_ITEMS; it++) {
@@ -278,19 +305,22 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
             if (ok) ok = feasible(g, S.plan, n, l, x, bytes);
             if (ok) {
                 if (count) {
-                    uint64_t a, b;
-                    tuple_hash(x, l, a, b);
                     cnt++;
-                    h1 += a;
-                    h2 ^= b;
+                    if (hash) {
+                        uint64_t a, b;
+                        tuple_hash(x, l, a, b);
+                        h1 += a;
+                        h2 ^= b;
+                    }
                 }
+                if (leaf) cnt += leaf_count(g, S.plan, l, x, bytes);
                 mat = S.kind != FX_SEG_COUNT;
             }
             flag[(uint64_t)blockIdx.x * FX_TILE + it * FX_BS + threadIdx.x] = mat ? 1 : 0;
         }
         passed += mat ? 1u : 0u;
     }
-    if (count) {  // uniform across the workgroup
+    if (count || leaf) {  // uniform across the workgroup
         unsigned long long c = cnt;
         unsigned long long s1 = h1, s2 = h2;
 #pragma unroll
@@ -322,10 +352,10 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
     if (threadIdx.x == 0) bcnt[blockIdx.x] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
 }
 
-// Exclusive scan of the per-workgroup pass counts over the whole launch (one
+// Exclusive scan of per-workgroup values over the whole launch (one
 // workgroup of 1024 threads); boff[nblocks] receives the total.
-__global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t *__restrict__ bcnt, uint32_t nblocks,
-                                                      uint64_t *boff)
+template <class T>
+__global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt, uint32_t nblocks, uint64_t *boff)
 {
     __shared__ uint64_t part[1024];
     const uint32_t per = (nblocks + 1023) / 1024;
@@ -352,15 +382,19 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t *__restrict
 
 // Ordered write of the passing candidates of each segment into its level l+1
 // (position = passes before it in the segment, in candidate order), with the
-// candidate run of the next pattern vertex for inner levels.
+// candidate run of the next pattern vertex for inner levels.  For inner
+// segments it also writes each new row's prefix of run lengths within this
+// workgroup's rows to off[] and the workgroup's total to lsum[]; k_fix_off
+// adds the workgroup offsets after a scan of lsum.
 __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
                                                    const uint32_t *__restrict__ blk0s, int32_t nsegs,
                                                    const uint8_t *__restrict__ flag,
-                                                   const uint64_t *__restrict__ boff)
+                                                   const uint64_t *__restrict__ boff, uint64_t *lsum)
 {
     __shared__ int64_t s_off[FX_LDSP + 1];
     __shared__ int64_t s_meta[2];
     __shared__ uint32_t wcnt[FX_ITEMS][FX_BS / 64];
+    __shared__ unsigned long long ltot[FX_ITEMS][FX_BS / 64];
     const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
     const FxSeg &S = segs[si];
     const int32_t l = S.l, n = S.n;
@@ -369,6 +403,7 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
         const uint32_t nblk = (S.span + FX_TILE - 1) / FX_TILE;
         S.sum->total_out = boff[S.blk0 + nblk] - seg_base;
     }
+    if (S.kind != FX_SEG_INNER && threadIdx.x == 0) lsum[blockIdx.x] = 0;
     if (S.kind == FX_SEG_COUNT) return;  // nothing is written for a counting segment
     const uint32_t tile0 = (blockIdx.x - S.blk0) * FX_TILE;
     const uint32_t wave = threadIdx.x >> 6;
@@ -386,18 +421,21 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
     const int32_t w1 = l + 1;
     uint32_t bytes = 0;
     uint64_t pos = boff[blockIdx.x] - seg_base;
+    uint64_t p_out[FX_ITEMS];
+    int32_t lens[FX_ITEMS];
 #pragma unroll
     for (int it = 0; it < FX_ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
         // flag read per candidate; row and run descriptor written per survivor
-        bytes += (tl < S.span ? 1u : 0u) + (f[it] ? 4u * (uint32_t)w1 : 0u) + ((f[it] && w1 < n) ? 13u : 0u);
+        bytes += (tl < S.span ? 1u : 0u) + (f[it] ? 4u * (uint32_t)w1 : 0u) + ((f[it] && w1 < n) ? 21u : 0u);
+        lens[it] = 0;
+        p_out[it] = pos + (uint64_t)__popcll(bal[it] & lanemask_lt());
+        for (uint32_t w = 0; w < wave; w++) p_out[it] += wcnt[it][w];
         if (f[it]) {
-            uint64_t p_out = pos + (uint64_t)__popcll(bal[it] & lanemask_lt());
-            for (uint32_t w = 0; w < wave; w++) p_out += wcnt[it][w];
             const uint64_t t = S.t0 + tl;
             Cand x;
             load_cand(g, S.in, l, tile_part(m, S.in.off, s_off, t), t, x);
-            int32_t *dst = S.out.rows + p_out * w1;
+            int32_t *dst = S.out.rows + p_out[it] * w1;
 #pragma unroll
             for (int k = 0; k < FX_MAXN; k++)
                 if (k < l) dst[k] = x.v[k];
@@ -430,12 +468,39 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
                         }
                     }
                 }
-                S.out.lo[p_out] = best_lo;
-                S.out.len[p_out] = best_len;
-                S.out.anc[p_out] = (int8_t)best_anc;
+                S.out.lo[p_out[it]] = best_lo;
+                S.out.len[p_out[it]] = best_len;
+                S.out.anc[p_out[it]] = (int8_t)best_anc;
+                lens[it] = best_len;
             }
         }
         for (uint32_t w = 0; w < FX_BS / 64; w++) pos += wcnt[it][w];
+    }
+    if (S.kind == FX_SEG_INNER) {  // uniform across the workgroup
+        // exclusive prefix of the run lengths in output order (item, wave, lane)
+        long long inc[FX_ITEMS];
+        const uint32_t lane = __lane_id();
+#pragma unroll
+        for (int it = 0; it < FX_ITEMS; it++) {
+            inc[it] = lens[it];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const long long u = __shfl_up(inc[it], o);
+                if (lane >= (uint32_t)o) inc[it] += u;
+            }
+            const long long tot = __shfl(inc[it], 63);
+            if (lane == 0) ltot[it][wave] = (unsigned long long)tot;
+        }
+        __syncthreads();
+        uint64_t before = 0;
+#pragma unroll
+        for (int it = 0; it < FX_ITEMS; it++) {
+            uint64_t mine = before;
+            for (uint32_t w = 0; w < wave; w++) mine += ltot[it][w];
+            if (f[it]) S.out.off[p_out[it]] = (int64_t)(mine + (uint64_t)(inc[it] - lens[it]));
+            for (uint32_t w = 0; w < FX_BS / 64; w++) before += ltot[it][w];
+        }
+        if (threadIdx.x == 0) lsum[blockIdx.x] = before;
     }
     unsigned long long b = bytes;
 #pragma unroll
@@ -443,42 +508,27 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
     if (__lane_id() == 0 && b) atomicAdd(&S.sum->alg_scatter, b);
 }
 
-// Exclusive scan of the run lengths of each inner segment's new level (one
-// workgroup per segment, each wave a contiguous quarter read in coalesced
-// 64-wide tiles); writes off[0..N] and the level's candidate total.
-__global__ __launch_bounds__(FX_BS) void k_scan_len(const FxSeg *__restrict__ segs)
+// Adds each workgroup's offset (scan of lsum within its segment) to the
+// run-length prefixes k_scatter wrote, and closes each inner level with
+// off[N] and the level's candidate total.
+__global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ segs, const uint32_t *__restrict__ blk0s,
+                                                   int32_t nsegs, const uint64_t *__restrict__ boff,
+                                                   const uint64_t *__restrict__ loff)
 {
-    __shared__ long long wsum[FX_BS / 64];
-    const FxSeg &S = segs[blockIdx.x];
+    const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
+    const FxSeg &S = segs[si];
     if (S.kind != FX_SEG_INNER) return;
-    const uint64_t N = S.sum->total_out;
-    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
-    const uint64_t quarter = ((N + 3) / 4 + 63) / 64 * 64;
-    const uint64_t beg = min((uint64_t)wave * quarter, N), end = min(beg + quarter, N);
-    long long s = 0;
-    for (uint64_t i = beg + lane; i < end; i += 64) s += S.out.len[i];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) wsum[wave] = s;
-    __syncthreads();
-    long long carry = 0;
-    for (uint32_t w = 0; w < wave; w++) carry += wsum[w];
-    for (uint64_t i0 = beg; i0 < end; i0 += 64) {
-        const uint64_t i = i0 + lane;
-        const long long v = i < end ? (long long)S.out.len[i] : 0;
-        long long inc = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const long long u = __shfl_up(inc, o);
-            if (lane >= (uint32_t)o) inc += u;
-        }
-        if (i < end) S.out.off[i] = carry + inc - v;
-        carry += __shfl(inc, 63);
-    }
-    if (threadIdx.x == FX_BS - 1) {
-        const long long total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        S.out.off[N] = total;
-        S.sum->t_next = (unsigned long long)total;
+    const uint64_t seg_base = boff[S.blk0];
+    const uint64_t r0 = boff[blockIdx.x] - seg_base, r1 = boff[blockIdx.x + 1] - seg_base;
+    const uint64_t add = loff[blockIdx.x] - loff[S.blk0];
+    if (add)
+        for (uint64_t r = r0 + threadIdx.x; r < r1; r += FX_BS) S.out.off[r] += (int64_t)add;
+    if (blockIdx.x == S.blk0 && threadIdx.x == 0) {
+        const uint32_t nblk = (S.span + FX_TILE - 1) / FX_TILE;
+        const uint64_t N = boff[S.blk0 + nblk] - seg_base;
+        const uint64_t total = loff[S.blk0 + nblk] - loff[S.blk0];
+        S.out.off[N] = (int64_t)total;
+        S.sum->t_next = total;
     }
 }
 
@@ -639,6 +689,7 @@ hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *init
 
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
                           int32_t nsegs, uint32_t nblocks, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
+                          uint64_t *lsum, uint64_t *loff,
                           hipEvent_t probe_begin, hipEvent_t probe_end, hipEvent_t scatter_begin,
                           hipEvent_t scatter_end, hipEvent_t greedy_begin, hipEvent_t greedy_end,
                           int32_t any_inner, int32_t any_greedy, int32_t any_write)
@@ -647,12 +698,15 @@ hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs,
     if (probe_begin && (e = hipEventRecord(probe_begin, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_probe, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, bcnt);
     if (probe_end && (e = hipEventRecord(probe_end, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bcnt, nblocks, boff);
+    hipLaunchKernelGGL(k_scan_blocks<uint32_t>, dim3(1), dim3(1024), 0, s, bcnt, nblocks, boff);
     if (scatter_begin && (e = hipEventRecord(scatter_begin, s)) != hipSuccess) return e;
     (void)any_write;
-    hipLaunchKernelGGL(k_scatter, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, boff);
+    hipLaunchKernelGGL(k_scatter, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, boff, lsum);
     if (scatter_end && (e = hipEventRecord(scatter_end, s)) != hipSuccess) return e;
-    if (any_inner) hipLaunchKernelGGL(k_scan_len, dim3(nsegs), dim3(FX_BS), 0, s, segs);
+    if (any_inner) {
+        hipLaunchKernelGGL(k_scan_blocks<uint64_t>, dim3(1), dim3(1024), 0, s, lsum, nblocks, loff);
+        hipLaunchKernelGGL(k_fix_off, dim3(nblocks), dim3(FX_BS), 0, s, segs, blk0s, nsegs, boff, loff);
+    }
     if (greedy_begin && (e = hipEventRecord(greedy_begin, s)) != hipSuccess) return e;
     if (any_greedy) hipLaunchKernelGGL(k_greedy, dim3(nsegs), dim3(FX_BS), 0, s, segs);
     if (greedy_end && (e = hipEventRecord(greedy_end, s)) != hipSuccess) return e;

@@ -39,6 +39,7 @@ EXPORTS = ["fx_ctx_create", "fx_ctx_destroy", "fx_graph_load", "fx_graph_destroy
            "fx_enumerate", "fx_support_batch", "fx_ctx_stats", "fx_last_error", "fx_version"]
 
 CTX_KERNEL_TIMING = 1
+CTX_NO_DIGEST = 2
 
 
 class FxError(RuntimeError):
@@ -211,7 +212,7 @@ class Context:
     """fx_ctx: a device, a stream, and the workspace sizing."""
 
     def __init__(self, device: int = 0, stream: Optional[int] = None, slice_rows: int = 0, count_cap: int = 0,
-                 kernel_timing: bool = False, mem_budget_bytes: int = 0):
+                 kernel_timing: bool = False, mem_budget_bytes: int = 0, no_digest: bool = False):
         lib = load_library()
         if stream is None:
             import torch
@@ -219,7 +220,7 @@ class Context:
             stream = _current_stream()
         self.stream = stream
         self._opts = CtxOpts(device, stream or None, slice_rows, count_cap, mem_budget_bytes,
-                             CTX_KERNEL_TIMING if kernel_timing else 0)
+                             (CTX_KERNEL_TIMING if kernel_timing else 0) | (CTX_NO_DIGEST if no_digest else 0))
         self._h = ctypes.c_void_p()
         _check(lib.fx_ctx_create(ctypes.byref(self._opts), ctypes.byref(self._h)))
         self.count_cap = count_cap if count_cap > 0 else (1 << 62)

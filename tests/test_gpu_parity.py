@@ -271,3 +271,29 @@ def test_alone_equals_in_the_mix(ctx, ctx_small, er1k):
         for j, i in enumerate(perm):
             for k in keys:
                 assert alone[i][k] == mix2[j][k], (i, k)
+
+
+@pytest.mark.parametrize("slice_rows", [0, 64])
+def test_no_digest_counts(torch_cuda, er1k, slice_rows):
+    """Without the digest, counts of leaf-ended patterns come from the closed
+    form (run length minus matched vertices in the run); they must equal the
+    oracle's enumeration exactly, as must support and verdict."""
+    g = er1k
+    cands = _mining_candidates(g, 20, 1.0, 3) + sample_patterns(g, 40, seed=17, kmin=2, kmax=6)
+    c = fx.Context(device=0, slice_rows=slice_rows, no_digest=True)
+    with c.load_graph(g) as dg:
+        _say("no digest, slice rows", slice_rows, "patterns", len(cands))
+        got = dg.support_batch(cands, [20] * len(cands), [0.5] * len(cands), fx.MODE_FULL)
+        for p, r in zip(cands, got):
+            want = O.query(g, p, 20, 0.5, O.FULL)
+            for k in ("tau", "support", "frequent", "embedding_count", "count_saturated"):
+                assert r[k] == want[k], (p, k, r[k], want[k])
+            assert r["digest"] == (0, 0)
+    # tiny graphs, including labels that collide with earlier pattern vertices
+    for idx, gg, p in _tiny_cases(80, 555):
+        with c.load_graph(gg) as dg:
+            want = O.query(gg, p, 2, 1.0, O.FULL)
+            r = dg.support(p, 2, 1.0, fx.MODE_FULL)
+            for k in ("support", "embedding_count"):
+                assert r[k] == want[k], (idx, k, r[k], want[k])
+    c.close()
