@@ -120,7 +120,20 @@ def main():
                     help="also hash every embedding (FULL-mode digest); counts are exact either way")
     ap.add_argument("--plain-seconds", type=float, default=5.0,
                     help="time the one-pattern-per-call form on a prefix of the batch for this long")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="calibration only: copy a buffer of this many bytes 5 times with torch and exit "
+                         "(a plain copy kernel of known size for the PMC traffic factors)")
     args = ap.parse_args()
+
+    if args.copy_bytes > 0:
+        import torch
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_bytes} bytes 5 times")
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
