@@ -224,6 +224,44 @@ typedef struct {
 /* Copies the context's statistics into *out; reset != 0 zeroes them after. */
 fx_status fx_ctx_stats(fx_ctx *ctx, fx_stats *out, int32_t reset);
 
+/* Continuous-batching server over a resident graph.  A worker thread with its
+ * own HIP stream runs the batched engine; queries submitted from any thread
+ * join the next device step as soon as a slot and stack memory are free
+ * (admission by projected stack bytes), share every launch with the queries
+ * already running, and are answered exactly as fx_support would answer them.
+ * VERDICT queries leave as soon as their verdict is decided (Section 3.1.1).
+ *   max_active        queries in flight (0 = 4096)
+ *   slice_rows        level capacity per query (0 = the context's)
+ *   mem_budget_bytes  device memory for in-flight stacks (0 = the context's)
+ *   step_candidates   candidates per device step over all queries (0 = 2^25);
+ *                     smaller steps lower latency, larger ones raise throughput
+ *   flags             0 or FX_CTX_NO_DIGEST
+ * fx_result.device_ms of a served query is its latency: submit to result.
+ * The graph cannot be destroyed while a server uses it (FX_EBUSY). */
+typedef struct {
+    int32_t max_active;
+    int64_t slice_rows;
+    int64_t mem_budget_bytes;
+    int64_t step_candidates;
+    uint32_t flags;
+} fx_server_opts;
+
+fx_status fx_server_create(fx_graph *g, const fx_server_opts *opts, fx_server **out);
+/* Thread-safe.  Validates sigma, lambda, mode and the pattern (errors are
+ * returned here); the pattern is copied.  *ticket identifies the query. */
+fx_status fx_server_submit(fx_server *s, const fx_pattern *p, int64_t sigma, double lambda, int32_t mode,
+                           uint64_t *ticket);
+/* Thread-safe.  *done = 1 and *out filled (the ticket is then released) once
+ * the query is finished, else *done = 0.  FX_EINVAL for an unknown ticket. */
+fx_status fx_server_poll(fx_server *s, uint64_t ticket, fx_result *out, int32_t *done);
+/* Thread-safe.  Blocks until the query is finished (timeout_us < 0: no limit)
+ * and releases the ticket; FX_ETIMEOUT when the limit passes first. */
+fx_status fx_server_wait(fx_server *s, uint64_t ticket, int64_t timeout_us, fx_result *out);
+/* Engine statistics of the server (steps, syncs, queries). */
+fx_status fx_server_stats(fx_server *s, fx_stats *out);
+/* Finishes every submitted query, then stops the worker and frees the server. */
+fx_status fx_server_destroy(fx_server *s);
+
 /* Thread-local description of the last error. */
 const char *fx_last_error(void);
 

@@ -182,16 +182,12 @@ extern "C" fx_status fx_ctx_create(const fx_ctx_opts *opts, fx_ctx **out)
     fx_ctx *c = new fx_ctx();
     c->device = o.device;
     c->stream = (hipStream_t)o.hip_stream;
-    if (o.slice_rows > 0) c->slice_rows = std::min<int64_t>(std::max<int64_t>(o.slice_rows, 64), (int64_t)1 << 26);
-    if (o.count_cap > 0) c->count_cap = o.count_cap;
-    c->pool.budget = o.mem_budget_bytes > 0 ? (size_t)o.mem_budget_bytes : ((size_t)64 << 30);
-    c->timing = (o.flags & FX_CTX_KERNEL_TIMING) != 0;
-    c->no_digest = (o.flags & FX_CTX_NO_DIGEST) != 0;
-    for (auto &e : c->evk)
-        if (hipEventCreate(&e) != hipSuccess) {
-            delete c;
-            return fx_fail(FX_EDEVICE, "event creation failed");
-        }
+    if (o.slice_rows > 0)
+        c->params.slice_rows = std::min<int64_t>(std::max<int64_t>(o.slice_rows, 64), (int64_t)1 << 26);
+    if (o.count_cap > 0) c->params.count_cap = o.count_cap;
+    c->work.pool.budget = o.mem_budget_bytes > 0 ? (size_t)o.mem_budget_bytes : ((size_t)64 << 30);
+    c->params.timing = (o.flags & FX_CTX_KERNEL_TIMING) != 0;
+    c->params.no_digest = (o.flags & FX_CTX_NO_DIGEST) != 0;
     *out = c;
     return FX_OK;
 }
@@ -203,8 +199,6 @@ extern "C" fx_status fx_ctx_destroy(fx_ctx *c)
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    for (auto &e : c->evk)
-        if (e) (void)hipEventDestroy(e);
     delete c;
     return FX_OK;
 }
@@ -285,7 +279,7 @@ extern "C" fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_patter
         reqs[i].kind = mode == FX_MODE_FULL ? FX_Q_FULL : FX_Q_VERDICT;
         reqs[i].out = &res[i];
     }
-    FX_TRY(fx_engine_run(g, reqs, g->ctx->max_active));
+    FX_TRY(fx_engine_run(g, reqs, g->ctx->params.max_active));
     for (int32_t i = 0; i < npat; i++)
         if (reqs[i].status != FX_OK) return reqs[i].status;
     std::copy(res.begin(), res.end(), out);

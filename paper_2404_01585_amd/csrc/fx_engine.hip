@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <memory>
 #include <numeric>
 
 #include "fx_host.h"
@@ -149,14 +150,17 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
 namespace {
 
 constexpr uint32_t kLastSpanMin = 1024;
-constexpr uint32_t kLastSpanInit = 4096;
 constexpr uint64_t kCountSpan = 1ull << 22;  // last-vertex candidates per counting step
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 enum { PH_SUPPORT = 0, PH_COUNT = 1, PH_LIST = 2 };
 
-struct Query {
+bool wants_selection(const FxRequest &r) { return r.kind == FX_Q_FULL && r.selected && r.selected_cap > 0; }
+
+}  // namespace
+
+struct FxQuery {
     FxRequest *req = nullptr;
     HostPlan hp;
     int n = 0;
@@ -174,18 +178,18 @@ struct Query {
     uint64_t T[FX_MAXN + 1]{}, cur[FX_MAXN + 1]{};
     int64_t nparts[FX_MAXN + 1]{};
     int64_t rank_base = 0;
-    uint32_t last_span = kLastSpanInit;
+    uint32_t last_span = 0;
     int32_t steps = 0;
     int64_t listed = 0;
-    // the segment of the current step
+    // the segment of the current step (-1: none)
     int seg_l = -1, seg_kind = 0;
     uint64_t seg_t0 = 0;
     uint32_t seg_span = 0;
 };
 
-bool wants_selection(const FxRequest &r) { return r.kind == FX_Q_FULL && r.selected && r.selected_cap > 0; }
+namespace {
 
-size_t region_size(const Query &q, int64_t nv)
+size_t region_size(const FxQuery &q, int64_t nv)
 {
     const int n = q.n;
     const size_t C = (size_t)q.cap;
@@ -202,7 +206,7 @@ size_t region_size(const Query &q, int64_t nv)
     return b;
 }
 
-void carve(Query &q, int64_t nv)
+void carve(FxQuery &q, int64_t nv)
 {
     char *p = (char *)q.region;
     auto take = [&](size_t bytes) {
@@ -237,14 +241,14 @@ void carve(Query &q, int64_t nv)
     }
 }
 
-int deepest_open_level(const Query &q)
+int deepest_open_level(const FxQuery &q)
 {
     for (int l = q.n - 1; l >= 0; l--)
         if (q.cur[l] < q.T[l]) return l;
     return -1;
 }
 
-void restart_stack(Query &q, const fx_graph *G)
+void restart_stack(FxQuery &q, const fx_graph *G)
 {
     const uint32_t vl0 = q.hp.plan.vl[0];
     for (int l = 0; l <= q.n; l++) q.T[l] = q.cur[l] = 0, q.nparts[l] = 0;
@@ -252,324 +256,360 @@ void restart_stack(Query &q, const fx_graph *G)
     q.nparts[0] = 1;
 }
 
-fx_result base_result(const Query &q)
+}  // namespace
+
+EngineWork::~EngineWork()
 {
-    fx_result r{};
-    r.tau = q.tau;
-    return r;
+    for (auto &e : evk)
+        if (e) (void)hipEventDestroy(e);
 }
 
-}  // namespace
+fx_status EngineWork::init_events()
+{
+    for (auto &e : evk)
+        if (!e) FX_HIP(hipEventCreate(&e));
+    return FX_OK;
+}
+
+FxEngine::FxEngine(fx_graph *G, EngineWork *W, hipStream_t s, const EngineParams &p, fx_stats *stats)
+    : G_(G), W_(W), s_(s), P_(p), stats_(stats), t0_(std::chrono::steady_clock::now())
+{
+    if (P_.max_active < 1) P_.max_active = 1;
+    for (int k = P_.max_active - 1; k >= 0; k--) free_slots_.push_back(k);
+}
+
+FxEngine::~FxEngine() = default;
+
+bool FxEngine::idle() const { return pending_.empty() && active_.empty(); }
+
+void FxEngine::done(FxRequest *r)
+{
+    if (on_done) on_done(r);
+}
+
+void FxEngine::add(FxRequest *r)
+{
+    auto q = std::make_unique<FxQuery>();
+    q->req = r;
+    r->status = fx_build_plan(G_, r->pattern, q->hp);
+    if (r->status != FX_OK) return done(r);
+    q->n = r->pattern->n;
+    if (r->kind != FX_Q_LIST) {
+        r->status = fx_tau_checked(r->sigma, r->lambda, q->n, &q->tau);
+        if (r->status != FX_OK) return done(r);
+        q->tau_eff = std::max<int64_t>(q->tau, 1);
+    }
+    fx_result res{};
+    res.tau = q->tau;
+    if (q->hp.empty) {  // some label never occurs: M is empty
+        if (r->kind == FX_Q_LIST) {
+            *r->list_count = 0;
+        } else {
+            res.support = r->kind == FX_Q_VERDICT ? -1 : 0;
+            res.embedding_count = r->kind == FX_Q_VERDICT ? -1 : 0;
+            *r->out = res;
+        }
+        return done(r);
+    }
+    if (r->kind == FX_Q_VERDICT && q->hp.upper_bound < q->tau_eff) {  // support can never reach tau
+        res.support = -1;
+        res.embedding_count = -1;
+        *r->out = res;
+        return done(r);
+    }
+    q->phase = r->kind == FX_Q_LIST ? PH_LIST : PH_SUPPORT;
+    q->cap = P_.slice_rows;
+    q->last_span = (uint32_t)std::min<int64_t>(P_.last_span_init, q->cap);
+    pending_.push_back(std::move(q));
+}
+
+fx_status FxEngine::finish(FxQuery &q)
+{
+    FxRequest &r = *q.req;
+    const FxSummary &S = W_->sums_h.as<FxSummary>()[q.slot];
+    if (q.phase == PH_LIST) {
+        *r.list_count = (int64_t)S.count;
+    } else {
+        fx_result res{};
+        res.tau = q.tau;
+        res.steps = q.steps;
+        res.rounds = (int32_t)S.rounds;
+        res.alg_bytes = S.alg_probe + S.alg_scatter;
+        res.device_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0_).count();
+        if (r.kind == FX_Q_VERDICT) {
+            res.frequent = (int64_t)S.support >= q.tau_eff;
+            res.support = res.frequent ? q.tau : -1;
+            res.embedding_count = -1;
+        } else {
+            res.support = (int64_t)S.support;
+            res.frequent = res.support >= q.tau_eff;
+            const bool sat = (int64_t)S.count >= P_.count_cap;
+            res.count_saturated = sat;
+            res.embedding_count = sat ? P_.count_cap : (int64_t)S.count;
+            if (!sat && !P_.no_digest) {
+                res.digest[0] = S.digest0;
+                res.digest[1] = S.digest1;
+            }
+            if (wants_selection(r) && S.support > 0) {
+                const int64_t k = (int64_t)S.support;
+                std::vector<int32_t> rows((size_t)k * q.n);
+                std::vector<int64_t> rank(k);
+                FX_HIP(hipMemcpyAsync(rows.data(), q.sel_rows, rows.size() * 4, hipMemcpyDeviceToHost, s_));
+                FX_HIP(hipMemcpyAsync(rank.data(), q.sel_rank, rank.size() * 8, hipMemcpyDeviceToHost, s_));
+                FX_HIP(hipStreamSynchronize(s_));
+                std::vector<int64_t> idx(k);
+                std::iota(idx.begin(), idx.end(), 0);
+                std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return rank[a] < rank[b]; });
+                const int64_t w = std::min<int64_t>(k, r.selected_cap);
+                for (int64_t i = 0; i < w; i++)
+                    memcpy(r.selected + i * q.n, rows.data() + idx[i] * q.n, (size_t)q.n * 4);
+            }
+        }
+        *r.out = res;
+    }
+    stats_->probe_alg_bytes += S.alg_probe;
+    stats_->scatter_alg_bytes += S.alg_scatter;
+    stats_->queries++;
+    W_->pool.give(q.region, q.region_bytes);
+    q.region = nullptr;
+    free_slots_.push_back(q.slot);
+    q.slot = -1;
+    done(&r);
+    return FX_OK;
+}
+
+// Admission: as many pending queries as slots and memory allow.
+fx_status FxEngine::admit()
+{
+    const int64_t nv = G_->nv;
+    const uint64_t u_words = ((uint64_t)nv + 31) / 32;
+    FxInit *inits = W_->inits_h.as<FxInit>();
+    FxSummary *sums_d = W_->sums_d.as<FxSummary>();
+    int ninit = 0;
+    while (!pending_.empty() && !free_slots_.empty()) {
+        FxQuery &q = *pending_.front();
+        const size_t bytes = region_size(q, nv);
+        fx_status st = W_->pool.take(bytes, &q.region);
+        if (st != FX_OK) {
+            if (!active_.empty() || ninit > 0) break;  // wait until running queries free their regions
+            q.req->status = st;                       // it cannot fit even alone
+            FxRequest *r = q.req;
+            pending_.pop_front();
+            done(r);
+            continue;
+        }
+        q.region_bytes = bytes;
+        carve(q, nv);
+        q.slot = free_slots_.back();
+        free_slots_.pop_back();
+        FxInit &I = inits[ninit++];
+        I.plan = q.hp.plan;
+        I.plan_dst = q.plan;
+        I.lev0 = q.lev[0];
+        I.U = q.U;
+        I.sum = sums_d + q.slot;
+        I.u_words = u_words;
+        I.clear_u = 1;
+        I.clear_sum = 1;
+        restart_stack(q, G_);
+        active_.push_back(std::move(pending_.front()));
+        pending_.pop_front();
+    }
+    if (ninit) {
+        FX_HIP(hipMemcpyAsync(W_->inits_d.p, inits, (size_t)ninit * sizeof(FxInit), hipMemcpyHostToDevice, s_));
+        FX_HIP(fx_launch_init(s_, G_->dev, W_->inits_d.as<FxInit>(), ninit));
+    }
+    return FX_OK;
+}
+
+fx_status FxEngine::step()
+{
+    if (!buffers_ready_) {
+        const int32_t A = P_.max_active;
+        const uint64_t max_blocks = (P_.step_candidates + FX_TILE - 1) / FX_TILE + (uint64_t)A;
+        FX_TRY(W_->flag.ensure(max_blocks * FX_TILE));
+        FX_TRY(W_->bcnt.ensure(max_blocks * 4));
+        FX_TRY(W_->boff.ensure((max_blocks + 1) * 8));
+        FX_TRY(W_->lsum.ensure(max_blocks * 8));
+        FX_TRY(W_->loff.ensure((max_blocks + 1) * 8));
+        FX_TRY(W_->segs_d.ensure((size_t)A * sizeof(FxSeg)));
+        FX_TRY(W_->segs_h.ensure((size_t)A * sizeof(FxSeg)));
+        FX_TRY(W_->blk0_d.ensure(((size_t)A + 1) * 4));
+        FX_TRY(W_->blk0_h.ensure(((size_t)A + 1) * 4));
+        FX_TRY(W_->inits_d.ensure((size_t)A * sizeof(FxInit)));
+        FX_TRY(W_->inits_h.ensure((size_t)A * sizeof(FxInit)));
+        FX_TRY(W_->sums_d.ensure((size_t)A * sizeof(FxSummary)));
+        FX_TRY(W_->sums_h.ensure((size_t)A * sizeof(FxSummary)));
+        FX_TRY(W_->init_events());
+        buffers_ready_ = true;
+    }
+    FX_TRY(admit());
+    if (active_.empty()) return FX_OK;
+
+    // ---- one segment per active query, within the step's candidate budget
+    FxSeg *segs = W_->segs_h.as<FxSeg>();
+    uint32_t *blk0 = W_->blk0_h.as<uint32_t>();
+    FxSummary *sums_d = W_->sums_d.as<FxSummary>();
+    FxSummary *sums_h = W_->sums_h.as<FxSummary>();
+    int nsegs = 0;
+    uint64_t budget = P_.step_candidates;
+    uint32_t nblocks = 0;
+    int any_inner = 0, any_greedy = 0, any_write = 0;
+    const size_t A = active_.size();
+    for (auto &qp : active_) qp->seg_l = -1;
+    for (size_t k = 0; k < A && budget > 0; k++) {
+        FxQuery &q = *active_[(rot_ + k) % A];
+        const int l = deepest_open_level(q);
+        if (l < 0) continue;
+        const bool last = (l == q.n - 1);
+        int kind, flags = 0;
+        uint64_t cap;
+        if (q.phase == PH_SUPPORT) {
+            flags = FX_PROBE_UFILTER;
+            kind = last ? FX_SEG_GREEDY : FX_SEG_INNER;
+            cap = last ? std::min<uint64_t>(q.last_span, (uint64_t)q.cap) : (uint64_t)q.cap;
+        } else if (q.phase == PH_COUNT) {
+            // without a digest, a leaf last vertex is counted in closed form
+            // from the partials of vertex n-2 (level n-1 is never built)
+            const bool leaf = P_.no_digest && q.n >= 2 && q.hp.plan.nback[q.n - 1] == 1;
+            const bool end = leaf ? (l == q.n - 2) : last;
+            flags = end ? (leaf ? FX_PROBE_LEAF : (FX_PROBE_COUNT | (P_.no_digest ? 0 : FX_PROBE_HASH))) : 0;
+            kind = end ? FX_SEG_COUNT : FX_SEG_INNER;
+            cap = end ? kCountSpan : (uint64_t)q.cap;
+        } else {
+            flags = last ? FX_PROBE_COUNT : 0;
+            kind = last ? FX_SEG_LIST : FX_SEG_INNER;
+            cap = (uint64_t)q.cap;
+        }
+        const uint64_t span = std::min<uint64_t>(std::min<uint64_t>(q.T[l] - q.cur[l], cap), budget);
+        if (span == 0) continue;
+        // every passing candidate of a writing segment takes one row of level l+1
+        if (kind != FX_SEG_COUNT && span > (uint64_t)q.cap)
+            return fx_fail(FX_EDEVICE, "internal: slice of %llu candidates exceeds the level capacity %lld",
+                           (unsigned long long)span, (long long)q.cap);
+        FxSeg &S = segs[nsegs];
+        S.in = q.lev[l];
+        S.out = q.lev[l + 1];
+        S.plan = q.plan;
+        S.U = q.U;
+        S.sum = sums_d + q.slot;
+        S.sel_rows = q.sel_rows;
+        S.sel_rank = q.sel_rank;
+        S.nparts = q.nparts[l];
+        S.t0 = q.cur[l];
+        S.rank_base = q.rank_base;
+        S.span = (uint32_t)span;
+        S.blk0 = nblocks;
+        S.n = q.n;
+        S.l = l;
+        S.flags = flags;
+        S.kind = kind;
+        blk0[nsegs] = nblocks;
+        nblocks += (uint32_t)((span + FX_TILE - 1) / FX_TILE);
+        budget -= span;
+        q.seg_l = l;
+        q.seg_kind = kind;
+        q.seg_t0 = q.cur[l];
+        q.seg_span = (uint32_t)span;
+        any_inner |= kind == FX_SEG_INNER;
+        any_greedy |= kind == FX_SEG_GREEDY;
+        any_write |= kind != FX_SEG_COUNT;
+        nsegs++;
+    }
+    rot_++;
+    if (nsegs == 0) return fx_fail(FX_EDEVICE, "engine stalled with %zu active queries", active_.size());
+    blk0[nsegs] = nblocks;
+    FX_HIP(hipMemcpyAsync(W_->segs_d.p, segs, (size_t)nsegs * sizeof(FxSeg), hipMemcpyHostToDevice, s_));
+    FX_HIP(hipMemcpyAsync(W_->blk0_d.p, blk0, ((size_t)nsegs + 1) * 4, hipMemcpyHostToDevice, s_));
+    hipEvent_t *ev = P_.timing ? W_->evk : nullptr;
+    FX_HIP(fx_launch_step(s_, G_->dev, W_->segs_d.as<FxSeg>(), W_->blk0_d.as<uint32_t>(), nsegs, nblocks,
+                          W_->flag.as<uint8_t>(), W_->bcnt.as<uint32_t>(), W_->boff.as<uint64_t>(),
+                          W_->lsum.as<uint64_t>(), W_->loff.as<uint64_t>(), ev ? ev[0] : nullptr,
+                          ev ? ev[1] : nullptr, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
+                          ev ? ev[5] : nullptr, any_inner, any_greedy, any_write));
+    int hi = 0;
+    for (auto &qp : active_) hi = std::max(hi, qp->slot + 1);
+    FX_HIP(hipMemcpyAsync(sums_h, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, s_));
+    FX_HIP(hipStreamSynchronize(s_));
+    stats_->steps++;
+    stats_->syncs++;
+    stats_->probe_launches++;
+    stats_->scatter_launches++;
+    if (any_greedy) stats_->greedy_launches++;
+    if (ev) {
+        float ms = 0;
+        FX_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        stats_->probe_ms += ms;
+        FX_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+        stats_->scatter_ms += ms;
+        FX_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
+        stats_->greedy_ms += ms;
+    }
+
+    // ---- advance every query that took part
+    for (auto &qp : active_) {
+        FxQuery &q = *qp;
+        if (q.seg_l < 0) continue;
+        const FxSummary &S = sums_h[q.slot];
+        if (S.error) return fx_fail(FX_EDEVICE, "device consistency check failed (greedy round limit)");
+        const int l = q.seg_l;
+        q.cur[l] = q.seg_t0 + q.seg_span;
+        q.steps++;
+        const uint64_t N = S.total_out;
+        if (q.seg_kind == FX_SEG_INNER) {
+            q.nparts[l + 1] = (int64_t)N;
+            q.T[l + 1] = S.t_next;
+            q.cur[l + 1] = 0;
+        } else if (q.seg_kind == FX_SEG_GREEDY) {
+            q.rank_base += (int64_t)N;
+            // keep the greedy's slices near a few thousand embeddings
+            if (N * 8 < q.seg_span) q.last_span = (uint32_t)std::min<int64_t>(2 * (int64_t)q.last_span, q.cap);
+            else if (N > 8192) q.last_span = std::max<uint32_t>(q.last_span / 2, kLastSpanMin);
+            q.last_span = (uint32_t)std::min<int64_t>(q.last_span, q.cap);
+        } else if (q.seg_kind == FX_SEG_LIST) {
+            FxRequest &r = *q.req;
+            const int64_t take = std::min<int64_t>((int64_t)N, std::max<int64_t>(0, r.list_cap - q.listed));
+            if (take > 0) {
+                FX_HIP(hipMemcpyAsync(r.list_rows + q.listed * q.n, q.lev[q.n].rows, (size_t)take * q.n * 4,
+                                      hipMemcpyDeviceToHost, s_));
+                FX_HIP(hipStreamSynchronize(s_));
+            }
+            q.listed += (int64_t)N;
+        }
+    }
+    // ---- retire finished queries, move FULL queries to their counting phase
+    for (size_t k = 0; k < active_.size();) {
+        FxQuery &q = *active_[k];
+        const FxSummary &S = sums_h[q.slot];
+        bool fin = false;
+        if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_VERDICT && (int64_t)S.support >= q.tau_eff) fin = true;
+        if (q.phase == PH_COUNT && (int64_t)S.count >= P_.count_cap) fin = true;
+        if (!fin && deepest_open_level(q) < 0) {
+            if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_FULL) {
+                q.phase = PH_COUNT;  // level 0 is unchanged; restart the cursors
+                restart_stack(q, G_);
+            } else {
+                fin = true;
+            }
+        }
+        if (fin) {
+            FX_TRY(finish(q));
+            active_[k] = std::move(active_.back());
+            active_.pop_back();
+        } else {
+            k++;
+        }
+    }
+    return FX_OK;
+}
 
 fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active)
 {
     fx_ctx *c = G->ctx;
-    hipStream_t s = c->stream;
-    const int64_t nv = G->nv;
-    if (max_active < 1) max_active = 1;
-
-    std::vector<Query> qs;
-    qs.reserve(reqs.size());
-    std::deque<int> pending;
-    for (auto &r : reqs) {
-        Query q;
-        q.req = &r;
-        r.status = fx_build_plan(G, r.pattern, q.hp);
-        if (r.status != FX_OK) continue;
-        q.n = r.pattern->n;
-        if (r.kind != FX_Q_LIST) {
-            r.status = fx_tau_checked(r.sigma, r.lambda, q.n, &q.tau);
-            if (r.status != FX_OK) continue;
-            q.tau_eff = std::max<int64_t>(q.tau, 1);
-        }
-        if (q.hp.empty) {  // some label never occurs: M is empty
-            if (r.kind == FX_Q_LIST) {
-                *r.list_count = 0;
-            } else {
-                fx_result res = base_result(q);
-                res.support = r.kind == FX_Q_VERDICT ? -1 : 0;
-                res.embedding_count = r.kind == FX_Q_VERDICT ? -1 : 0;
-                *r.out = res;
-            }
-            continue;
-        }
-        if (r.kind == FX_Q_VERDICT && q.hp.upper_bound < q.tau_eff) {  // support can never reach tau
-            fx_result res = base_result(q);
-            res.support = -1;
-            res.embedding_count = -1;
-            *r.out = res;
-            continue;
-        }
-        q.phase = r.kind == FX_Q_LIST ? PH_LIST : PH_SUPPORT;
-        q.cap = c->slice_rows;
-        q.last_span = (uint32_t)std::min<int64_t>(kLastSpanInit, q.cap);
-        qs.push_back(q);
-        pending.push_back((int)qs.size() - 1);
-    }
-    if (qs.empty()) return FX_OK;
-    max_active = std::min<int32_t>(max_active, (int32_t)qs.size());
-
-    // step buffers
-    const uint64_t max_blocks = (c->step_candidates + FX_TILE - 1) / FX_TILE + (uint64_t)max_active;
-    FX_TRY(c->flag.ensure(max_blocks * FX_TILE));
-    FX_TRY(c->bcnt.ensure(max_blocks * 4));
-    FX_TRY(c->boff.ensure((max_blocks + 1) * 8));
-    FX_TRY(c->lsum.ensure(max_blocks * 8));
-    FX_TRY(c->loff.ensure((max_blocks + 1) * 8));
-    FX_TRY(c->segs_d.ensure((size_t)max_active * sizeof(FxSeg)));
-    FX_TRY(c->segs_h.ensure((size_t)max_active * sizeof(FxSeg)));
-    FX_TRY(c->blk0_d.ensure(((size_t)max_active + 1) * 4));
-    FX_TRY(c->blk0_h.ensure(((size_t)max_active + 1) * 4));
-    FX_TRY(c->inits_d.ensure((size_t)max_active * sizeof(FxInit)));
-    FX_TRY(c->inits_h.ensure((size_t)max_active * sizeof(FxInit)));
-    FX_TRY(c->sums_d.ensure((size_t)max_active * sizeof(FxSummary)));
-    FX_TRY(c->sums_h.ensure((size_t)max_active * sizeof(FxSummary)));
-    FxSummary *sums_d = c->sums_d.as<FxSummary>();
-    FxSummary *sums_h = c->sums_h.as<FxSummary>();
-
-    const auto t_start = std::chrono::steady_clock::now();
-    std::vector<int> active;
-    std::vector<int> free_slots;
-    for (int k = max_active - 1; k >= 0; k--) free_slots.push_back(k);
-    size_t rot = 0;
-    const uint64_t u_words = ((uint64_t)nv + 31) / 32;
-
-    auto finish = [&](Query &q) -> fx_status {
-        FxRequest &r = *q.req;
-        const FxSummary &S = sums_h[q.slot];
-        if (q.phase == PH_LIST) {
-            *r.list_count = (int64_t)S.count;
-        } else {
-            fx_result res = base_result(q);
-            res.steps = q.steps;
-            res.device_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-            res.rounds = (int32_t)S.rounds;
-            res.alg_bytes = S.alg_probe + S.alg_scatter;
-            if (r.kind == FX_Q_VERDICT) {
-                res.frequent = (int64_t)S.support >= q.tau_eff;
-                res.support = res.frequent ? q.tau : -1;
-                res.embedding_count = -1;
-            } else {
-                res.support = (int64_t)S.support;
-                res.frequent = res.support >= q.tau_eff;
-                const bool sat = (int64_t)S.count >= c->count_cap;
-                res.count_saturated = sat;
-                res.embedding_count = sat ? c->count_cap : (int64_t)S.count;
-                if (!sat && !c->no_digest) {
-                    res.digest[0] = S.digest0;
-                    res.digest[1] = S.digest1;
-                }
-                if (wants_selection(r) && S.support > 0) {
-                    const int64_t k = (int64_t)S.support;
-                    std::vector<int32_t> rows((size_t)k * q.n);
-                    std::vector<int64_t> rank(k);
-                    FX_HIP(hipMemcpy(rows.data(), q.sel_rows, rows.size() * 4, hipMemcpyDeviceToHost));
-                    FX_HIP(hipMemcpy(rank.data(), q.sel_rank, rank.size() * 8, hipMemcpyDeviceToHost));
-                    std::vector<int64_t> idx(k);
-                    std::iota(idx.begin(), idx.end(), 0);
-                    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return rank[a] < rank[b]; });
-                    const int64_t w = std::min<int64_t>(k, r.selected_cap);
-                    for (int64_t i = 0; i < w; i++)
-                        memcpy(r.selected + i * q.n, rows.data() + idx[i] * q.n, (size_t)q.n * 4);
-                }
-            }
-            *r.out = res;
-        }
-        c->stats.probe_alg_bytes += S.alg_probe;
-        c->stats.scatter_alg_bytes += S.alg_scatter;
-        c->stats.queries++;
-        c->pool.give(q.region, q.region_bytes);
-        q.region = nullptr;
-        free_slots.push_back(q.slot);
-        q.slot = -1;
-        return FX_OK;
-    };
-
-    while (!pending.empty() || !active.empty()) {
-        // ---- admission: as many pending queries as slots and memory allow
-        int ninit = 0;
-        FxInit *inits = c->inits_h.as<FxInit>();
-        while (!pending.empty() && !free_slots.empty()) {
-            Query &q = qs[pending.front()];
-            const size_t bytes = region_size(q, nv);
-            fx_status st = c->pool.take(bytes, &q.region);
-            if (st != FX_OK) {
-                if (!active.empty()) break;  // wait until running queries free their regions
-                return st;
-            }
-            q.region_bytes = bytes;
-            carve(q, nv);
-            q.slot = free_slots.back();
-            free_slots.pop_back();
-            FxInit &I = inits[ninit++];
-            I.plan = q.hp.plan;
-            I.plan_dst = q.plan;
-            I.lev0 = q.lev[0];
-            I.U = q.U;
-            I.sum = sums_d + q.slot;
-            I.u_words = u_words;
-            I.clear_u = 1;
-            I.clear_sum = 1;
-            restart_stack(q, G);
-            active.push_back(pending.front());
-            pending.pop_front();
-        }
-        if (ninit) {
-            FX_HIP(hipMemcpyAsync(c->inits_d.p, inits, (size_t)ninit * sizeof(FxInit), hipMemcpyHostToDevice, s));
-            FX_HIP(fx_launch_init(s, G->dev, c->inits_d.as<FxInit>(), ninit));
-        }
-
-        // ---- one segment per active query, within the step's candidate budget
-        FxSeg *segs = c->segs_h.as<FxSeg>();
-        uint32_t *blk0 = c->blk0_h.as<uint32_t>();
-        int nsegs = 0;
-        uint64_t budget = c->step_candidates;
-        uint32_t nblocks = 0;
-        int any_inner = 0, any_greedy = 0, any_write = 0;
-        std::vector<int> segq;
-        const size_t A = active.size();
-        for (size_t k = 0; k < A && budget > 0; k++) {
-            Query &q = qs[active[(rot + k) % A]];
-            const int l = deepest_open_level(q);
-            if (l < 0) continue;
-            const bool last = (l == q.n - 1);
-            int kind, flags = 0;
-            uint64_t cap;
-            if (q.phase == PH_SUPPORT) {
-                flags = FX_PROBE_UFILTER;
-                kind = last ? FX_SEG_GREEDY : FX_SEG_INNER;
-                cap = last ? std::min<uint64_t>(q.last_span, (uint64_t)q.cap) : (uint64_t)q.cap;
-            } else if (q.phase == PH_COUNT) {
-                // without a digest, a leaf last vertex is counted in closed form
-                // from the partials of vertex n-2 (level n-1 is never built)
-                const bool leaf = c->no_digest && q.n >= 2 && q.hp.plan.nback[q.n - 1] == 1;
-                const bool end = leaf ? (l == q.n - 2) : last;
-                flags = end ? (leaf ? FX_PROBE_LEAF : (FX_PROBE_COUNT | (c->no_digest ? 0 : FX_PROBE_HASH))) : 0;
-                kind = end ? FX_SEG_COUNT : FX_SEG_INNER;
-                cap = end ? kCountSpan : (uint64_t)q.cap;
-            } else {
-                flags = last ? FX_PROBE_COUNT : 0;
-                kind = last ? FX_SEG_LIST : FX_SEG_INNER;
-                cap = (uint64_t)q.cap;
-            }
-            const uint64_t span = std::min<uint64_t>(std::min<uint64_t>(q.T[l] - q.cur[l], cap), budget);
-            if (span == 0) continue;
-            // every passing candidate of a writing segment takes one row of level l+1
-            if (kind != FX_SEG_COUNT && span > (uint64_t)q.cap)
-                return fx_fail(FX_EDEVICE, "internal: slice of %llu candidates exceeds the level capacity %lld",
-                               (unsigned long long)span, (long long)q.cap);
-            FxSeg &S = segs[nsegs];
-            S.in = q.lev[l];
-            S.out = q.lev[l + 1];
-            S.plan = q.plan;
-            S.U = q.U;
-            S.sum = sums_d + q.slot;
-            S.sel_rows = q.sel_rows;
-            S.sel_rank = q.sel_rank;
-            S.nparts = q.nparts[l];
-            S.t0 = q.cur[l];
-            S.rank_base = q.rank_base;
-            S.span = (uint32_t)span;
-            S.blk0 = nblocks;
-            S.n = q.n;
-            S.l = l;
-            S.flags = flags;
-            S.kind = kind;
-            blk0[nsegs] = nblocks;
-            nblocks += (uint32_t)((span + FX_TILE - 1) / FX_TILE);
-            budget -= span;
-            q.seg_l = l;
-            q.seg_kind = kind;
-            q.seg_t0 = q.cur[l];
-            q.seg_span = (uint32_t)span;
-            any_inner |= kind == FX_SEG_INNER;
-            any_greedy |= kind == FX_SEG_GREEDY;
-            any_write |= kind != FX_SEG_COUNT;
-            segq.push_back(active[(rot + k) % A]);
-            nsegs++;
-        }
-        rot++;
-        if (nsegs == 0) return fx_fail(FX_EDEVICE, "engine stalled with %zu active queries", active.size());
-        blk0[nsegs] = nblocks;
-        FX_HIP(hipMemcpyAsync(c->segs_d.p, segs, (size_t)nsegs * sizeof(FxSeg), hipMemcpyHostToDevice, s));
-        FX_HIP(hipMemcpyAsync(c->blk0_d.p, blk0, ((size_t)nsegs + 1) * 4, hipMemcpyHostToDevice, s));
-        hipEvent_t *ev = c->timing ? c->evk : nullptr;
-        FX_HIP(fx_launch_step(s, G->dev, c->segs_d.as<FxSeg>(), c->blk0_d.as<uint32_t>(), nsegs, nblocks,
-                              c->flag.as<uint8_t>(), c->bcnt.as<uint32_t>(), c->boff.as<uint64_t>(),
-                              c->lsum.as<uint64_t>(), c->loff.as<uint64_t>(),
-                              ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, ev ? ev[2] : nullptr,
-                              ev ? ev[3] : nullptr, ev ? ev[4] : nullptr, ev ? ev[5] : nullptr, any_inner,
-                              any_greedy, any_write));
-        int hi = 0;
-        for (int qi : active) hi = std::max(hi, qs[qi].slot + 1);
-        FX_HIP(hipMemcpyAsync(sums_h, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, s));
-        FX_HIP(hipStreamSynchronize(s));
-        c->stats.steps++;
-        c->stats.syncs++;
-        c->stats.probe_launches++;
-        c->stats.scatter_launches++;
-        if (any_greedy) c->stats.greedy_launches++;
-        if (c->timing) {
-            float ms = 0;
-            FX_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-            c->stats.probe_ms += ms;
-            FX_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
-            c->stats.scatter_ms += ms;
-            FX_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
-            c->stats.greedy_ms += ms;
-        }
-
-        // ---- advance every query that took part
-        for (int qi : segq) {
-            Query &q = qs[qi];
-            const FxSummary &S = sums_h[q.slot];
-            if (S.error) return fx_fail(FX_EDEVICE, "device consistency check failed (greedy round limit)");
-            const int l = q.seg_l;
-            q.cur[l] = q.seg_t0 + q.seg_span;
-            q.steps++;
-            const uint64_t N = S.total_out;
-            if (q.seg_kind == FX_SEG_INNER) {
-                q.nparts[l + 1] = (int64_t)N;
-                q.T[l + 1] = S.t_next;
-                q.cur[l + 1] = 0;
-            } else if (q.seg_kind == FX_SEG_GREEDY) {
-                q.rank_base += (int64_t)N;
-                // keep the greedy's slices near a few thousand embeddings
-                if (N * 8 < q.seg_span) q.last_span = (uint32_t)std::min<int64_t>(2 * (int64_t)q.last_span, q.cap);
-                else if (N > 8192) q.last_span = std::max<uint32_t>(q.last_span / 2, kLastSpanMin);
-                q.last_span = (uint32_t)std::min<int64_t>(q.last_span, q.cap);
-            } else if (q.seg_kind == FX_SEG_LIST) {
-                FxRequest &r = *q.req;
-                const int64_t take = std::min<int64_t>((int64_t)N, std::max<int64_t>(0, r.list_cap - q.listed));
-                if (take > 0)
-                    FX_HIP(hipMemcpy(r.list_rows + q.listed * q.n, q.lev[q.n].rows, (size_t)take * q.n * 4,
-                                     hipMemcpyDeviceToHost));
-                q.listed += (int64_t)N;
-            }
-        }
-        // ---- retire finished queries, move FULL queries to their counting phase
-        for (size_t k = 0; k < active.size();) {
-            Query &q = qs[active[k]];
-            const FxSummary &S = sums_h[q.slot];
-            bool done = false;
-            if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_VERDICT && (int64_t)S.support >= q.tau_eff) done = true;
-            if (q.phase == PH_COUNT && (int64_t)S.count >= c->count_cap) done = true;
-            if (!done && deepest_open_level(q) < 0) {
-                if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_FULL) {
-                    q.phase = PH_COUNT;  // level 0 is unchanged; restart the cursors
-                    restart_stack(q, G);
-                } else {
-                    done = true;
-                }
-            }
-            if (done) {
-                FX_TRY(finish(q));
-                active[k] = active.back();
-                active.pop_back();
-            } else {
-                k++;
-            }
-        }
-    }
+    EngineParams p = c->params;
+    p.max_active = std::max<int32_t>(1, std::min<int32_t>(max_active, (int32_t)std::max<size_t>(reqs.size(), 1)));
+    FxEngine eng(G, &c->work, c->stream, p, &c->stats);
+    for (auto &r : reqs) eng.add(&r);
+    while (!eng.idle()) FX_TRY(eng.step());
     return FX_OK;
 }

@@ -205,6 +205,7 @@ extern "C" fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *d, fx_graph
 extern "C" fx_status fx_graph_destroy(fx_graph *g)
 {
     if (!g) return fx_fail(FX_EINVAL, "graph is NULL");
+    if (g->servers.load() != 0) return fx_fail(FX_EBUSY, "%d server(s) still use the graph", g->servers.load());
     (void)hipSetDevice(g->ctx->device);
     g->ctx->graphs--;
     delete g;

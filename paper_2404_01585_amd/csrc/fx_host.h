@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
+#include <memory>
 #include <cstdarg>
 #include <cstdint>
 #include <deque>
@@ -77,26 +79,39 @@ struct RegionPool {
     void give(void *p, size_t bytes);
 };
 
-struct fx_ctx {
-    int32_t device = 0;
-    hipStream_t stream = nullptr;
-    int64_t slice_rows = 1 << 17;         // level capacity of one query's stack
+// Tunables of an engine.
+struct EngineParams {
+    int64_t slice_rows = 1 << 17;          // level capacity of one query's stack
     int64_t count_cap = (int64_t)1 << 62;
-    uint64_t step_candidates = 1ull << 25; // flattened candidates per step, all queries together
-    int32_t max_active = 4096;            // queries in flight in a batch
-    std::atomic<int> graphs{0};
+    uint64_t step_candidates = 1ull << 25;  // flattened candidates per step, all queries together
+    int32_t max_active = 4096;             // queries in flight
+    uint32_t last_span_init = 4096;        // first last-vertex slice of the support phase
     bool timing = false;
     bool no_digest = false;
-    fx_stats stats{};
+};
 
+// Device and pinned buffers of one engine (a context's, or a server's).
+struct EngineWork {
     RegionPool pool;
     DevBuf flag, bcnt, boff, lsum, loff, segs_d, blk0_d, inits_d, sums_d;
     HostBuf segs_h, blk0_h, inits_h, sums_h;
     hipEvent_t evk[6] = {};
+    ~EngineWork();
+    fx_status init_events();
+};
+
+struct fx_ctx {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    EngineParams params;
+    std::atomic<int> graphs{0};
+    fx_stats stats{};
+    EngineWork work;
 };
 
 struct fx_graph {
     fx_ctx *ctx = nullptr;
+    std::atomic<int> servers{0};
     int64_t nv = 0, nadj = 0;
     std::vector<int32_t> vl_values, el_values;  // dense id -> caller's label
     std::unordered_map<int32_t, uint32_t> vl_map, el_map;
@@ -121,6 +136,7 @@ enum FxQueryKind { FX_Q_FULL = 0, FX_Q_VERDICT = 1, FX_Q_LIST = 2 };
 
 struct FxRequest {
     const fx_pattern *pattern = nullptr;
+    void *user = nullptr;                // owner's tag (the server's ticket)
     int64_t sigma = 1;
     double lambda = 1.0;
     int32_t kind = FX_Q_FULL;
@@ -133,7 +149,43 @@ struct FxRequest {
     fx_status status = FX_OK;            // per-request validation status
 };
 
+struct FxQuery;
+
+// The multi-query engine: requests are added at any time; each step() admits
+// pending requests while slots and memory allow, runs one device step for all
+// active ones and reports finished requests through on_done.
+class FxEngine {
+public:
+    FxEngine(fx_graph *G, EngineWork *W, hipStream_t s, const EngineParams &p, fx_stats *stats);
+    ~FxEngine();
+    FxEngine(const FxEngine &) = delete;
+    FxEngine &operator=(const FxEngine &) = delete;
+    // Validates and plans r.  Requests that are decided without device work
+    // (invalid, a label absent from the graph, exact upper-bound reject) are
+    // finished at once.
+    void add(FxRequest *r);
+    bool idle() const;
+    fx_status step();
+    std::function<void(FxRequest *)> on_done;
+
+private:
+    fx_status admit();
+    fx_status finish(FxQuery &q);
+    void done(FxRequest *r);
+    fx_graph *G_;
+    EngineWork *W_;
+    hipStream_t s_;
+    EngineParams P_;
+    fx_stats *stats_;
+    std::deque<std::unique_ptr<FxQuery>> pending_;
+    std::vector<std::unique_ptr<FxQuery>> active_;
+    std::vector<int> free_slots_;
+    size_t rot_ = 0;
+    std::chrono::steady_clock::time_point t0_;
+    bool buffers_ready_ = false;
+};
+
 // Runs every request to completion, many at a time (at most max_active in
-// flight).  Requests that fail validation get their status set and are
-// skipped; any device error aborts the whole run.
+// flight).  Requests that fail validation get their status set; any device
+// error aborts the run.
 fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active);

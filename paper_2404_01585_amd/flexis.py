@@ -36,7 +36,9 @@ _STATUS_NAMES = {0: "FX_OK", -1: "FX_EINVAL", -2: "FX_EGRAPH", -3: "FX_EPATTERN"
 
 # Every symbol include/flexis.h declares.
 EXPORTS = ["fx_ctx_create", "fx_ctx_destroy", "fx_graph_load", "fx_graph_destroy", "fx_tau", "fx_support",
-           "fx_enumerate", "fx_support_batch", "fx_ctx_stats", "fx_last_error", "fx_version"]
+           "fx_enumerate", "fx_support_batch", "fx_ctx_stats", "fx_server_create", "fx_server_submit",
+           "fx_server_poll", "fx_server_wait", "fx_server_stats", "fx_server_destroy", "fx_last_error",
+           "fx_version"]
 
 CTX_KERNEL_TIMING = 1
 CTX_NO_DIGEST = 2
@@ -62,6 +64,11 @@ class GraphDesc(ctypes.Structure):
 class PatternC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("vlabel", ctypes.c_void_p),
                 ("edges", ctypes.c_void_p), ("elabel", ctypes.c_void_p)]
+
+
+class ServerOptsC(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int32), ("slice_rows", ctypes.c_int64), ("mem_budget_bytes", ctypes.c_int64),
+                ("step_candidates", ctypes.c_int64), ("flags", ctypes.c_uint32)]
 
 
 class StatsC(ctypes.Structure):
@@ -163,6 +170,18 @@ def load_library():
     lib.fx_support.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P, P, ctypes.c_int64]
     lib.fx_enumerate.restype = ctypes.c_int32
     lib.fx_enumerate.argtypes = [P, P, P, ctypes.c_int64, P]
+    lib.fx_server_create.restype = ctypes.c_int32
+    lib.fx_server_create.argtypes = [P, P, P]
+    lib.fx_server_submit.restype = ctypes.c_int32
+    lib.fx_server_submit.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P]
+    lib.fx_server_poll.restype = ctypes.c_int32
+    lib.fx_server_poll.argtypes = [P, ctypes.c_uint64, P, P]
+    lib.fx_server_wait.restype = ctypes.c_int32
+    lib.fx_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, P]
+    lib.fx_server_stats.restype = ctypes.c_int32
+    lib.fx_server_stats.argtypes = [P, P]
+    lib.fx_server_destroy.restype = ctypes.c_int32
+    lib.fx_server_destroy.argtypes = [P]
     lib.fx_ctx_stats.restype = ctypes.c_int32
     lib.fx_ctx_stats.argtypes = [P, P, ctypes.c_int32]
     lib.fx_support_batch.restype = ctypes.c_int32
@@ -325,6 +344,54 @@ class DeviceGraph:
     def close(self):
         if self._h:
             _check(load_library().fx_graph_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Server:
+    """fx_server: continuous-batching support queries over a resident graph.
+
+    submit/poll/wait are thread-safe (ctypes releases the GIL during calls)."""
+
+    def __init__(self, graph: "DeviceGraph", max_active: int = 0, slice_rows: int = 0, mem_budget_bytes: int = 0,
+                 step_candidates: int = 0, no_digest: bool = False):
+        self.graph = graph
+        self._opts = ServerOptsC(max_active, slice_rows, mem_budget_bytes, step_candidates,
+                                 CTX_NO_DIGEST if no_digest else 0)
+        self._h = ctypes.c_void_p()
+        _check(load_library().fx_server_create(graph._h, ctypes.byref(self._opts), ctypes.byref(self._h)))
+
+    def submit(self, p, sigma: int, lam: float, mode: int = MODE_FULL) -> int:
+        ph = _PatternHolder.of(p)
+        t = ctypes.c_uint64(0)
+        _check(load_library().fx_server_submit(self._h, ctypes.byref(ph.c), int(sigma), float(lam), int(mode),
+                                               ctypes.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int) -> Optional[Dict]:
+        res = ResultC()
+        done = ctypes.c_int32(0)
+        _check(load_library().fx_server_poll(self._h, ticket, ctypes.byref(res), ctypes.byref(done)))
+        return res.to_dict() if done.value else None
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> Dict:
+        res = ResultC()
+        _check(load_library().fx_server_wait(self._h, ticket, int(timeout_us), ctypes.byref(res)))
+        return res.to_dict()
+
+    def stats(self) -> Dict:
+        st = StatsC()
+        _check(load_library().fx_server_stats(self._h, ctypes.byref(st)))
+        return st.to_dict()
+
+    def close(self):
+        if self._h:
+            _check(load_library().fx_server_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __enter__(self):

@@ -297,3 +297,59 @@ def test_no_digest_counts(torch_cuda, er1k, slice_rows):
             for k in ("support", "embedding_count"):
                 assert r[k] == want[k], (idx, k, r[k], want[k])
     c.close()
+
+
+def test_server_alone_equals_in_the_mix(ctx, er1k):
+    """Queries submitted concurrently from several threads to the
+    continuous-batching server get exactly the results fx_support gives them
+    alone (tolerance 0)."""
+    import threading
+    import time
+
+    g = er1k
+    pats = sample_patterns(g, 120, seed=41, kmin=2, kmax=6)
+    rng = np.random.default_rng(9)
+    sig = [int(x) for x in rng.integers(5, 60, size=len(pats))]
+    lam = [float(x) for x in rng.choice([0.1, 0.5, 1.0], size=len(pats))]
+    modes = [int(x) for x in rng.integers(0, 2, size=len(pats))]
+    with ctx.load_graph(g) as dg:
+        alone = [dg.support(p, s, l, m) for p, s, l, m in zip(pats, sig, lam, modes)]
+        with fx.Server(dg, max_active=32, step_candidates=1 << 16) as srv:
+            tickets = [None] * len(pats)
+
+            def submitter(idx):
+                for i in idx:
+                    tickets[i] = srv.submit(pats[i], sig[i], lam[i], modes[i])
+                    time.sleep(float(rng.random()) * 1e-3)
+
+            parts = [list(range(k, len(pats), 4)) for k in range(4)]
+            th = [threading.Thread(target=submitter, args=(pp,)) for pp in parts]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+            _say("server: all submitted")
+            got = [srv.wait(t, 60_000_000) for t in tickets]
+            st = srv.stats()
+        assert st["queries"] > 0
+        for i in range(len(pats)):
+            for k in ("tau", "support", "frequent", "embedding_count", "count_saturated", "digest"):
+                assert got[i][k] == alone[i][k], (i, k, got[i][k], alone[i][k])
+            assert got[i]["device_ms"] >= 0
+        # errors are reported at submission; unknown tickets are rejected; the
+        # graph cannot go while a server holds it
+        with fx.Server(dg) as srv:
+            with pytest.raises(fx.FxError) as e:
+                srv.submit(pats[0], 0, 1.0)
+            assert e.value.status == fx.FX_EINVAL
+            with pytest.raises(fx.FxError) as e:
+                srv.submit(Pattern([0, 0, 0], [(0, 1)], [0]), 1, 1.0)
+            assert e.value.status == fx.FX_EPATTERN
+            with pytest.raises(fx.FxError):
+                srv.poll(123456)
+            with pytest.raises(fx.FxError) as e:
+                dg.close()
+            assert e.value.status == fx.FX_EBUSY
+            t = srv.submit(pats[1], 20, 1.0)
+            r = srv.wait(t)
+            assert r["support"] == alone[1]["support"] or modes[1] != fx.MODE_FULL
