@@ -106,6 +106,119 @@ def cpu_baseline(g, cands, spec, seconds: float, threads: int):
                        f"(support + count + digest), {dt:.1f} s wall")
 
 
+def serving_queries(g, count: int, seed: int):
+    """Support queries of the serving workload: patterns of 3-8 vertices
+    sampled from the graph, sigma log-uniform in [50, 5000], lambda uniform in
+    {0.1, 0.5, 1.0}."""
+    import numpy as np
+
+    from paper_2404_01585_amd.synth import sample_patterns
+
+    rng = np.random.default_rng(seed)
+    pats = sample_patterns(g, count, seed=seed, kmin=3, kmax=8)
+    sig = np.floor(np.exp(rng.uniform(np.log(50), np.log(5001), size=count))).astype(np.int64)
+    lam = rng.choice([0.1, 0.5, 1.0], size=count)
+    return pats, [int(x) for x in sig], [float(x) for x in lam]
+
+
+def _lat_summary(lat_ms, n, wall):
+    import numpy as np
+    a = np.asarray(lat_ms)
+    return dict(n=n, p50_ms=round(float(np.percentile(a, 50)), 3), p99_ms=round(float(np.percentile(a, 99)), 3),
+                throughput_qps=round(n / wall, 1))
+
+
+def run_served(srv, queries, rate: float, mode: int, seed: int):
+    """Open-loop Poisson arrivals into the server; latency = submit -> result
+    (measured by the library)."""
+    import numpy as np
+    pats, sig, lam = queries
+    n = len(pats)
+    arr = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, size=n))
+    t0 = time.perf_counter()
+    tickets = []
+    for i in range(n):
+        wait = t0 + arr[i] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(pats[i], sig[i], lam[i], mode))
+    log(f"[serve] {n} submitted at {rate} q/s")
+    res = []
+    for k, t in enumerate(tickets):
+        res.append(srv.wait(t))
+        if (k + 1) % 250 == 0:
+            log(f"[serve] {k + 1}/{n} answered")
+    wall = time.perf_counter() - t0
+    return _lat_summary([r["device_ms"] for r in res], n, wall), res
+
+
+def run_fifo(dg, queries, rate: float, mode: int, seed: int):
+    """The same arrivals served one query per call, first come first served;
+    latency = completion - arrival."""
+    import numpy as np
+    pats, sig, lam = queries
+    n = len(pats)
+    arr = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, size=n))
+    t0 = time.perf_counter()
+    lat, res = [], []
+    for i in range(n):
+        wait = t0 + arr[i] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        res.append(dg.support(pats[i], sig[i], lam[i], mode))
+        lat.append((time.perf_counter() - (t0 + arr[i])) * 1e3)
+        if (i + 1) % 100 == 0:
+            log(f"[fifo] {i + 1}/{n} answered")
+    wall = time.perf_counter() - t0
+    return _lat_summary(lat, n, wall), res
+
+
+def serve_sweep(args):
+    """Serving workload: the cl100k graph resident, Poisson streams of support
+    queries at several rates; continuous batching vs one query per call, in
+    VERDICT and FULL modes.  Prints one JSON line."""
+    import torch
+
+    from paper_2404_01585_amd import flexis as fx
+    from paper_2404_01585_amd.synth import workload_graph
+
+    g = workload_graph("cl100k")
+    torch.cuda.set_device(0)
+    ctx = fx.Context(device=0, no_digest=True, count_cap=args.serve_count_cap)
+    dg = ctx.load_graph(g)
+    queries = serving_queries(g, args.serve_queries, seed=4)
+    log(f"[serve] {len(queries[0])} queries sampled")
+    out = []
+    plan = (("verdict", fx.MODE_VERDICT, args.serve_rates, queries),
+            ("full", fx.MODE_FULL, args.serve_full_rates, tuple(x[:args.serve_full_queries] for x in queries)))
+    for mode_name, mode, rate_list, qset in plan:
+        rates = [float(r) for r in rate_list.split(",") if r]
+        with fx.Server(dg, no_digest=True, step_candidates=args.serve_step) as srv:
+            run_served(srv, tuple(x[:100] for x in qset), 1000.0, mode, seed=99)  # warm the server
+            for rate in rates:
+                queries = qset
+                served, res_s = run_served(srv, queries, rate, mode, seed=int(rate))
+                row = dict(mode=mode_name, rate_qps=rate, served=served)
+                if not args.no_fifo:
+                    fifo, res_f = run_fifo(dg, queries, rate, mode, seed=int(rate))
+                    row["fifo_one_per_call"] = fifo
+                    row["same_results"] = all(a["frequent"] == b["frequent"] and a["support"] == b["support"]
+                                              for a, b in zip(res_s, res_f))
+                log(f"[serve] {row}")
+                out.append(row)
+    line = {"metric": "p50/p99 support-query latency and throughput at 1 GPU (served, continuous batching)",
+            "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": "cl100k-serve: Chung-Lu 100K vertices / 500K edges resident; Poisson arrivals; "
+                                   "patterns of 3-8 vertices sampled from the graph; sigma log-uniform [50, 5000]; "
+                                   "lambda in {0.1, 0.5, 1.0}", "queries_per_rate_verdict": args.serve_queries,
+                       "queries_per_rate_full": args.serve_full_queries, "count_cap_full": args.serve_count_cap,
+                       "step_candidates": args.serve_step},
+            "rates": out}
+    print(json.dumps(line), flush=True)
+    dg.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,10 +233,24 @@ def main():
                     help="also hash every embedding (FULL-mode digest); counts are exact either way")
     ap.add_argument("--plain-seconds", type=float, default=5.0,
                     help="time the one-pattern-per-call form on a prefix of the batch for this long")
+    ap.add_argument("--serve", action="store_true", help="serving sweep (Poisson arrivals) instead of the batch")
+    ap.add_argument("--serve-rates", default="100,300,1000,3000,5000")
+    ap.add_argument("--serve-queries", type=int, default=1000)
+    ap.add_argument("--serve-full-rates", default="100,1000")
+    ap.add_argument("--serve-full-queries", type=int, default=300)
+    ap.add_argument("--serve-count-cap", type=int, default=10 ** 9)
+    ap.add_argument("--serve-step", type=int, default=1 << 22, help="candidates per device step of the server")
+    ap.add_argument("--no-fifo", action="store_true")
+    ap.add_argument("--serve-probe-rate", type=float, default=1000.0,
+                    help="rate of the short serving probe in the default run (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="calibration only: copy a buffer of this many bytes 5 times with torch and exit "
                          "(a plain copy kernel of known size for the PMC traffic factors)")
     args = ap.parse_args()
+
+    if args.serve:
+        serve_sweep(args)
+        return
 
     if args.copy_bytes > 0:
         import torch
@@ -209,6 +336,16 @@ def main():
         plain = dict(patterns_per_s=round(k / (time.perf_counter() - t1), 3), sample=k)
         log(f"[bench] plain form: {plain}")
 
+    serving = None
+    if args.serve_probe_rate > 0:
+        queries = serving_queries(g, 1000, seed=4)
+        with fx.Server(dg, no_digest=not args.digest, step_candidates=args.serve_step) as srv:
+            run_served(srv, tuple(x[:100] for x in queries), 1000.0, fx.MODE_VERDICT, seed=99)
+            served, _ = run_served(srv, queries, args.serve_probe_rate, fx.MODE_VERDICT, seed=7)
+        fifo, _ = run_fifo(dg, queries, args.serve_probe_rate, fx.MODE_VERDICT, seed=7)
+        serving = dict(rate_qps=args.serve_probe_rate, mode="verdict", served=served, fifo_one_per_call=fifo)
+        log(f"[bench] serving probe: {serving}")
+
     cpu = None
     if not args.no_cpu:
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
@@ -242,6 +379,7 @@ def main():
         "syncs_per_step": st["syncs"] / args.steps,
         "device_steps_per_step": st["steps"] / args.steps,
         "plain_form": plain,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -306,23 +306,38 @@ def sample_pattern(g: Graph, rng: np.random.Generator, k: int, shape: str,
     nv = g.num_vertices
     deg = g.degree()
     vcount = np.bincount(g.vlabel, minlength=int(g.vlabel.max()) + 1)
+    def rand_nb(x, excl):
+        """A uniformly random neighbour of x outside excl, or None."""
+        nb = g.neighbors(x)
+        d = nb.shape[0]
+        if d == 0:
+            return None
+        for _t in range(8):
+            y = int(nb[int(rng.integers(0, d))])
+            if y not in excl:
+                return y
+        rest = [int(y) for y in nb if int(y) not in excl]
+        return rest[int(rng.integers(0, len(rest)))] if rest else None
+
+    def adjacent(u, v):
+        nb = g.neighbors(u)
+        j = int(np.searchsorted(nb, v))
+        return j < nb.shape[0] and int(nb[j]) == v
+
     for _ in range(max_tries):
         start = int(rng.integers(0, nv))
         if deg[start] == 0:
             continue
         if shape == "cycle":
             path = [start]
-            ok = False
-            for _step in range(4 * k):
-                if len(path) == k:
-                    if path[0] in set(g.neighbors(path[-1]).tolist()):
-                        ok = True
+            seen = {start}
+            while len(path) < k:
+                y = rand_nb(path[-1], seen)
+                if y is None:
                     break
-                nb = [int(x) for x in g.neighbors(path[-1]) if int(x) not in path]
-                if not nb:
-                    break
-                path.append(nb[int(rng.integers(0, len(nb)))])
-            if not ok:
+                path.append(y)
+                seen.add(y)
+            if len(path) < k or not adjacent(path[-1], path[0]):
                 continue
             verts = path
             edges_local = [(i, i + 1) for i in range(k - 1)] + [(k - 1, 0)]
@@ -332,23 +347,24 @@ def sample_pattern(g: Graph, rng: np.random.Generator, k: int, shape: str,
             frontier = [start]
             while len(verts) < k and frontier:
                 x = frontier[int(rng.integers(0, len(frontier)))]
-                nb = [int(y) for y in g.neighbors(x) if int(y) not in vset]
-                if not nb:
+                y = rand_nb(x, vset)
+                if y is None:
                     frontier.remove(x)
                     continue
-                y = nb[int(rng.integers(0, len(nb)))]
                 verts.append(y)
                 vset.add(y)
                 frontier.append(y)
             if len(verts) < k:
                 continue
-            index = {v: i for i, v in enumerate(verts)}
+            varr = np.asarray(verts, dtype=np.int64)
             induced = []
             for i, v in enumerate(verts):
-                for y in g.neighbors(v):
-                    j = index.get(int(y))
-                    if j is not None and i < j:
-                        induced.append((i, j))
+                nb = g.neighbors(v)
+                j = np.minimum(np.searchsorted(nb, varr), max(nb.shape[0] - 1, 0))
+                hit = (nb.shape[0] > 0) & (nb[j] == varr) if nb.shape[0] else np.zeros(k, dtype=bool)
+                for jj in np.nonzero(hit)[0]:
+                    if i < int(jj):
+                        induced.append((i, int(jj)))
             # random spanning tree of the induced subgraph (randomised Kruskal)
             order = rng.permutation(len(induced))
             parent = list(range(k))
