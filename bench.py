@@ -229,6 +229,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (untimed) before the timed steps")
     ap.add_argument("--digest", action="store_true",
                     help="also hash every embedding (FULL-mode digest); counts are exact either way")
     ap.add_argument("--plain-seconds", type=float, default=5.0,
@@ -290,6 +291,11 @@ def main():
     lam = [spec["lam"]] * len(cands)
     batch = fx.PatternBatch(cands)
 
+    tuned = None
+    if not args.no_tune:
+        t = time.perf_counter()
+        tuned = dg.autotune(batch, spec["sigma"], spec["lam"], mode)
+        log(f"[bench] autotune {tuned} ({time.perf_counter() - t:.1f} s)")
     for w in range(args.warmup):
         dg.support_batch_array(batch, spec["sigma"], spec["lam"], mode)
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
@@ -368,7 +374,8 @@ def main():
         "config": {"workload": args.workload, "description": spec["desc"], "patterns": P,
                    "patterns_per_level": per_level, "sigma": spec["sigma"], "lambda": spec["lam"],
                    "mode": args.mode, "count_cap": ctx.count_cap, "digest": bool(args.digest),
-                   "form": "batched (all candidates of the batch in flight, one segment each per step)"},
+                   "form": "batched (all candidates of the batch in flight, one segment each per step)",
+                   "tuned": tuned},
         "embeddings_per_s": round(emb * args.steps / dt, 1),
         "frequent": frequent,
         "query_device_ms_p50": round(float(np.percentile(qms, 50)), 4),

@@ -262,6 +262,28 @@ fx_status fx_server_stats(fx_server *s, fx_stats *out);
 /* Finishes every submitted query, then stops the worker and frees the server. */
 fx_status fx_server_destroy(fx_server *s);
 
+/* Autotuner of the batched launch shape.  Times fx_support_batch on the
+ * given sample while it walks the tunables one at a time: candidates per
+ * thread of the expansion kernels (2, 4, 8: the workgroup tile), candidates
+ * per device step, the level capacity of a pattern's slice stack (the frontier
+ * chunk) and the first last-vertex slice of the greedy.  The fastest setting
+ * is kept in the context (later calls use it; results never depend on it).
+ * cache_path (optional): a text file of tuned keys (architecture, graph shape,
+ * largest pattern, mode); a cached key is applied without timing. */
+typedef struct {
+    int64_t slice_rows;
+    int64_t step_candidates;
+    int32_t items_per_thread;
+    int32_t last_span_init;
+    double best_ms;     /* sample time with the chosen setting */
+    double default_ms;  /* sample time with the context's setting before tuning */
+    int32_t trials;
+    int32_t from_cache;
+} fx_tune_result;
+
+fx_status fx_autotune(fx_graph *g, int32_t npat, const fx_pattern *pats, const int64_t *sigma, const double *lambda,
+                      int32_t mode, const char *cache_path, fx_tune_result *out);
+
 /* Thread-local description of the last error. */
 const char *fx_last_error(void);
 

@@ -424,10 +424,11 @@ fx_status FxEngine::admit()
 
 fx_status FxEngine::step()
 {
-    if (!buffers_ready_) {
+    if (!buffers_ready_) {  // grow-only buffers sized for these parameters
         const int32_t A = P_.max_active;
-        const uint64_t max_blocks = (P_.step_candidates + FX_TILE - 1) / FX_TILE + (uint64_t)A;
-        FX_TRY(W_->flag.ensure(max_blocks * FX_TILE));
+        const uint64_t tile = (uint64_t)FX_BS * P_.items;
+        const uint64_t max_blocks = (P_.step_candidates + tile - 1) / tile + (uint64_t)A;
+        FX_TRY(W_->flag.ensure(max_blocks * tile));
         FX_TRY(W_->bcnt.ensure(max_blocks * 4));
         FX_TRY(W_->boff.ensure((max_blocks + 1) * 8));
         FX_TRY(W_->lsum.ensure(max_blocks * 8));
@@ -454,7 +455,7 @@ fx_status FxEngine::step()
     int nsegs = 0;
     uint64_t budget = P_.step_candidates;
     uint32_t nblocks = 0;
-    int any_inner = 0, any_greedy = 0, any_write = 0;
+    int any_inner = 0, any_greedy = 0;
     const size_t A = active_.size();
     for (auto &qp : active_) qp->seg_l = -1;
     for (size_t k = 0; k < A && budget > 0; k++) {
@@ -505,7 +506,7 @@ fx_status FxEngine::step()
         S.flags = flags;
         S.kind = kind;
         blk0[nsegs] = nblocks;
-        nblocks += (uint32_t)((span + FX_TILE - 1) / FX_TILE);
+        nblocks += (uint32_t)((span + (uint64_t)FX_BS * P_.items - 1) / ((uint64_t)FX_BS * P_.items));
         budget -= span;
         q.seg_l = l;
         q.seg_kind = kind;
@@ -513,7 +514,6 @@ fx_status FxEngine::step()
         q.seg_span = (uint32_t)span;
         any_inner |= kind == FX_SEG_INNER;
         any_greedy |= kind == FX_SEG_GREEDY;
-        any_write |= kind != FX_SEG_COUNT;
         nsegs++;
     }
     rot_++;
@@ -523,10 +523,10 @@ fx_status FxEngine::step()
     FX_HIP(hipMemcpyAsync(W_->blk0_d.p, blk0, ((size_t)nsegs + 1) * 4, hipMemcpyHostToDevice, s_));
     hipEvent_t *ev = P_.timing ? W_->evk : nullptr;
     FX_HIP(fx_launch_step(s_, G_->dev, W_->segs_d.as<FxSeg>(), W_->blk0_d.as<uint32_t>(), nsegs, nblocks,
-                          W_->flag.as<uint8_t>(), W_->bcnt.as<uint32_t>(), W_->boff.as<uint64_t>(),
+                          P_.items, W_->flag.as<uint8_t>(), W_->bcnt.as<uint32_t>(), W_->boff.as<uint64_t>(),
                           W_->lsum.as<uint64_t>(), W_->loff.as<uint64_t>(), ev ? ev[0] : nullptr,
                           ev ? ev[1] : nullptr, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
-                          ev ? ev[5] : nullptr, any_inner, any_greedy, any_write));
+                          ev ? ev[5] : nullptr, any_inner, any_greedy));
     int hi = 0;
     for (auto &qp : active_) hi = std::max(hi, qp->slot + 1);
     FX_HIP(hipMemcpyAsync(sums_h, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, s_));

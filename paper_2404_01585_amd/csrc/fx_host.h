@@ -86,6 +86,7 @@ struct EngineParams {
     uint64_t step_candidates = 1ull << 25;  // flattened candidates per step, all queries together
     int32_t max_active = 4096;             // queries in flight
     uint32_t last_span_init = 4096;        // first last-vertex slice of the support phase
+    int32_t items = 4;                     // candidates per thread in the expansion kernels (2, 4, 8)
     bool timing = false;
     bool no_digest = false;
 };

@@ -27,8 +27,7 @@
 #define FX_MAXN 16
 #define FX_NLF 4
 #define FX_BS 256            // threads per workgroup for the streaming kernels
-#define FX_ITEMS 4           // candidates per thread in the expansion kernels
-#define FX_TILE (FX_BS * FX_ITEMS)  // candidates per expansion workgroup
+#define FX_MAX_TILE (FX_BS * 8)  // most candidates per expansion workgroup (8 per thread)
 #define FX_LDSP 1024         // partial offsets a workgroup stages in LDS
 #define FX_GREEDY_H 4096     // LDS hash slots of the per-query greedy
 #define FX_GREEDY_VN 2048    // embedding-vertices per greedy chunk (<= H / 2)
@@ -109,7 +108,7 @@ struct FxSeg {
     uint64_t t0;            // first flattened candidate of the slice
     int64_t rank_base;      // rank of the first complete embedding this step writes
     uint32_t span;          // candidates in the slice
-    uint32_t blk0;          // first workgroup of this segment in the launch (FX_TILE candidates each)
+    uint32_t blk0;          // first workgroup of this segment in the launch (FX_BS * items candidates each)
     int32_t n, l;
     int32_t flags;          // FX_PROBE_*
     int32_t kind;           // FX_SEG_*
@@ -129,9 +128,11 @@ struct FxInit {
 
 // Launchers (fx_kernels.hip).  All return the hipError_t of the launches.
 hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *inits, int32_t ninit);
+// One step: probe, scan, scatter (+ run-length prefix fix-up), greedy.  items
+// (2, 4 or 8) is the number of candidates per thread; segment j owns
+// ceil(span_j / (FX_BS * items)) consecutive workgroups starting at blk0s[j].
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                          int32_t nsegs, uint32_t nblocks, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
-                          uint64_t *lsum, uint64_t *loff,
-                          hipEvent_t probe_begin, hipEvent_t probe_end, hipEvent_t scatter_begin,
-                          hipEvent_t scatter_end, hipEvent_t greedy_begin, hipEvent_t greedy_end,
-                          int32_t any_inner, int32_t any_greedy, int32_t any_write);
+                          int32_t nsegs, uint32_t nblocks, int32_t items, uint8_t *flag, uint32_t *bcnt,
+                          uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
+                          hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
+                          hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy);

@@ -263,21 +263,23 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
     return (uint64_t)c;
 }
 
-// Test every candidate of every segment (FX_ITEMS per thread, strided by
+// Test every candidate of every segment (ITEMS per thread, strided by
 // the workgroup size so each item pass covers consecutive candidates).
 // Writes a pass flag per candidate and the number of passes per workgroup.
+template <int ITEMS>
 __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__restrict__ segs,
                                                  const uint32_t *__restrict__ blk0s, int32_t nsegs, uint8_t *flag,
                                                  uint32_t *bcnt)
 {
+    constexpr uint32_t TILE = FX_BS * ITEMS;
     __shared__ int64_t s_off[FX_LDSP + 1];
     __shared__ int64_t s_meta[2];
     __shared__ uint32_t wcnt[FX_BS / 64];
     const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
     const FxSeg &S = segs[si];
     const int32_t l = S.l, n = S.n, flags = S.flags;
-    const uint32_t tile0 = (blockIdx.x - S.blk0) * FX_TILE;
-    const uint32_t tile_n = min((uint32_t)FX_TILE, S.span - tile0);
+    const uint32_t tile0 = (blockIdx.x - S.blk0) * TILE;
+    const uint32_t tile_n = min((uint32_t)TILE, S.span - tile0);
     const TileMap m = map_tile(S.in.off, S.nparts, S.t0 + tile0, S.t0 + tile0 + tile_n - 1, s_off, s_meta);
     const bool ufilter = (flags & FX_PROBE_UFILTER) != 0;
     const bool count = (flags & FX_PROBE_COUNT) != 0;
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
     unsigned long long cnt = 0;
     uint64_t h1 = 0, h2 = 0;
 #pragma unroll
-    for (int it = 0; it < FX_ITEMS; it++) {
+    for (int it = 0; it < ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
         bool mat = false;
         if (tl < S.span) {
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
                 if (leaf) cnt += leaf_count(g, S.plan, l, x, bytes);
                 mat = S.kind != FX_SEG_COUNT;
             }
-            flag[(uint64_t)blockIdx.x * FX_TILE + it * FX_BS + threadIdx.x] = mat ? 1 : 0;
+            flag[(uint64_t)blockIdx.x * TILE + it * FX_BS + threadIdx.x] = mat ? 1 : 0;
         }
         passed += mat ? 1u : 0u;
     }
@@ -386,45 +388,47 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt
 // segments it also writes each new row's prefix of run lengths within this
 // workgroup's rows to off[] and the workgroup's total to lsum[]; k_fix_off
 // adds the workgroup offsets after a scan of lsum.
+template <int ITEMS>
 __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
                                                    const uint32_t *__restrict__ blk0s, int32_t nsegs,
                                                    const uint8_t *__restrict__ flag,
                                                    const uint64_t *__restrict__ boff, uint64_t *lsum)
 {
+    constexpr uint32_t TILE = FX_BS * ITEMS;
     __shared__ int64_t s_off[FX_LDSP + 1];
     __shared__ int64_t s_meta[2];
-    __shared__ uint32_t wcnt[FX_ITEMS][FX_BS / 64];
-    __shared__ unsigned long long ltot[FX_ITEMS][FX_BS / 64];
+    __shared__ uint32_t wcnt[ITEMS][FX_BS / 64];
+    __shared__ unsigned long long ltot[ITEMS][FX_BS / 64];
     const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
     const FxSeg &S = segs[si];
     const int32_t l = S.l, n = S.n;
     const uint64_t seg_base = boff[S.blk0];
     if (blockIdx.x == S.blk0 && threadIdx.x == 0) {
-        const uint32_t nblk = (S.span + FX_TILE - 1) / FX_TILE;
+        const uint32_t nblk = (S.span + TILE - 1) / TILE;
         S.sum->total_out = boff[S.blk0 + nblk] - seg_base;
     }
     if (S.kind != FX_SEG_INNER && threadIdx.x == 0) lsum[blockIdx.x] = 0;
     if (S.kind == FX_SEG_COUNT) return;  // nothing is written for a counting segment
-    const uint32_t tile0 = (blockIdx.x - S.blk0) * FX_TILE;
+    const uint32_t tile0 = (blockIdx.x - S.blk0) * TILE;
     const uint32_t wave = threadIdx.x >> 6;
-    uint64_t bal[FX_ITEMS];
-    bool f[FX_ITEMS];
+    uint64_t bal[ITEMS];
+    bool f[ITEMS];
 #pragma unroll
-    for (int it = 0; it < FX_ITEMS; it++) {
+    for (int it = 0; it < ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
-        f[it] = tl < S.span && flag[(uint64_t)blockIdx.x * FX_TILE + it * FX_BS + threadIdx.x];
+        f[it] = tl < S.span && flag[(uint64_t)blockIdx.x * TILE + it * FX_BS + threadIdx.x];
         bal[it] = __ballot(f[it]);
         if (__lane_id() == 0) wcnt[it][wave] = (uint32_t)__popcll(bal[it]);
     }
-    const uint32_t tile_n = min((uint32_t)FX_TILE, S.span - tile0);
+    const uint32_t tile_n = min((uint32_t)TILE, S.span - tile0);
     const TileMap m = map_tile(S.in.off, S.nparts, S.t0 + tile0, S.t0 + tile0 + tile_n - 1, s_off, s_meta);
     const int32_t w1 = l + 1;
     uint32_t bytes = 0;
     uint64_t pos = boff[blockIdx.x] - seg_base;
-    uint64_t p_out[FX_ITEMS];
-    int32_t lens[FX_ITEMS];
+    uint64_t p_out[ITEMS];
+    int32_t lens[ITEMS];
 #pragma unroll
-    for (int it = 0; it < FX_ITEMS; it++) {
+    for (int it = 0; it < ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
         // flag read per candidate; row and run descriptor written per survivor
         bytes += (tl < S.span ? 1u : 0u) + (f[it] ? 4u * (uint32_t)w1 : 0u) + ((f[it] && w1 < n) ? 21u : 0u);
@@ -478,10 +482,10 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
     }
     if (S.kind == FX_SEG_INNER) {  // uniform across the workgroup
         // exclusive prefix of the run lengths in output order (item, wave, lane)
-        long long inc[FX_ITEMS];
+        long long inc[ITEMS];
         const uint32_t lane = __lane_id();
 #pragma unroll
-        for (int it = 0; it < FX_ITEMS; it++) {
+        for (int it = 0; it < ITEMS; it++) {
             inc[it] = lens[it];
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -494,7 +498,7 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
         __syncthreads();
         uint64_t before = 0;
 #pragma unroll
-        for (int it = 0; it < FX_ITEMS; it++) {
+        for (int it = 0; it < ITEMS; it++) {
             uint64_t mine = before;
             for (uint32_t w = 0; w < wave; w++) mine += ltot[it][w];
             if (f[it]) S.out.off[p_out[it]] = (int64_t)(mine + (uint64_t)(inc[it] - lens[it]));
@@ -511,10 +515,12 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
 // Adds each workgroup's offset (scan of lsum within its segment) to the
 // run-length prefixes k_scatter wrote, and closes each inner level with
 // off[N] and the level's candidate total.
+template <int ITEMS>
 __global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ segs, const uint32_t *__restrict__ blk0s,
                                                    int32_t nsegs, const uint64_t *__restrict__ boff,
                                                    const uint64_t *__restrict__ loff)
 {
+    constexpr uint32_t TILE = FX_BS * ITEMS;
     const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
     const FxSeg &S = segs[si];
     if (S.kind != FX_SEG_INNER) return;
@@ -524,7 +530,7 @@ __global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ seg
     if (add)
         for (uint64_t r = r0 + threadIdx.x; r < r1; r += FX_BS) S.out.off[r] += (int64_t)add;
     if (blockIdx.x == S.blk0 && threadIdx.x == 0) {
-        const uint32_t nblk = (S.span + FX_TILE - 1) / FX_TILE;
+        const uint32_t nblk = (S.span + TILE - 1) / TILE;
         const uint64_t N = boff[S.blk0 + nblk] - seg_base;
         const uint64_t total = loff[S.blk0 + nblk] - loff[S.blk0];
         S.out.off[N] = (int64_t)total;
@@ -687,28 +693,49 @@ hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *init
     return hipGetLastError();
 }
 
-hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                          int32_t nsegs, uint32_t nblocks, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
-                          uint64_t *lsum, uint64_t *loff,
-                          hipEvent_t probe_begin, hipEvent_t probe_end, hipEvent_t scatter_begin,
-                          hipEvent_t scatter_end, hipEvent_t greedy_begin, hipEvent_t greedy_end,
-                          int32_t any_inner, int32_t any_greedy, int32_t any_write)
+template <int ITEMS>
+hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
+                             int32_t nsegs, uint32_t nblocks, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
+                             uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin, hipEvent_t probe_end,
+                             hipEvent_t scatter_begin, hipEvent_t scatter_end, hipEvent_t greedy_begin,
+                             hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
 {
     hipError_t e;
     if (probe_begin && (e = hipEventRecord(probe_begin, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_probe, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, bcnt);
+    hipLaunchKernelGGL(k_probe<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, bcnt);
     if (probe_end && (e = hipEventRecord(probe_end, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_blocks<uint32_t>, dim3(1), dim3(1024), 0, s, bcnt, nblocks, boff);
     if (scatter_begin && (e = hipEventRecord(scatter_begin, s)) != hipSuccess) return e;
-    (void)any_write;
-    hipLaunchKernelGGL(k_scatter, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, boff, lsum);
+    hipLaunchKernelGGL(k_scatter<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, boff, lsum);
     if (scatter_end && (e = hipEventRecord(scatter_end, s)) != hipSuccess) return e;
     if (any_inner) {
         hipLaunchKernelGGL(k_scan_blocks<uint64_t>, dim3(1), dim3(1024), 0, s, lsum, nblocks, loff);
-        hipLaunchKernelGGL(k_fix_off, dim3(nblocks), dim3(FX_BS), 0, s, segs, blk0s, nsegs, boff, loff);
+        hipLaunchKernelGGL(k_fix_off<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, segs, blk0s, nsegs, boff, loff);
     }
     if (greedy_begin && (e = hipEventRecord(greedy_begin, s)) != hipSuccess) return e;
     if (any_greedy) hipLaunchKernelGGL(k_greedy, dim3(nsegs), dim3(FX_BS), 0, s, segs);
     if (greedy_end && (e = hipEventRecord(greedy_end, s)) != hipSuccess) return e;
     return hipGetLastError();
+}
+
+hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
+                          int32_t nsegs, uint32_t nblocks, int32_t items, uint8_t *flag, uint32_t *bcnt,
+                          uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
+                          hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
+                          hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
+{
+    switch (items) {
+    case 2:
+        return launch_step_items<2>(s, g, segs, blk0s, nsegs, nblocks, flag, bcnt, boff, lsum, loff, probe_begin,
+                                    probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end, any_inner,
+                                    any_greedy);
+    case 8:
+        return launch_step_items<8>(s, g, segs, blk0s, nsegs, nblocks, flag, bcnt, boff, lsum, loff, probe_begin,
+                                    probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end, any_inner,
+                                    any_greedy);
+    default:
+        return launch_step_items<4>(s, g, segs, blk0s, nsegs, nblocks, flag, bcnt, boff, lsum, loff, probe_begin,
+                                    probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end, any_inner,
+                                    any_greedy);
+    }
 }

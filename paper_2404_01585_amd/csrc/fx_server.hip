@@ -113,7 +113,7 @@ extern "C" fx_status fx_server_create(fx_graph *g, const fx_server_opts *opts, f
     S->params.timing = false;
     if (o.max_active > 0) S->params.max_active = o.max_active;
     if (o.slice_rows > 0) S->params.slice_rows = std::min<int64_t>(std::max<int64_t>(o.slice_rows, 64), (int64_t)1 << 26);
-    if (o.step_candidates > 0) S->params.step_candidates = (uint64_t)std::max<int64_t>(o.step_candidates, FX_TILE);
+    if (o.step_candidates > 0) S->params.step_candidates = (uint64_t)std::max<int64_t>(o.step_candidates, FX_MAX_TILE);
     if (o.flags & FX_CTX_NO_DIGEST) S->params.no_digest = true;
     S->work.pool.budget = o.mem_budget_bytes > 0 ? (size_t)o.mem_budget_bytes : g->ctx->work.pool.budget;
     FX_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));

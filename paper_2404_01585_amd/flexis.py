@@ -37,8 +37,8 @@ _STATUS_NAMES = {0: "FX_OK", -1: "FX_EINVAL", -2: "FX_EGRAPH", -3: "FX_EPATTERN"
 # Every symbol include/flexis.h declares.
 EXPORTS = ["fx_ctx_create", "fx_ctx_destroy", "fx_graph_load", "fx_graph_destroy", "fx_tau", "fx_support",
            "fx_enumerate", "fx_support_batch", "fx_ctx_stats", "fx_server_create", "fx_server_submit",
-           "fx_server_poll", "fx_server_wait", "fx_server_stats", "fx_server_destroy", "fx_last_error",
-           "fx_version"]
+           "fx_server_poll", "fx_server_wait", "fx_server_stats", "fx_server_destroy", "fx_autotune",
+           "fx_last_error", "fx_version"]
 
 CTX_KERNEL_TIMING = 1
 CTX_NO_DIGEST = 2
@@ -69,6 +69,15 @@ class PatternC(ctypes.Structure):
 class ServerOptsC(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("slice_rows", ctypes.c_int64), ("mem_budget_bytes", ctypes.c_int64),
                 ("step_candidates", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+
+
+class TuneC(ctypes.Structure):
+    _fields_ = [("slice_rows", ctypes.c_int64), ("step_candidates", ctypes.c_int64),
+                ("items_per_thread", ctypes.c_int32), ("last_span_init", ctypes.c_int32), ("best_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double), ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+
+    def to_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class StatsC(ctypes.Structure):
@@ -182,6 +191,8 @@ def load_library():
     lib.fx_server_stats.argtypes = [P, P]
     lib.fx_server_destroy.restype = ctypes.c_int32
     lib.fx_server_destroy.argtypes = [P]
+    lib.fx_autotune.restype = ctypes.c_int32
+    lib.fx_autotune.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_int32, ctypes.c_char_p, P]
     lib.fx_ctx_stats.restype = ctypes.c_int32
     lib.fx_ctx_stats.argtypes = [P, P, ctypes.c_int32]
     lib.fx_support_batch.restype = ctypes.c_int32
@@ -330,6 +341,17 @@ class DeviceGraph:
         _check(load_library().fx_support_batch(self._h, k, batch.arr.ctypes.data, sg.ctypes.data, lm.ctypes.data,
                                                int(mode), res.ctypes.data))
         return res[:k]
+
+    def autotune(self, batch: "PatternBatch", sigma, lam, mode: int = MODE_FULL,
+                 cache_path: Optional[str] = None) -> Dict:
+        """fx_autotune on a sample batch; the chosen setting stays in the context."""
+        k = len(batch)
+        sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.int64), (k,)))
+        lm = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float64), (k,)))
+        r = TuneC()
+        _check(load_library().fx_autotune(self._h, k, batch.arr.ctypes.data, sg.ctypes.data, lm.ctypes.data,
+                                          int(mode), cache_path.encode() if cache_path else None, ctypes.byref(r)))
+        return r.to_dict()
 
     def support_batch(self, patterns: List, sigma: Sequence[int], lam: Sequence[float],
                       mode: int = MODE_FULL) -> List[Dict]:

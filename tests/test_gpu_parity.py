@@ -353,3 +353,28 @@ def test_server_alone_equals_in_the_mix(ctx, er1k):
             t = srv.submit(pats[1], 20, 1.0)
             r = srv.wait(t)
             assert r["support"] == alone[1]["support"] or modes[1] != fx.MODE_FULL
+
+
+def test_autotune_keeps_results(torch_cuda, er1k, tmp_path):
+    """The autotuner picks a launch shape by timing; results never change, and
+    a second call with the same cache file applies the cached choice."""
+    g = er1k
+    cands = _mining_candidates(g, 20, 1.0, 2)
+    c = fx.Context(device=0)
+    with c.load_graph(g) as dg:
+        batch = fx.PatternBatch(cands)
+        cache = str(tmp_path / "tune.txt")
+        _say("autotune")
+        t1 = dg.autotune(batch, 20, 1.0, fx.MODE_FULL, cache_path=cache)
+        assert t1["from_cache"] == 0 and t1["trials"] >= 10
+        assert t1["items_per_thread"] in (2, 4, 8)
+        got = dg.support_batch(cands, [20] * len(cands), [1.0] * len(cands), fx.MODE_FULL)
+        for p, r in zip(cands, got):
+            want = O.query(g, p, 20, 1.0, O.FULL)
+            for k in ("support", "frequent", "embedding_count", "digest"):
+                assert r[k] == want[k], (p, k)
+        t2 = dg.autotune(batch, 20, 1.0, fx.MODE_FULL, cache_path=cache)
+        assert t2["from_cache"] == 1
+        for k in ("slice_rows", "step_candidates", "items_per_thread", "last_span_init"):
+            assert t2[k] == t1[k]
+    c.close()
