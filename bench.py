@@ -68,10 +68,10 @@ def build_candidates(dg, g, spec):
     return cands, [len(l) for l in res["levels"]]
 
 
-def traffic_from_profile(kernel_src: str):
-    """HBM traffic per probe launch from the committed PMC summary, if it was
-    taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_probe_cl100k-l2.json")
+def traffic_from_profile(kernel_src: str, workload: str):
+    """HBM traffic per probe launch from the committed PMC summary of this
+    workload, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_probe_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -325,7 +325,7 @@ def main():
         roofline = dict(bound="hbm", achieved=round(achieved, 3), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(achieved / HBM_PEAK_GBS, 6),
                         traffic=traffic_from_profile(os.path.join(ROOT, "paper_2404_01585_amd", "csrc",
-                                                                  "fx_kernels.hip")),
+                                                                  "fx_kernels.hip"), args.workload),
                         kernel="k_probe", avg_launch_us=round(avg_ms * 1e3, 3),
                         alg_bytes_per_launch=round(bytes_per_launch, 1), launches=st["probe_launches"],
                         kernel_ms_share=dict(probe=round(st["probe_ms"], 3), scatter=round(st["scatter_ms"], 3),

@@ -71,6 +71,11 @@ typedef struct fx_server fx_server;
  *   mem_budget_bytes  device memory the per-pattern stacks of one batch may
  *                     hold at once (0 = 64 GiB); patterns are admitted while
  *                     their projected stack bytes fit.
+ *   run_index_bytes   largest label-run index a graph of this context may
+ *                     build (0 = 8 GiB, -1 = none): for every vertex and every
+ *                     (vertex label, edge label) pair, the offset of that run in
+ *                     the vertex's adjacency row, 4 bytes each.  With it a
+ *                     candidate run is two loads instead of two binary searches.
  *   flags             bitwise or of FX_CTX_KERNEL_TIMING (bracket the kernels of
  *                     every step with HIP events on the context's stream and
  *                     accumulate their durations, see fx_ctx_stats) and
@@ -87,6 +92,7 @@ typedef struct {
     int64_t slice_rows;
     int64_t count_cap;
     int64_t mem_budget_bytes;
+    int64_t run_index_bytes;
     uint32_t flags;
 } fx_ctx_opts;
 

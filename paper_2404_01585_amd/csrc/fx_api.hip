@@ -172,8 +172,8 @@ extern "C" fx_status fx_ctx_create(const fx_ctx_opts *opts, fx_ctx **out)
     if (opts) o = *opts;
     if ((o.flags & ~(FX_CTX_KERNEL_TIMING | FX_CTX_NO_DIGEST)) != 0)
         return fx_fail(FX_EINVAL, "unknown flags 0x%x", o.flags);
-    if (o.slice_rows < 0 || o.count_cap < 0 || o.mem_budget_bytes < 0)
-        return fx_fail(FX_EINVAL, "slice_rows, count_cap and mem_budget_bytes must be >= 0");
+    if (o.slice_rows < 0 || o.count_cap < 0 || o.mem_budget_bytes < 0 || o.run_index_bytes < -1)
+        return fx_fail(FX_EINVAL, "slice_rows, count_cap, mem_budget_bytes must be >= 0, run_index_bytes >= -1");
     int ndev = 0;
     FX_HIP(hipGetDeviceCount(&ndev));
     if (o.device < 0 || o.device >= ndev)
@@ -186,6 +186,7 @@ extern "C" fx_status fx_ctx_create(const fx_ctx_opts *opts, fx_ctx **out)
         c->params.slice_rows = std::min<int64_t>(std::max<int64_t>(o.slice_rows, 64), (int64_t)1 << 26);
     if (o.count_cap > 0) c->params.count_cap = o.count_cap;
     c->work.pool.budget = o.mem_budget_bytes > 0 ? (size_t)o.mem_budget_bytes : ((size_t)64 << 30);
+    if (o.run_index_bytes != 0) c->run_index_bytes = o.run_index_bytes;
     c->params.timing = (o.flags & FX_CTX_KERNEL_TIMING) != 0;
     c->params.no_digest = (o.flags & FX_CTX_NO_DIGEST) != 0;
     *out = c;

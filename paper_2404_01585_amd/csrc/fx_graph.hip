@@ -197,6 +197,33 @@ extern "C" fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *d, fx_graph
     G->dev.bptr = G->bptr_d.as<int64_t>();
     G->dev.nvl = (int32_t)G->vl_values.size();
     G->dev.nel = (int32_t)G->el_values.size();
+    G->dev.nkeys = G->dev.nvl * G->dev.nel;
+    G->dev.runoff = nullptr;
+    // label-run index: one offset per (vertex, key) plus the degree
+    const uint64_t K1 = (uint64_t)G->dev.nkeys + 1;
+    const uint64_t index_bytes = (uint64_t)nv * K1 * 4;
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < nv; v++) maxdeg = std::max<int64_t>(maxdeg, rp[v + 1] - rp[v]);
+    if (ctx->run_index_bytes >= 0 && index_bytes <= (uint64_t)ctx->run_index_bytes && maxdeg < 0xffffffffLL) {
+        std::vector<uint32_t> ro(nv * K1);
+        const int32_t nel = G->dev.nel;
+        parallel_for_chunks(nv, [&](int64_t a, int64_t b) {
+            for (int64_t v = a; v < b; v++) {
+                uint32_t *r = ro.data() + v * K1;
+                const int64_t base = rp[v], deg = rp[v + 1] - rp[v];
+                int64_t k = 0;
+                for (int64_t i = 0; i < deg; i++) {  // the row is sorted by key
+                    const uint64_t e = adj[base + i];
+                    const uint64_t key = (e >> 48) * (uint64_t)nel + ((e >> 32) & 0xffffu);
+                    while ((uint64_t)k <= key) r[k++] = (uint32_t)i;
+                }
+                while ((uint64_t)k < K1) r[k++] = (uint32_t)deg;
+            }
+        });
+        if (G->runoff.ensure(ro.size() * 4) == FX_OK &&
+            hipMemcpy(G->runoff.p, ro.data(), ro.size() * 4, hipMemcpyHostToDevice) == hipSuccess)
+            G->dev.runoff = G->runoff.as<uint32_t>();
+    }
     ctx->graphs++;
     *out = G;
     return FX_OK;

@@ -104,6 +104,7 @@ struct EngineWork {
 struct fx_ctx {
     int32_t device = 0;
     hipStream_t stream = nullptr;
+    int64_t run_index_bytes = (int64_t)8 << 30;  // < 0: no label-run index
     EngineParams params;
     std::atomic<int> graphs{0};
     fx_stats stats{};
@@ -117,7 +118,7 @@ struct fx_graph {
     std::vector<int32_t> vl_values, el_values;  // dense id -> caller's label
     std::unordered_map<int32_t, uint32_t> vl_map, el_map;
     std::vector<int64_t> bptr;                  // host copy of the label buckets' offsets
-    DevBuf rowp, adj, bucket, bptr_d;
+    DevBuf rowp, adj, bucket, bptr_d, runoff;
     FxGraphDev dev{};
 };
 

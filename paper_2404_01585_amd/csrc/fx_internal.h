@@ -11,6 +11,12 @@
 //                              label) form one contiguous run in ascending id.
 //   bucket int32 [nv]          vertex ids grouped by dense label, ascending id
 //   bptr   int64 [L+1]         start of each label group in bucket
+//   runoff uint32 [nv * (K+1)] label-run index, K = (vertex labels) x (edge labels):
+//                              runoff[v*(K+1) + k] = offset in v's row of the
+//                              first neighbour with key >= k (k = label * nel +
+//                              elabel); runoff[v*(K+1) + K] = degree.  Built when
+//                              it fits the index budget; otherwise runs are
+//                              found by binary search.
 //
 // A pattern plan fixes, for every pattern vertex i (in submitted order), its
 // dense label, its earlier neighbours b < i with the edge label of (b, i),
@@ -52,6 +58,8 @@ struct FxGraphDev {
     const int64_t *bptr;
     int32_t nvl;   // dense vertex labels
     int32_t nel;   // dense edge labels
+    const uint32_t *runoff;  // label-run index or nullptr
+    int32_t nkeys;           // nvl * nel
 };
 
 // Device-side counters of one query, read by the host once per step.

@@ -49,25 +49,45 @@ __device__ __forceinline__ int64_t lower_bound64(const uint64_t *__restrict__ a,
     return lo;
 }
 
-// Does the row of u contain the packed entry (label, elabel, id)?
-__device__ __forceinline__ bool has_entry(const FxGraphDev &g, int32_t u, uint64_t entry, uint32_t &bytes)
-{
-    int64_t lo = g.rowp[u], hi = g.rowp[u + 1];
-    bytes += 16;
-    int64_t k = lower_bound64(g.adj, lo, hi, entry, bytes);
-    return k < hi && g.adj[k] == entry;
-}
-
-// The run of neighbours of u with the given (label, elabel) key.
+// The run of neighbours of u with the given (label, elabel) key: two offsets
+// of the label-run index when the graph has one, else two binary searches
+// over u's row.
 __device__ __forceinline__ void run_of(const FxGraphDev &g, int32_t u, uint64_t key, int64_t &lo, int32_t &len,
                                        uint32_t &bytes)
 {
+    if (g.runoff) {
+        const uint32_t kidx = (uint32_t)(key >> 48) * (uint32_t)g.nel + (uint32_t)((key >> 32) & 0xffffu);
+        const uint32_t *r = g.runoff + (uint64_t)(uint32_t)u * (uint32_t)(g.nkeys + 1) + kidx;
+        const uint32_t a = r[0], b = r[1];
+        lo = g.rowp[u] + a;
+        len = (int32_t)(b - a);
+        bytes += 16;
+        return;
+    }
     int64_t a = g.rowp[u], b = g.rowp[u + 1];
     bytes += 16;
     int64_t s = lower_bound64(g.adj, a, b, key, bytes);
     int64_t e = lower_bound64(g.adj, s, b, key + (1ULL << 32), bytes);
     lo = s;
     len = (int32_t)(e - s);
+}
+
+// Does the row of u contain the packed entry (label, elabel, id)?  A binary
+// search inside the entry's (label, elabel) run.
+__device__ __forceinline__ bool has_entry(const FxGraphDev &g, int32_t u, uint64_t entry, uint32_t &bytes)
+{
+    int64_t lo, hi;
+    if (g.runoff) {
+        int32_t len;
+        run_of(g, u, entry & 0xffffffff00000000ULL, lo, len, bytes);
+        hi = lo + len;
+    } else {
+        lo = g.rowp[u];
+        hi = g.rowp[u + 1];
+        bytes += 16;
+    }
+    int64_t k = lower_bound64(g.adj, lo, hi, entry, bytes);
+    return k < hi && g.adj[k] == entry;
 }
 
 __device__ __forceinline__ bool is_used(const uint32_t *__restrict__ U, int32_t v)

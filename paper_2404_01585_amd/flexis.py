@@ -52,7 +52,8 @@ class FxError(RuntimeError):
 
 class CtxOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("hip_stream", ctypes.c_void_p), ("slice_rows", ctypes.c_int64),
-                ("count_cap", ctypes.c_int64), ("mem_budget_bytes", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+                ("count_cap", ctypes.c_int64), ("mem_budget_bytes", ctypes.c_int64),
+                ("run_index_bytes", ctypes.c_int64), ("flags", ctypes.c_uint32)]
 
 
 class GraphDesc(ctypes.Structure):
@@ -242,14 +243,15 @@ class Context:
     """fx_ctx: a device, a stream, and the workspace sizing."""
 
     def __init__(self, device: int = 0, stream: Optional[int] = None, slice_rows: int = 0, count_cap: int = 0,
-                 kernel_timing: bool = False, mem_budget_bytes: int = 0, no_digest: bool = False):
+                 kernel_timing: bool = False, mem_budget_bytes: int = 0, no_digest: bool = False,
+                 run_index_bytes: int = 0):
         lib = load_library()
         if stream is None:
             import torch
             torch.cuda.set_device(device)
             stream = _current_stream()
         self.stream = stream
-        self._opts = CtxOpts(device, stream or None, slice_rows, count_cap, mem_budget_bytes,
+        self._opts = CtxOpts(device, stream or None, slice_rows, count_cap, mem_budget_bytes, run_index_bytes,
                              (CTX_KERNEL_TIMING if kernel_timing else 0) | (CTX_NO_DIGEST if no_digest else 0))
         self._h = ctypes.c_void_p()
         _check(lib.fx_ctx_create(ctypes.byref(self._opts), ctypes.byref(self._h)))

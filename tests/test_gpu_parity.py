@@ -36,8 +36,9 @@ def ctx(torch_cuda):
 
 @pytest.fixture(scope="module")
 def ctx_small(torch_cuda):
-    # tiny slices: every level is cut into many slices with ragged tails
-    c = fx.Context(device=0, slice_rows=64)
+    # tiny slices: every level is cut into many slices with ragged tails; no
+    # label-run index, so runs come from binary searches
+    c = fx.Context(device=0, slice_rows=64, run_index_bytes=-1)
     yield c
 
 
@@ -280,7 +281,7 @@ def test_no_digest_counts(torch_cuda, er1k, slice_rows):
     oracle's enumeration exactly, as must support and verdict."""
     g = er1k
     cands = _mining_candidates(g, 20, 1.0, 3) + sample_patterns(g, 40, seed=17, kmin=2, kmax=6)
-    c = fx.Context(device=0, slice_rows=slice_rows, no_digest=True)
+    c = fx.Context(device=0, slice_rows=slice_rows, no_digest=True, run_index_bytes=(-1 if slice_rows else 0))
     with c.load_graph(g) as dg:
         _say("no digest, slice rows", slice_rows, "patterns", len(cands))
         got = dg.support_batch(cands, [20] * len(cands), [0.5] * len(cands), fx.MODE_FULL)
