@@ -28,6 +28,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -43,6 +45,14 @@ WORKLOADS = {
                            "3 edge labels; all candidates of mining levels 1-3 at sigma=200, lambda=1.0"),
     "cl100k-l2-l03": dict(graph="cl100k", sigma=200, lam=0.3, levels=2,
                           desc="as cl100k-l2 with lambda=0.3"),
+    "cl1m-s2000": dict(graph="cl1m", sigma=200, lam=1.0, sample=dict(count=2000, seed=33, kmin=3, kmax=7),
+                       desc="Chung-Lu 1M vertices / 8M edges (gamma 2.3), 30 Zipf(1.0) vertex labels, 1 edge "
+                            "label; 2,000 patterns of 3-7 vertices (trees, cycles, trees plus a chord) sampled "
+                            "as connected subgraphs of the graph, sigma=200, lambda=1.0"),
+    "rmat22-l2": dict(graph="rmat22", sigma=2000, lam=1.0, levels=2,
+                      desc="R-MAT scale 22 (4,194,304 vertices, 40M edges, a,b,c = 0.57,0.19,0.19), 50 Zipf(1.1) "
+                           "vertex labels, 4 edge labels, int64 offsets; all candidates of mining levels 1-2 at "
+                           "sigma=2000, lambda=1.0"),
     "er1k-l4": dict(graph="er1k", sigma=20, lam=1.0, levels=4,
                     desc="Erdos-Renyi 1K vertices / 4K edges, 5 uniform vertex labels, 1 edge label; all "
                          "candidates of mining levels 1-4 at sigma=20, lambda=1.0"),
@@ -54,11 +64,17 @@ def log(*a):
 
 
 def build_candidates(dg, g, spec):
-    """Candidate batch: every candidate of the first `levels` mining levels.
-    The level-wise loop itself runs here (untimed), with verdicts from the
-    device path."""
+    """Candidate batch: patterns sampled from the graph, or every candidate
+    of the first `levels` mining levels (the level-wise loop itself runs here,
+    untimed, with verdicts from the device path)."""
     from paper_2404_01585_amd import flexis as fx
     from paper_2404_01585_amd import mining
+    from paper_2404_01585_amd.synth import sample_patterns
+
+    if "sample" in spec:
+        sm = spec["sample"]
+        cands = sample_patterns(g, sm["count"], seed=sm["seed"], kmin=sm["kmin"], kmax=sm["kmax"])
+        return cands, [len(cands)]
 
     def evaluate(ps, sigma, lam):
         return dg.support_batch(ps, [sigma] * len(ps), [lam] * len(ps), fx.MODE_VERDICT)
@@ -81,29 +97,71 @@ def traffic_from_profile(kernel_src: str, workload: str):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(g, cands, spec, seconds: float, threads: int):
-    """The oracle (untuned) on the host cores: FULL-mode queries over a prefix
-    of the same batch, spread over a thread pool, bounded to ~`seconds`."""
-    from concurrent.futures import ThreadPoolExecutor
+_CPU = {}
 
+
+def _cpu_task(args):
+    """Worker of the CPU baseline: one FULL-mode oracle query.  The graph and
+    the batch are read once per worker from the file the parent wrote."""
+    path, i = args
     from oracle import oracle as O
 
-    OG = O.OracleGraph.of(g)
-    pats = [O.OraclePattern.of(p) for p in cands]
-    t0 = time.perf_counter()
-    deadline = t0 + seconds
-    done = 0
-    idx = 0
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        while idx < len(pats) and time.perf_counter() < deadline:
-            chunk = pats[idx:idx + 4 * threads]
-            list(ex.map(lambda p: O.query(OG, p, spec["sigma"], spec["lam"], O.FULL), chunk))
-            idx += len(chunk)
-            done += len(chunk)
-    dt = time.perf_counter() - t0
+    if _CPU.get("path") != path:
+        z = np.load(path)
+        _CPU.update(path=path, g=O.OracleGraph(z["row_ptr"], z["col"], z["vlabel"], z["elabel"]),
+                    pats=[O.OraclePattern(p["vlabel"], p["edges"], p["elabel"])
+                          for p in json.loads(str(z["patterns"]))],
+                    sigma=int(z["sigma"]), lam=float(z["lam"]))
+    O.query(_CPU["g"], _CPU["pats"][i], _CPU["sigma"], _CPU["lam"], O.FULL)
+    return i
+
+
+def start_cpu_pool(threads: int):
+    """Worker processes of the CPU baseline, started before this process
+    touches the GPU (they never do)."""
+    import multiprocessing as mp
+
+    return mp.get_context("spawn").Pool(threads)
+
+
+def cpu_baseline(pool, threads: int, g, cands, spec, seconds: float):
+    """The oracle (untuned) on the host cores: FULL-mode queries over the
+    batch in order, one per worker process, for about `seconds`; the rate is
+    the queries finished by then over the wall time (queries still running
+    at the deadline are not counted)."""
+    import tempfile
+
+    fd, path = tempfile.mkstemp(suffix=".npz", prefix="fx_cpu_")
+    os.close(fd)
+    try:
+        pats = [dict(vlabel=list(map(int, p.vlabel)), edges=[list(map(int, e)) for e in p.edges],
+                     elabel=list(map(int, p.elabel))) for p in cands]
+        with open(path, "wb") as f:
+            np.savez(f, row_ptr=g.row_ptr, col=g.col, vlabel=g.vlabel, elabel=g.elabel,
+                     patterns=np.array(json.dumps(pats)), sigma=spec["sigma"], lam=spec["lam"])
+        t0 = time.perf_counter()
+        deadline = t0 + seconds
+        done = 0
+        it = pool.imap_unordered(_cpu_task, [(path, i) for i in range(len(cands))])
+        while True:
+            left = deadline - time.perf_counter()
+            if left <= 0:
+                break
+            try:
+                it.next(timeout=left)
+            except StopIteration:
+                break
+            except __import__("multiprocessing").TimeoutError:
+                break
+            done += 1
+        dt = time.perf_counter() - t0
+    finally:
+        pool.terminate()
+        pool.join()
+        os.unlink(path)
     return dict(value=done / dt, unit="patterns/s", cores=threads, kind="oracle",
-                sample=f"first {done} of {len(pats)} candidates of the same batch, FULL mode "
-                       f"(support + count + digest), {dt:.1f} s wall")
+                sample=f"{done} of {len(cands)} candidates of the same batch finished in {dt:.1f} s wall, "
+                       f"taken in batch order, FULL mode (support + count + digest), one process per core")
 
 
 def serving_queries(g, count: int, seed: int):
@@ -227,9 +285,12 @@ def main():
     ap.add_argument("--workload", default="cl100k-l2", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="full", choices=["full", "verdict"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--count-cap", type=int, default=0, help="embedding count cap (0: 2^62)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (untimed) before the timed steps")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: a later run with the same file reuses the same launch shape")
     ap.add_argument("--digest", action="store_true",
                     help="also hash every embedding (FULL-mode digest); counts are exact either way")
     ap.add_argument("--plain-seconds", type=float, default=5.0,
@@ -269,7 +330,9 @@ def main():
                                    "notes but not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import numpy as np
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    pool = None if args.no_cpu else start_cpu_pool(threads)
+
     import torch
 
     from paper_2404_01585_amd import flexis as fx
@@ -281,7 +344,8 @@ def main():
     log(f"[bench] graph {spec['graph']}: {g.num_vertices} vertices, {g.num_adj // 2} edges "
         f"({time.perf_counter() - t:.1f} s)")
     torch.cuda.set_device(0)
-    ctx = fx.Context(device=0, kernel_timing=not args.no_timing, no_digest=not args.digest)
+    ctx = fx.Context(device=0, kernel_timing=not args.no_timing, no_digest=not args.digest,
+                     count_cap=args.count_cap)
     dg = ctx.load_graph(g)
     t = time.perf_counter()
     cands, per_level = build_candidates(dg, g, spec)
@@ -294,7 +358,7 @@ def main():
     tuned = None
     if not args.no_tune:
         t = time.perf_counter()
-        tuned = dg.autotune(batch, spec["sigma"], spec["lam"], mode)
+        tuned = dg.autotune(batch, spec["sigma"], spec["lam"], mode, cache_path=args.tune_cache)
         log(f"[bench] autotune {tuned} ({time.perf_counter() - t:.1f} s)")
     for w in range(args.warmup):
         dg.support_batch_array(batch, spec["sigma"], spec["lam"], mode)
@@ -354,9 +418,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        threads = max(1, min(16, len(os.sched_getaffinity(0))))
-        log(f"[bench] cpu baseline: oracle on {threads} threads for ~{args.cpu_seconds} s")
-        cpu = cpu_baseline(g, cands, spec, args.cpu_seconds, threads)
+        log(f"[bench] cpu baseline: oracle on {threads} processes for ~{args.cpu_seconds} s")
+        cpu = cpu_baseline(pool, threads, g, cands, spec, args.cpu_seconds)
 
     line = {
         "metric": "candidate patterns/s (support queries, FULL mode) at 1 GPU",
@@ -384,6 +447,8 @@ def main():
                                     int(results["steps"].max())],
         "greedy_rounds_max": int(results["rounds"].max()),
         "syncs_per_step": st["syncs"] / args.steps,
+        "reoffered_candidates_per_step": st["reoffered"] / args.steps,
+        "stack_promotions_per_step": st["promotions"] / args.steps,
         "device_steps_per_step": st["steps"] / args.steps,
         "plain_form": plain,
         "serving": serving,

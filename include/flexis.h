@@ -212,7 +212,13 @@ fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, co
  *               counted on the device: candidate entries, partial rows and
  *               their run descriptors, every binary-search step of an
  *               adjacency test (8 bytes) and the used-set words read.
- *   steps, syncs, queries   host-side counts. */
+ *               Candidates of a slice that were probed but left for a later
+ *               step (a slice stops at its row cap) are not counted.
+ *   steps, syncs, queries   host-side counts.
+ *   reoffered   candidates probed in a slice that stopped at its row cap and
+ *               offered again in a later step (wasted probe work).
+ *   promotions  stacks moved to a larger slice capacity because few queries
+ *               were left to share the device. */
 typedef struct {
     uint64_t probe_launches;
     double probe_ms;
@@ -225,6 +231,8 @@ typedef struct {
     uint64_t steps;
     uint64_t syncs;
     uint64_t queries;
+    uint64_t reoffered;
+    uint64_t promotions;
 } fx_stats;
 
 /* Copies the context's statistics into *out; reset != 0 zeroes them after. */

@@ -78,7 +78,7 @@ RegionPool::~RegionPool()
         if (c.base) (void)hipFree(c.base);
 }
 
-fx_status RegionPool::take(size_t bytes, void **out)
+fx_status RegionPool::take(size_t bytes, void **out, bool quiet)
 {
     bytes = (bytes + 255) & ~(size_t)255;
     for (auto &c : chunks)
@@ -93,6 +93,7 @@ fx_status RegionPool::take(size_t bytes, void **out)
             }
     if (held + bytes > budget) {
         *out = nullptr;
+        if (quiet) return FX_ENOMEM;
         return fx_fail(FX_ENOMEM, "query region of %zu bytes does not fit in the %zu-byte budget", bytes, budget);
     }
     Chunk c;
@@ -100,6 +101,8 @@ fx_status RegionPool::take(size_t bytes, void **out)
     hipError_t e = hipMalloc((void **)&c.base, c.size);
     if (e != hipSuccess) {
         *out = nullptr;
+        (void)hipGetLastError();
+        if (quiet) return FX_ENOMEM;
         return fx_fail(FX_ENOMEM, "hipMalloc(%zu) for query regions failed: %s", c.size, hipGetErrorString(e));
     }
     held += c.size;

@@ -149,8 +149,10 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
 
 namespace {
 
-constexpr uint32_t kLastSpanMin = 1024;
-constexpr uint64_t kCountSpan = 1ull << 22;  // last-vertex candidates per counting step
+constexpr uint64_t kCountSpan = 1ull << 22;  // least last-vertex candidates per counting step
+constexpr double kFill = 0.8;                // aim a slice at this fraction of the rows it may write
+constexpr int64_t kPromoteCap = 1 << 23;     // largest slice capacity a stack is moved to
+constexpr int32_t kPromoteAfter = 16;        // steps a query has run before its stack may grow
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -178,7 +180,11 @@ struct FxQuery {
     uint64_t T[FX_MAXN + 1]{}, cur[FX_MAXN + 1]{};
     int64_t nparts[FX_MAXN + 1]{};
     int64_t rank_base = 0;
-    uint32_t last_span = 0;
+    uint32_t last_span = 0;                // complete embeddings per greedy slice
+    double rate[FX_MAXN + 1]{};            // passing fraction of each level's last slice
+    uint64_t alg_probe_seen = 0;           // probe bytes read back so far
+    double alg_probe_credit = 0;           // of those, the share of the candidates taken
+    uint64_t probed_support = 0;           // candidates probed in the support phase
     int32_t steps = 0;
     int64_t listed = 0;
     // the segment of the current step (-1: none)
@@ -275,6 +281,8 @@ FxEngine::FxEngine(fx_graph *G, EngineWork *W, hipStream_t s, const EngineParams
     : G_(G), W_(W), s_(s), P_(p), stats_(stats), t0_(std::chrono::steady_clock::now())
 {
     if (P_.max_active < 1) P_.max_active = 1;
+    // a segment's span is a 32-bit count
+    P_.step_candidates = std::min<uint64_t>(std::max<uint64_t>(P_.step_candidates, FX_MAX_TILE), 1ull << 31);
     for (int k = P_.max_active - 1; k >= 0; k--) free_slots_.push_back(k);
 }
 
@@ -320,6 +328,7 @@ void FxEngine::add(FxRequest *r)
     q->phase = r->kind == FX_Q_LIST ? PH_LIST : PH_SUPPORT;
     q->cap = P_.slice_rows;
     q->last_span = (uint32_t)std::min<int64_t>(P_.last_span_init, q->cap);
+    for (auto &r : q->rate) r = 1.0;
     pending_.push_back(std::move(q));
 }
 
@@ -328,13 +337,13 @@ fx_status FxEngine::finish(FxQuery &q)
     FxRequest &r = *q.req;
     const FxSummary &S = W_->sums_h.as<FxSummary>()[q.slot];
     if (q.phase == PH_LIST) {
-        *r.list_count = (int64_t)S.count;
+        *r.list_count = q.listed;  // rows written at the last level (a capped slice re-offers the rest)
     } else {
         fx_result res{};
         res.tau = q.tau;
         res.steps = q.steps;
         res.rounds = (int32_t)S.rounds;
-        res.alg_bytes = S.alg_probe + S.alg_scatter;
+        res.alg_bytes = (uint64_t)q.alg_probe_credit + S.alg_scatter;
         res.device_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0_).count();
         if (r.kind == FX_Q_VERDICT) {
             res.frequent = (int64_t)S.support >= q.tau_eff;
@@ -367,7 +376,7 @@ fx_status FxEngine::finish(FxQuery &q)
         }
         *r.out = res;
     }
-    stats_->probe_alg_bytes += S.alg_probe;
+    stats_->probe_alg_bytes += (uint64_t)q.alg_probe_credit;
     stats_->scatter_alg_bytes += S.alg_scatter;
     stats_->queries++;
     W_->pool.give(q.region, q.region_bytes);
@@ -422,6 +431,67 @@ fx_status FxEngine::admit()
     return FX_OK;
 }
 
+// Moves q's stack to a region with new_cap rows per level (when the pool has
+// room; otherwise q keeps its stack).  Every level that still has candidates
+// left is copied on the stream, so the next step sees the same stack with
+// room for larger slices.
+fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
+{
+    const int64_t nv = G_->nv;
+    FxQuery old;
+    old.n = q.n;
+    old.req = q.req;
+    old.cap = q.cap;
+    old.region = q.region;
+    old.region_bytes = q.region_bytes;
+    for (int l = 0; l <= q.n; l++) old.lev[l] = q.lev[l];
+    old.U = q.U;
+    old.plan = q.plan;
+    old.sel_rows = q.sel_rows;
+    old.sel_rank = q.sel_rank;
+    q.cap = new_cap;
+    const size_t bytes = region_size(q, nv);
+    void *region = nullptr;
+    if (W_->pool.take(bytes, &region, true) != FX_OK) {
+        q.cap = old.cap;
+        return FX_OK;
+    }
+    q.region = region;
+    q.region_bytes = bytes;
+    carve(q, nv);
+    auto cp = [&](void *dst, const void *src, size_t b) -> fx_status {
+        if (b) FX_HIP(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, s_));
+        return FX_OK;
+    };
+    FX_TRY(cp(q.lev[0].lo, old.lev[0].lo, 8));
+    FX_TRY(cp(q.lev[0].len, old.lev[0].len, 4));
+    FX_TRY(cp(q.lev[0].anc, old.lev[0].anc, 1));
+    FX_TRY(cp(q.lev[0].off, old.lev[0].off, 16));
+    const int deep = deepest_open_level(q);
+    for (int l = 1; l <= deep; l++) {
+        const size_t np = (size_t)q.nparts[l];
+        if (np == 0) continue;
+        FX_TRY(cp(q.lev[l].rows, old.lev[l].rows, np * l * 4));
+        FX_TRY(cp(q.lev[l].lo, old.lev[l].lo, np * 8));
+        FX_TRY(cp(q.lev[l].len, old.lev[l].len, np * 4));
+        FX_TRY(cp(q.lev[l].anc, old.lev[l].anc, np));
+        FX_TRY(cp(q.lev[l].off, old.lev[l].off, (np + 1) * 8));
+    }
+    FX_TRY(cp(q.U, old.U, ((size_t)nv + 31) / 32 * 4));
+    FX_TRY(cp(q.plan, old.plan, sizeof(FxPlan)));
+    if (q.sel_rows) {
+        const size_t k = (size_t)nv / q.n + 1;
+        FX_TRY(cp(q.sel_rows, old.sel_rows, k * q.n * 4));
+        FX_TRY(cp(q.sel_rank, old.sel_rank, k * 8));
+    }
+    // later work on the stream is ordered after these copies, so the old
+    // region may be handed out again at once
+    W_->pool.give(old.region, old.region_bytes);
+    q.last_span = (uint32_t)std::min<int64_t>(P_.last_span_init, q.cap);
+    stats_->promotions++;
+    return FX_OK;
+}
+
 fx_status FxEngine::step()
 {
     if (!buffers_ready_) {  // grow-only buffers sized for these parameters
@@ -457,18 +527,45 @@ fx_status FxEngine::step()
     uint32_t nblocks = 0;
     int any_inner = 0, any_greedy = 0;
     const size_t A = active_.size();
-    for (auto &qp : active_) qp->seg_l = -1;
+    uint64_t n_open = 0;
+    for (auto &qp : active_) {
+        qp->seg_l = -1;
+        n_open += deepest_open_level(*qp) >= 0;
+    }
+    // a query's fair share of the step; a slice may take more candidates
+    // than its level holds rows when few of them pass (the row cap bounds
+    // what is written, see k_scatter)
+    const uint64_t share = P_.step_candidates / std::max<uint64_t>(n_open, 1);
+    // long-running queries that now have the device nearly to themselves get
+    // room for slices of their share.  In the support phase the slice size is
+    // also the granularity at which selections prune the search through U:
+    // larger slices expand partials that a selection would have removed
+    // (measured: twice the probe work on cl1m).  A support-phase stack grows
+    // only while U has removed under 1/64 of its candidates.
+    const FxSummary *sums_prev = W_->sums_h.as<FxSummary>();
+    for (auto &qp : active_) {
+        FxQuery &q = *qp;
+        if (q.phase == PH_SUPPORT && (q.probed_support == 0 || sums_prev[q.slot].ufiltered * 64 > q.probed_support))
+            continue;
+        if (q.steps < kPromoteAfter || q.cap >= kPromoteCap || share < 4 * (uint64_t)q.cap) continue;
+        if (deepest_open_level(q) < 0) continue;
+        uint64_t left = 0;  // largest candidate range still open: no slice needs more rows
+        for (int l = 0; l < q.n; l++) left = std::max<uint64_t>(left, q.T[l] - q.cur[l]);
+        int64_t nc = q.cap;
+        while (nc < kPromoteCap && (uint64_t)nc * 2 <= share && (uint64_t)nc < left) nc *= 2;
+        if (nc > q.cap) FX_TRY(promote(q, nc));
+    }
     for (size_t k = 0; k < A && budget > 0; k++) {
         FxQuery &q = *active_[(rot_ + k) % A];
         const int l = deepest_open_level(q);
         if (l < 0) continue;
         const bool last = (l == q.n - 1);
         int kind, flags = 0;
-        uint64_t cap;
+        uint64_t out_cap = (uint64_t)q.cap;  // rows the segment may write
         if (q.phase == PH_SUPPORT) {
             flags = FX_PROBE_UFILTER;
             kind = last ? FX_SEG_GREEDY : FX_SEG_INNER;
-            cap = last ? std::min<uint64_t>(q.last_span, (uint64_t)q.cap) : (uint64_t)q.cap;
+            if (last) out_cap = std::min<uint64_t>(q.last_span, (uint64_t)q.cap);
         } else if (q.phase == PH_COUNT) {
             // without a digest, a leaf last vertex is counted in closed form
             // from the partials of vertex n-2 (level n-1 is never built)
@@ -476,18 +573,20 @@ fx_status FxEngine::step()
             const bool end = leaf ? (l == q.n - 2) : last;
             flags = end ? (leaf ? FX_PROBE_LEAF : (FX_PROBE_COUNT | (P_.no_digest ? 0 : FX_PROBE_HASH))) : 0;
             kind = end ? FX_SEG_COUNT : FX_SEG_INNER;
-            cap = end ? kCountSpan : (uint64_t)q.cap;
         } else {
-            flags = last ? FX_PROBE_COUNT : 0;
             kind = last ? FX_SEG_LIST : FX_SEG_INNER;
-            cap = (uint64_t)q.cap;
         }
-        const uint64_t span = std::min<uint64_t>(std::min<uint64_t>(q.T[l] - q.cur[l], cap), budget);
+        uint64_t want;
+        if (kind == FX_SEG_COUNT) {
+            want = std::max<uint64_t>(kCountSpan, share);
+        } else {
+            // expected passes = rate * span: aim at kFill of the row cap
+            const double r = std::max(q.rate[l], 1e-9);
+            want = r >= 1.0 ? out_cap : (uint64_t)std::min(kFill * (double)out_cap / r, 2147483648.0);
+            want = std::min<uint64_t>(std::max<uint64_t>(want, out_cap), std::max<uint64_t>(out_cap, share));
+        }
+        const uint64_t span = std::min<uint64_t>(std::min<uint64_t>(q.T[l] - q.cur[l], want), budget);
         if (span == 0) continue;
-        // every passing candidate of a writing segment takes one row of level l+1
-        if (kind != FX_SEG_COUNT && span > (uint64_t)q.cap)
-            return fx_fail(FX_EDEVICE, "internal: slice of %llu candidates exceeds the level capacity %lld",
-                           (unsigned long long)span, (long long)q.cap);
         FxSeg &S = segs[nsegs];
         S.in = q.lev[l];
         S.out = q.lev[l + 1];
@@ -500,6 +599,7 @@ fx_status FxEngine::step()
         S.t0 = q.cur[l];
         S.rank_base = q.rank_base;
         S.span = (uint32_t)span;
+        S.out_cap = (uint32_t)std::min<uint64_t>(out_cap, 0xffffffffu);
         S.blk0 = nblocks;
         S.n = q.n;
         S.l = l;
@@ -553,7 +653,16 @@ fx_status FxEngine::step()
         const FxSummary &S = sums_h[q.slot];
         if (S.error) return fx_fail(FX_EDEVICE, "device consistency check failed (greedy round limit)");
         const int l = q.seg_l;
-        q.cur[l] = q.seg_t0 + q.seg_span;
+        const uint64_t taken = S.consumed;
+        if (taken == 0 || taken > q.seg_span)
+            return fx_fail(FX_EDEVICE, "internal: segment took %llu of %u candidates", (unsigned long long)taken,
+                           q.seg_span);
+        q.cur[l] = q.seg_t0 + taken;
+        stats_->reoffered += q.seg_span - taken;
+        if (q.phase == PH_SUPPORT) q.probed_support += q.seg_span;
+        q.rate[l] = (double)S.passes / (double)q.seg_span;
+        q.alg_probe_credit += (double)(S.alg_probe - q.alg_probe_seen) * (double)taken / (double)q.seg_span;
+        q.alg_probe_seen = S.alg_probe;
         q.steps++;
         const uint64_t N = S.total_out;
         if (q.seg_kind == FX_SEG_INNER) {
@@ -562,10 +671,6 @@ fx_status FxEngine::step()
             q.cur[l + 1] = 0;
         } else if (q.seg_kind == FX_SEG_GREEDY) {
             q.rank_base += (int64_t)N;
-            // keep the greedy's slices near a few thousand embeddings
-            if (N * 8 < q.seg_span) q.last_span = (uint32_t)std::min<int64_t>(2 * (int64_t)q.last_span, q.cap);
-            else if (N > 8192) q.last_span = std::max<uint32_t>(q.last_span / 2, kLastSpanMin);
-            q.last_span = (uint32_t)std::min<int64_t>(q.last_span, q.cap);
         } else if (q.seg_kind == FX_SEG_LIST) {
             FxRequest &r = *q.req;
             const int64_t take = std::min<int64_t>((int64_t)N, std::max<int64_t>(0, r.list_cap - q.listed));

@@ -75,7 +75,8 @@ struct RegionPool {
     size_t in_use = 0, held = 0, budget = 0;
     static constexpr size_t kChunk = (size_t)4 << 30;
     ~RegionPool();
-    fx_status take(size_t bytes, void **out);  // FX_ENOMEM when nothing fits within the budget
+    // FX_ENOMEM when nothing fits within the budget (quiet: no error message is recorded)
+    fx_status take(size_t bytes, void **out, bool quiet = false);
     void give(void *p, size_t bytes);
 };
 
@@ -172,6 +173,7 @@ public:
 
 private:
     fx_status admit();
+    fx_status promote(FxQuery &q, int64_t new_cap);
     fx_status finish(FxQuery &q);
     void done(FxRequest *r);
     fx_graph *G_;

@@ -74,7 +74,10 @@ struct FxSummary {
     unsigned long long alg_probe;   // algorithmic bytes of the probe launches
     unsigned long long alg_scatter; // algorithmic bytes of the scatter launches
     unsigned long long error;       // nonzero: a device-side consistency check failed
-    unsigned long long pad[6];
+    unsigned long long passes;      // candidates of the last segment that passed (before the row cap)
+    unsigned long long consumed;    // candidates of the last segment taken (the rest are offered again)
+    unsigned long long ufiltered;   // candidates the used set U has removed so far
+    unsigned long long pad[3];
 };
 
 // One level of a slice stack: partial embeddings with l matched vertices
@@ -116,6 +119,8 @@ struct FxSeg {
     uint64_t t0;            // first flattened candidate of the slice
     int64_t rank_base;      // rank of the first complete embedding this step writes
     uint32_t span;          // candidates in the slice
+    uint32_t out_cap;       // rows of level l+1 this segment may write; the candidates after the
+                            // out_cap-th passing one are left for a later step
     uint32_t blk0;          // first workgroup of this segment in the launch (FX_BS * items candidates each)
     int32_t n, l;
     int32_t flags;          // FX_PROBE_*

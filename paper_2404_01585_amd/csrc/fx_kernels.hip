@@ -305,7 +305,7 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
     const bool count = (flags & FX_PROBE_COUNT) != 0;
     const bool leaf = (flags & FX_PROBE_LEAF) != 0;
     const bool hash = (flags & FX_PROBE_HASH) != 0;
-    uint32_t passed = 0, bytes = 0;
+    uint32_t passed = 0, bytes = 0, uout = 0;
     unsigned long long cnt = 0;
     uint64_t h1 = 0, h2 = 0;
 #pragma unroll
@@ -322,6 +322,7 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
             bool ok = true;
             if (ufilter) {
                 ok = !touches_used(S.U, x, l);
+                uout += ok ? 0u : 1u;
                 bytes += 4u * (uint32_t)(l + 1);
             }
             if (ok) ok = feasible(g, S.plan, n, l, x, bytes);
@@ -359,14 +360,16 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
     }
     {
         unsigned long long b = bytes;
-        uint32_t pc = passed;
+        uint32_t pc = passed, uo = uout;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             b += __shfl_xor(b, o);
             pc += __shfl_xor(pc, o);
+            uo += __shfl_xor(uo, o);
         }
         if (__lane_id() == 0) {
             if (b) atomicAdd(&S.sum->alg_probe, b);
+            if (uo) atomicAdd(&S.sum->ufiltered, (unsigned long long)uo);
             wcnt[threadIdx.x >> 6] = pc;
         }
     }
@@ -407,7 +410,11 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt
 // candidate run of the next pattern vertex for inner levels.  For inner
 // segments it also writes each new row's prefix of run lengths within this
 // workgroup's rows to off[] and the workgroup's total to lsum[]; k_fix_off
-// adds the workgroup offsets after a scan of lsum.
+// adds the workgroup offsets after a scan of lsum.  A segment writes at most
+// out_cap rows: when more candidates pass, writing stops at the out_cap-th
+// and the summary records how many candidates that took (the rest are
+// probed again in a later step), so a slice may span many more candidates
+// than the level holds rows.
 template <int ITEMS>
 __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
                                                    const uint32_t *__restrict__ blk0s, int32_t nsegs,
@@ -423,9 +430,13 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
     const FxSeg &S = segs[si];
     const int32_t l = S.l, n = S.n;
     const uint64_t seg_base = boff[S.blk0];
+    const uint64_t seg_pass = boff[S.blk0 + (S.span + TILE - 1) / TILE] - seg_base;
+    const uint64_t cap = S.kind == FX_SEG_COUNT ? seg_pass : (uint64_t)S.out_cap;
+    const bool overflow = seg_pass > cap;
     if (blockIdx.x == S.blk0 && threadIdx.x == 0) {
-        const uint32_t nblk = (S.span + TILE - 1) / TILE;
-        S.sum->total_out = boff[S.blk0 + nblk] - seg_base;
+        S.sum->passes = seg_pass;
+        S.sum->total_out = overflow ? cap : seg_pass;
+        if (!overflow) S.sum->consumed = S.span;
     }
     if (S.kind != FX_SEG_INNER && threadIdx.x == 0) lsum[blockIdx.x] = 0;
     if (S.kind == FX_SEG_COUNT) return;  // nothing is written for a counting segment
@@ -450,11 +461,13 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
-        // flag read per candidate; row and run descriptor written per survivor
-        bytes += (tl < S.span ? 1u : 0u) + (f[it] ? 4u * (uint32_t)w1 : 0u) + ((f[it] && w1 < n) ? 21u : 0u);
         lens[it] = 0;
         p_out[it] = pos + (uint64_t)__popcll(bal[it] & lanemask_lt());
         for (uint32_t w = 0; w < wave; w++) p_out[it] += wcnt[it][w];
+        if (f[it] && overflow && p_out[it] == cap - 1) S.sum->consumed = tl + 1;  // the last row that fits
+        f[it] = f[it] && p_out[it] < cap;
+        // flag read per candidate; row and run descriptor written per survivor
+        bytes += (tl < S.span ? 1u : 0u) + (f[it] ? 4u * (uint32_t)w1 : 0u) + ((f[it] && w1 < n) ? 21u : 0u);
         if (f[it]) {
             const uint64_t t = S.t0 + tl;
             Cand x;
@@ -545,13 +558,14 @@ __global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ seg
     const FxSeg &S = segs[si];
     if (S.kind != FX_SEG_INNER) return;
     const uint64_t seg_base = boff[S.blk0];
-    const uint64_t r0 = boff[blockIdx.x] - seg_base, r1 = boff[blockIdx.x + 1] - seg_base;
+    const uint64_t cap = S.out_cap;
+    const uint64_t r0 = min(boff[blockIdx.x] - seg_base, cap), r1 = min(boff[blockIdx.x + 1] - seg_base, cap);
     const uint64_t add = loff[blockIdx.x] - loff[S.blk0];
     if (add)
         for (uint64_t r = r0 + threadIdx.x; r < r1; r += FX_BS) S.out.off[r] += (int64_t)add;
     if (blockIdx.x == S.blk0 && threadIdx.x == 0) {
         const uint32_t nblk = (S.span + TILE - 1) / TILE;
-        const uint64_t N = boff[S.blk0 + nblk] - seg_base;
+        const uint64_t N = min(boff[S.blk0 + nblk] - seg_base, cap);
         const uint64_t total = loff[S.blk0 + nblk] - loff[S.blk0];
         S.out.off[N] = (int64_t)total;
         S.sum->t_next = total;
@@ -585,13 +599,58 @@ __device__ __forceinline__ bool used_coherent(const uint32_t *U, int32_t v)
     return (w >> ((uint32_t)v & 31u)) & 1u;
 }
 
+// Sequential finish of a chunk by one wave, once the parallel rounds make
+// little progress (long chains of overlapping embeddings need one round per
+// link).  The wave walks the undecided embeddings in rank order, 64 at a
+// time: a lane whose slots are taken is dropped; otherwise the lowest
+// undecided lane is the lowest-ranked undecided embedding, so it is selected,
+// its slots are taken, and the lanes sharing a slot with it are dropped.
+// Decided embeddings of the rounds before are consistent with the sequential
+// greedy (a selected embedding has no undecided lower-ranked neighbour), so
+// the result is still the sequential greedy's.  Selections are marked 3; the
+// caller writes them out.
+__device__ void greedy_tail(uint8_t *state, const uint16_t *slot, unsigned long long *hval, uint32_t nb, int32_t n)
+{
+    const uint32_t lane = threadIdx.x;  // wave 0
+    for (uint32_t base = 0; base < nb; base += 64) {
+        const uint32_t e = base + lane;
+        const bool und = e < nb && state[e] == 0;
+        uint32_t s[FX_MAXN];
+        bool blocked = false;
+#pragma unroll
+        for (int j = 0; j < FX_MAXN; j++) {
+            s[j] = (und && j < n) ? (uint32_t)slot[e * n + j] : 0xffffffffu;
+            if (und && j < n) blocked = blocked || hval[s[j]] == 0ULL;
+        }
+        if (und && blocked) state[e] = 2;
+        uint64_t M = __ballot(und && !blocked);
+        while (M) {
+            const uint32_t f = (uint32_t)__ffsll((unsigned long long)M) - 1;
+            const uint32_t ef = base + f;
+            bool conf = false;
+            for (int j = 0; j < n; j++) {
+                const uint32_t fs = slot[ef * n + j];
+#pragma unroll
+                for (int k = 0; k < FX_MAXN; k++) conf = conf || s[k] == fs;
+                if (lane == (uint32_t)j) hval[fs] = 0ULL;
+            }
+            const bool in_m = (M >> lane) & 1ull;
+            const bool drop = in_m && lane != f && conf;
+            if (lane == f) state[e] = 3;
+            if (drop) state[e] = 2;
+            M &= ~(1ull << f);
+            M &= ~__ballot(drop);
+        }
+    }
+}
+
 __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs)
 {
     static_assert(FX_GREEDY_H == 4096, "lds_hash takes the top 12 bits");
     __shared__ int32_t hkey[FX_GREEDY_H];
     __shared__ unsigned long long hval[FX_GREEDY_H];
     __shared__ uint16_t slot[FX_GREEDY_VN];
-    __shared__ uint8_t state[FX_GREEDY_VN];  // 0 undecided, 1 selected, 2 out
+    __shared__ uint8_t state[FX_GREEDY_VN];  // 0 undecided, 1 selected, 2 out, 3 selected by the tail
     __shared__ uint32_t undecided;
     const FxSeg &S = segs[blockIdx.x];
     if (S.kind != FX_SEG_GREEDY) return;
@@ -599,6 +658,7 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
     const uint64_t N = S.sum->total_out;
     const int32_t *rows = S.out.rows;
     const uint32_t B = FX_GREEDY_VN / (uint32_t)n;  // embeddings per chunk
+    constexpr uint32_t kTailBelow = 64;              // undecided embeddings one wave finishes
     uint32_t rounds_total = 0;
     for (uint64_t c0 = 0; c0 < N; c0 += B) {
         const uint32_t nb = (uint32_t)((N - c0) < B ? (N - c0) : B);
@@ -626,6 +686,8 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
             }
         }
         __syncthreads();
+        bool tail = false;
+        uint32_t prev_und = nb;
         for (uint32_t r = 0; r <= nb; r++) {  // a chunk needs at most nb rounds
             if (threadIdx.x == 0) undecided = 0;
             for (uint32_t e = threadIdx.x; e < nb; e += FX_BS) {
@@ -669,7 +731,30 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
             rounds_total++;
             __syncthreads();  // everyone has read `undecided` before it is reset
             if (und == 0) break;
+            // few left, or a round that decided under 1/8 of them: chains
+            if (und <= kTailBelow || (r >= 1 && (prev_und - und) * 8 < prev_und)) {
+                tail = true;
+                break;
+            }
+            prev_und = und;
             if (r == nb && threadIdx.x == 0) atomicAdd(&S.sum->error, 1ULL);  // cannot happen
+        }
+        if (tail) {  // uniform
+            if (threadIdx.x < 64) greedy_tail(state, slot, hval, nb, n);
+            __syncthreads();
+            for (uint32_t e = threadIdx.x; e < nb; e += FX_BS) {
+                if (state[e] != 3) continue;
+                const int32_t *row = rows + (c0 + e) * n;
+                for (int j = 0; j < n; j++) {
+                    const uint32_t v = (uint32_t)row[j];
+                    atomicOr(&S.U[v >> 5], 1u << (v & 31u));
+                }
+                const unsigned long long pos = atomicAdd(&S.sum->support, 1ULL);
+                if (S.sel_rows) {
+                    for (int j = 0; j < n; j++) S.sel_rows[pos * n + j] = row[j];
+                    S.sel_rank[pos] = S.rank_base + (int64_t)(c0 + e);
+                }
+            }
         }
         __syncthreads();
     }

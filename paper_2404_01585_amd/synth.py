@@ -90,7 +90,7 @@ def csr_from_edges(nv: int, u: np.ndarray, v: np.ndarray, el: np.ndarray,
     src = np.concatenate([u, v])
     dst = np.concatenate([v, u])
     lab = np.concatenate([el, el])
-    order = np.lexsort((dst, src))
+    order = np.argsort(src * nv + dst)  # keys are unique: the (src, dst) order
     src, dst, lab = src[order], dst[order], lab[order]
     counts = np.bincount(src, minlength=nv)
     row_ptr = np.zeros(nv + 1, dtype=np.int64)

@@ -138,6 +138,27 @@ def test_er1k_sampled_patterns(ctx, ctx_small, er1k):
             verdict_match(ds, g, p, 20, 0.3)
 
 
+def test_capped_slices_and_promotion(ctx_small, er1k):
+    """Slices that stop at their row cap (the rest offered again) and stacks
+    moved to a larger capacity when few queries are left give the oracle's
+    results, alone and in a batch."""
+    g = er1k
+    pats = sample_patterns(g, 12, seed=77, kmin=4, kmax=7)
+    ctx_small.stats(reset=True)
+    with ctx_small.load_graph(g) as ds:
+        alone = []
+        for i, p in enumerate(pats):
+            _say("capped slices, pattern", i, "n", p.n, "m", p.m)
+            alone.append(full_match(ds, g, p, 20, 1.0))
+        mix = ds.support_batch(pats, [20] * len(pats), [1.0] * len(pats), fx.MODE_FULL)
+        for a, b in zip(alone, mix):
+            for k in ("support", "frequent", "embedding_count", "digest"):
+                assert a[k] == b[k], k
+    st = ctx_small.stats()
+    _say("stats", st)
+    assert st["reoffered"] > 0 and st["promotions"] > 0
+
+
 def test_er1k_listing(ctx, er1k):
     g = er1k
     pats = sample_patterns(g, 6, seed=8, kmin=3, kmax=4)

@@ -1,0 +1,85 @@
+"""Parity at full size: sampled patterns on the 1M-vertex Chung-Lu graph and
+the 4M-vertex R-MAT graph, answered as one batch per graph (the way the
+benchmark runs them), against the oracle's answers stored in
+tests/golden/large_expected.json (written by make_large_expected.py, which
+calls only the oracle).  The embedding count is capped at the stored cap on
+both sides; the digest is compared where the count did not saturate.
+
+Two launch configurations: with the digest (the count phase enumerates and
+hashes every embedding) and without it (a leaf last vertex is counted in
+closed form), each with the autotuned-size defaults of a context."""
+
+import functools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2404_01585_amd import flexis as fx
+from paper_2404_01585_amd.synth import Pattern, workload_graph
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def expected():
+    with open(os.path.join(HERE, "golden", "large_expected.json")) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@functools.lru_cache(maxsize=None)
+def _graph(name):
+    return workload_graph(name)
+
+
+def _check(name, expected, no_digest):
+    cases = [r for r in expected["results"] if r["graph"] == name]
+    assert len(cases) >= 100
+    _say(name, "building the graph")
+    g = _graph(name)
+    pats = [Pattern(vlabel=c["pattern"]["vlabel"], edges=[tuple(e) for e in c["pattern"]["edges"]],
+                    elabel=c["pattern"]["elabel"]) for c in cases]
+    sig = [c["sigma"] for c in cases]
+    lam = [c["lam"] for c in cases]
+    with fx.Context(device=0, count_cap=expected["count_cap"], no_digest=no_digest) as ctx:
+        with ctx.load_graph(g) as dg:
+            _say(name, "FULL batch of", len(pats), "no_digest", no_digest)
+            full = dg.support_batch(pats, sig, lam, fx.MODE_FULL)
+            _say(name, "VERDICT batch")
+            ver = dg.support_batch(pats, sig, lam, fx.MODE_VERDICT)
+    for i, c in enumerate(cases):
+        w, got = c["full"], full[i]
+        for k in ("tau", "support", "frequent", "embedding_count", "count_saturated"):
+            assert got[k] == w[k], (name, i, k, got[k], w[k])
+        if not no_digest and not w["count_saturated"]:
+            assert list(got["digest"]) == w["digest"], (name, i)
+        wv, gv = c["verdict"], ver[i]
+        for k in ("tau", "support", "frequent"):
+            assert gv[k] == wv[k], (name, i, k, gv[k], wv[k])
+    _say(name, "ok", len(cases), "patterns")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("no_digest", [False, True])
+def test_cl1m_sampled(torch_cuda, expected, no_digest):
+    _check("cl1m", expected, no_digest)
+
+
+@pytest.mark.timeout(600)
+def test_rmat22_sampled(torch_cuda, expected):
+    _check("rmat22", expected, False)
