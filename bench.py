@@ -449,6 +449,8 @@ def main():
         "syncs_per_step": st["syncs"] / args.steps,
         "reoffered_candidates_per_step": st["reoffered"] / args.steps,
         "stack_promotions_per_step": st["promotions"] / args.steps,
+        "host_ms_per_step": round(st["host_ms"] / args.steps, 3),
+        "device_wait_ms_per_step": round(st["wait_ms"] / args.steps, 3),
         "device_steps_per_step": st["steps"] / args.steps,
         "plain_form": plain,
         "serving": serving,

@@ -218,7 +218,9 @@ fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, co
  *   reoffered   candidates probed in a slice that stopped at its row cap and
  *               offered again in a later step (wasted probe work).
  *   promotions  stacks moved to a larger slice capacity because few queries
- *               were left to share the device. */
+ *               were left to share the device.
+ *   host_ms     host time inside the engine's steps, waits excluded.
+ *   wait_ms     host time waiting for each step's device work to finish. */
 typedef struct {
     uint64_t probe_launches;
     double probe_ms;
@@ -233,6 +235,8 @@ typedef struct {
     uint64_t queries;
     uint64_t reoffered;
     uint64_t promotions;
+    double host_ms;
+    double wait_ms;
 } fx_stats;
 
 /* Copies the context's statistics into *out; reset != 0 zeroes them after. */

@@ -494,6 +494,20 @@ fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
 
 fx_status FxEngine::step()
 {
+    using clk = std::chrono::steady_clock;
+    const auto h0 = clk::now();
+    double waited = 0;
+    struct HostTime {  // adds this step's host time to the statistics on every exit
+        fx_stats *st;
+        clk::time_point h0;
+        double *waited;
+        ~HostTime()
+        {
+            const double ms = std::chrono::duration<double, std::milli>(clk::now() - h0).count();
+            st->host_ms += ms - *waited;
+            st->wait_ms += *waited;
+        }
+    } host_time{stats_, h0, &waited};
     if (!buffers_ready_) {  // grow-only buffers sized for these parameters
         const int32_t A = P_.max_active;
         const uint64_t tile = (uint64_t)FX_BS * P_.items;
@@ -630,7 +644,11 @@ fx_status FxEngine::step()
     int hi = 0;
     for (auto &qp : active_) hi = std::max(hi, qp->slot + 1);
     FX_HIP(hipMemcpyAsync(sums_h, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, s_));
-    FX_HIP(hipStreamSynchronize(s_));
+    {
+        const auto w0 = clk::now();
+        FX_HIP(hipStreamSynchronize(s_));
+        waited += std::chrono::duration<double, std::milli>(clk::now() - w0).count();
+    }
     stats_->steps++;
     stats_->syncs++;
     stats_->probe_launches++;

@@ -87,7 +87,7 @@ class StatsC(ctypes.Structure):
                 ("scatter_ms", ctypes.c_double), ("scatter_alg_bytes", ctypes.c_uint64),
                 ("greedy_launches", ctypes.c_uint64), ("greedy_ms", ctypes.c_double), ("steps", ctypes.c_uint64),
                 ("syncs", ctypes.c_uint64), ("queries", ctypes.c_uint64), ("reoffered", ctypes.c_uint64),
-                ("promotions", ctypes.c_uint64)]
+                ("promotions", ctypes.c_uint64), ("host_ms", ctypes.c_double), ("wait_ms", ctypes.c_double)]
 
     def to_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
