@@ -156,6 +156,11 @@ constexpr int32_t kPromoteAfter = 16;        // steps a query has run before its
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Stage buffer of a step: workgroup starts of up to `segs` segments (plus the
+// end), then the segment table.
+size_t stage_off(size_t segs) { return align256((segs + 1) * 4); }
+size_t stage_bytes(size_t segs, size_t table) { return stage_off(segs) + table * sizeof(FxSeg); }
+
 enum { PH_SUPPORT = 0, PH_COUNT = 1, PH_LIST = 2 };
 
 bool wants_selection(const FxRequest &r) { return r.kind == FX_Q_FULL && r.selected && r.selected_cap > 0; }
@@ -266,14 +271,20 @@ void restart_stack(FxQuery &q, const fx_graph *G)
 
 EngineWork::~EngineWork()
 {
-    for (auto &e : evk)
-        if (e) (void)hipEventDestroy(e);
+    for (auto &L : lane) {
+        if (L.done) (void)hipEventDestroy(L.done);
+        for (auto &e : L.evk)
+            if (e) (void)hipEventDestroy(e);
+    }
 }
 
 fx_status EngineWork::init_events()
 {
-    for (auto &e : evk)
-        if (!e) FX_HIP(hipEventCreate(&e));
+    for (auto &L : lane) {
+        if (!L.done) FX_HIP(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+        for (auto &e : L.evk)
+            if (!e) FX_HIP(hipEventCreate(&e));
+    }
     return FX_OK;
 }
 
@@ -283,12 +294,21 @@ FxEngine::FxEngine(fx_graph *G, EngineWork *W, hipStream_t s, const EngineParams
     if (P_.max_active < 1) P_.max_active = 1;
     // a segment's span is a 32-bit count
     P_.step_candidates = std::min<uint64_t>(std::max<uint64_t>(P_.step_candidates, FX_MAX_TILE), 1ull << 31);
-    for (int k = P_.max_active - 1; k >= 0; k--) free_slots_.push_back(k);
+    P_.lanes = P_.lanes == 1 ? 1 : 2;
+    for (int k = P_.max_active - 1; k >= 0; k--) free_slots_[P_.lanes == 1 ? 0 : (k & 1)].push_back(k);
 }
 
-FxEngine::~FxEngine() = default;
+FxEngine::~FxEngine()
+{
+    // after an error, queries may still be running: let their work finish
+    // before their stack memory goes back to the pool
+    if (!active_[0].empty() || !active_[1].empty()) (void)hipStreamSynchronize(s_);
+    for (auto &A : active_)
+        for (auto &q : A)
+            if (q->region) W_->pool.give(q->region, q->region_bytes);
+}
 
-bool FxEngine::idle() const { return pending_.empty() && active_.empty(); }
+bool FxEngine::idle() const { return pending_.empty() && active_[0].empty() && active_[1].empty(); }
 
 void FxEngine::done(FxRequest *r)
 {
@@ -332,10 +352,10 @@ void FxEngine::add(FxRequest *r)
     pending_.push_back(std::move(q));
 }
 
-fx_status FxEngine::finish(FxQuery &q)
+fx_status FxEngine::finish(FxQuery &q, const FxSummary *sums)
 {
     FxRequest &r = *q.req;
-    const FxSummary &S = W_->sums_h.as<FxSummary>()[q.slot];
+    const FxSummary &S = sums[q.slot];
     if (q.phase == PH_LIST) {
         *r.list_count = q.listed;  // rows written at the last level (a capped slice re-offers the rest)
     } else {
@@ -381,26 +401,28 @@ fx_status FxEngine::finish(FxQuery &q)
     stats_->queries++;
     W_->pool.give(q.region, q.region_bytes);
     q.region = nullptr;
-    free_slots_.push_back(q.slot);
+    free_slots_[q.slot & 1].push_back(q.slot);
     q.slot = -1;
     done(&r);
     return FX_OK;
 }
 
-// Admission: as many pending queries as slots and memory allow.
-fx_status FxEngine::admit()
+// Admission into lane g: as many pending queries as its slots and memory allow.
+fx_status FxEngine::admit(int g)
 {
     const int64_t nv = G_->nv;
     const uint64_t u_words = ((uint64_t)nv + 31) / 32;
-    FxInit *inits = W_->inits_h.as<FxInit>();
+    EngineLane &L = W_->lane[g];
+    FxInit *inits = L.inits_h.as<FxInit>();
     FxSummary *sums_d = W_->sums_d.as<FxSummary>();
     int ninit = 0;
-    while (!pending_.empty() && !free_slots_.empty()) {
+    while (!pending_.empty() && !free_slots_[g].empty()) {
         FxQuery &q = *pending_.front();
         const size_t bytes = region_size(q, nv);
         fx_status st = W_->pool.take(bytes, &q.region);
         if (st != FX_OK) {
-            if (!active_.empty() || ninit > 0) break;  // wait until running queries free their regions
+            // wait until running queries free their regions
+            if (!active_[0].empty() || !active_[1].empty() || ninit > 0) break;
             q.req->status = st;                       // it cannot fit even alone
             FxRequest *r = q.req;
             pending_.pop_front();
@@ -409,8 +431,8 @@ fx_status FxEngine::admit()
         }
         q.region_bytes = bytes;
         carve(q, nv);
-        q.slot = free_slots_.back();
-        free_slots_.pop_back();
+        q.slot = free_slots_[g].back();
+        free_slots_[g].pop_back();
         FxInit &I = inits[ninit++];
         I.plan = q.hp.plan;
         I.plan_dst = q.plan;
@@ -421,12 +443,12 @@ fx_status FxEngine::admit()
         I.clear_u = 1;
         I.clear_sum = 1;
         restart_stack(q, G_);
-        active_.push_back(std::move(pending_.front()));
+        active_[g].push_back(std::move(pending_.front()));
         pending_.pop_front();
     }
     if (ninit) {
-        FX_HIP(hipMemcpyAsync(W_->inits_d.p, inits, (size_t)ninit * sizeof(FxInit), hipMemcpyHostToDevice, s_));
-        FX_HIP(fx_launch_init(s_, G_->dev, W_->inits_d.as<FxInit>(), ninit));
+        FX_HIP(hipMemcpyAsync(L.inits_d.p, inits, (size_t)ninit * sizeof(FxInit), hipMemcpyHostToDevice, s_));
+        FX_HIP(fx_launch_init(s_, G_->dev, L.inits_d.as<FxInit>(), ninit));
     }
     return FX_OK;
 }
@@ -517,35 +539,50 @@ fx_status FxEngine::step()
         FX_TRY(W_->boff.ensure((max_blocks + 1) * 8));
         FX_TRY(W_->lsum.ensure(max_blocks * 8));
         FX_TRY(W_->loff.ensure((max_blocks + 1) * 8));
-        FX_TRY(W_->segs_d.ensure((size_t)A * sizeof(FxSeg)));
-        FX_TRY(W_->segs_h.ensure((size_t)A * sizeof(FxSeg)));
-        FX_TRY(W_->blk0_d.ensure(((size_t)A + 1) * 4));
-        FX_TRY(W_->blk0_h.ensure(((size_t)A + 1) * 4));
-        FX_TRY(W_->inits_d.ensure((size_t)A * sizeof(FxInit)));
-        FX_TRY(W_->inits_h.ensure((size_t)A * sizeof(FxInit)));
         FX_TRY(W_->sums_d.ensure((size_t)A * sizeof(FxSummary)));
-        FX_TRY(W_->sums_h.ensure((size_t)A * sizeof(FxSummary)));
+        for (auto &L : W_->lane) {
+            FX_TRY(L.stage_d.ensure(stage_bytes(A, A)));
+            FX_TRY(L.stage_h.ensure(stage_bytes(A, A)));
+            FX_TRY(L.inits_d.ensure((size_t)A * sizeof(FxInit)));
+            FX_TRY(L.inits_h.ensure((size_t)A * sizeof(FxInit)));
+            FX_TRY(L.sums_h.ensure((size_t)A * sizeof(FxSummary)));
+        }
         FX_TRY(W_->init_events());
         buffers_ready_ = true;
     }
-    FX_TRY(admit());
-    if (active_.empty()) return FX_OK;
+    const int g = lane_;
+    lane_ = P_.lanes == 1 ? 0 : (lane_ ^ 1);
+    if (in_flight_[g]) FX_TRY(collect(g, waited));
+    FX_TRY(admit(g));
+    if (!active_[g].empty()) FX_TRY(launch(g));
+    return FX_OK;
+}
 
-    // ---- one segment per active query, within the step's candidate budget
-    FxSeg *segs = W_->segs_h.as<FxSeg>();
-    uint32_t *blk0 = W_->blk0_h.as<uint32_t>();
+// Builds and launches lane g's next device step: one segment per active
+// query of the lane, within the step's candidate budget, then the copy of
+// the summaries and the lane's completion event.
+fx_status FxEngine::launch(int g)
+{
+    EngineLane &L = W_->lane[g];
+    auto &act = active_[g];
+    // the stage buffer holds the workgroup starts, then the segment table,
+    // so one copy uploads both
+    const size_t seg_off = stage_off(act.size());
+    uint32_t *blk0 = L.stage_h.as<uint32_t>();
+    FxSeg *segs = (FxSeg *)((char *)L.stage_h.p + seg_off);
     FxSummary *sums_d = W_->sums_d.as<FxSummary>();
-    FxSummary *sums_h = W_->sums_h.as<FxSummary>();
+    const FxSummary *sums_prev = L.sums_h.as<FxSummary>();
     int nsegs = 0;
     uint64_t budget = P_.step_candidates;
     uint32_t nblocks = 0;
     int any_inner = 0, any_greedy = 0;
-    const size_t A = active_.size();
-    uint64_t n_open = 0;
-    for (auto &qp : active_) {
+    const size_t A = act.size();
+    uint64_t n_open = 0;  // over both lanes: a query gets a step of its lane every other step
+    for (auto &qp : act) {
         qp->seg_l = -1;
         n_open += deepest_open_level(*qp) >= 0;
     }
+    for (auto &qp : active_[g ^ 1]) n_open += deepest_open_level(*qp) >= 0;
     // a query's fair share of the step; a slice may take more candidates
     // than its level holds rows when few of them pass (the row cap bounds
     // what is written, see k_scatter)
@@ -556,8 +593,7 @@ fx_status FxEngine::step()
     // larger slices expand partials that a selection would have removed
     // (measured: twice the probe work on cl1m).  A support-phase stack grows
     // only while U has removed under 1/64 of its candidates.
-    const FxSummary *sums_prev = W_->sums_h.as<FxSummary>();
-    for (auto &qp : active_) {
+    for (auto &qp : act) {
         FxQuery &q = *qp;
         if (q.phase == PH_SUPPORT && (q.probed_support == 0 || sums_prev[q.slot].ufiltered * 64 > q.probed_support))
             continue;
@@ -570,7 +606,7 @@ fx_status FxEngine::step()
         if (nc > q.cap) FX_TRY(promote(q, nc));
     }
     for (size_t k = 0; k < A && budget > 0; k++) {
-        FxQuery &q = *active_[(rot_ + k) % A];
+        FxQuery &q = *act[(rot_[g] + k) % A];
         const int l = deepest_open_level(q);
         if (l < 0) continue;
         const bool last = (l == q.n - 1);
@@ -630,42 +666,57 @@ fx_status FxEngine::step()
         any_greedy |= kind == FX_SEG_GREEDY;
         nsegs++;
     }
-    rot_++;
-    if (nsegs == 0) return fx_fail(FX_EDEVICE, "engine stalled with %zu active queries", active_.size());
+    rot_[g]++;
+    if (nsegs == 0) return fx_fail(FX_EDEVICE, "engine stalled with %zu active queries", A);
     blk0[nsegs] = nblocks;
-    FX_HIP(hipMemcpyAsync(W_->segs_d.p, segs, (size_t)nsegs * sizeof(FxSeg), hipMemcpyHostToDevice, s_));
-    FX_HIP(hipMemcpyAsync(W_->blk0_d.p, blk0, ((size_t)nsegs + 1) * 4, hipMemcpyHostToDevice, s_));
-    hipEvent_t *ev = P_.timing ? W_->evk : nullptr;
-    FX_HIP(fx_launch_step(s_, G_->dev, W_->segs_d.as<FxSeg>(), W_->blk0_d.as<uint32_t>(), nsegs, nblocks,
-                          P_.items, W_->flag.as<uint8_t>(), W_->bcnt.as<uint32_t>(), W_->boff.as<uint64_t>(),
+    FX_HIP(hipMemcpyAsync(L.stage_d.p, L.stage_h.p, seg_off + (size_t)nsegs * sizeof(FxSeg), hipMemcpyHostToDevice,
+                          s_));
+    hipEvent_t *ev = P_.timing ? L.evk : nullptr;
+    FX_HIP(fx_launch_step(s_, G_->dev, (const FxSeg *)((char *)L.stage_d.p + seg_off), L.stage_d.as<uint32_t>(),
+                          nsegs, nblocks, P_.items,
+                          W_->flag.as<uint8_t>(), W_->bcnt.as<uint32_t>(), W_->boff.as<uint64_t>(),
                           W_->lsum.as<uint64_t>(), W_->loff.as<uint64_t>(), ev ? ev[0] : nullptr,
                           ev ? ev[1] : nullptr, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
                           ev ? ev[5] : nullptr, any_inner, any_greedy));
     int hi = 0;
-    for (auto &qp : active_) hi = std::max(hi, qp->slot + 1);
-    FX_HIP(hipMemcpyAsync(sums_h, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, s_));
+    for (auto &qp : act) hi = std::max(hi, qp->slot + 1);
+    FX_HIP(hipMemcpyAsync(L.sums_h.p, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, s_));
+    FX_HIP(hipEventRecord(L.done, s_));
+    in_flight_[g] = true;
+    any_greedy_[g] = any_greedy;
+    return FX_OK;
+}
+
+// Waits for lane g's device step, advances its queries, retires the finished
+// ones and moves FULL queries to their counting phase.
+fx_status FxEngine::collect(int g, double &waited)
+{
+    EngineLane &L = W_->lane[g];
+    auto &act = active_[g];
     {
-        const auto w0 = clk::now();
-        FX_HIP(hipStreamSynchronize(s_));
-        waited += std::chrono::duration<double, std::milli>(clk::now() - w0).count();
+        const auto w0 = std::chrono::steady_clock::now();
+        FX_HIP(hipEventSynchronize(L.done));
+        waited += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
     }
+    in_flight_[g] = false;
+    const FxSummary *sums_h = L.sums_h.as<FxSummary>();
     stats_->steps++;
     stats_->syncs++;
     stats_->probe_launches++;
     stats_->scatter_launches++;
-    if (any_greedy) stats_->greedy_launches++;
-    if (ev) {
+    if (any_greedy_[g]) stats_->greedy_launches++;
+    if (P_.timing) {
         float ms = 0;
-        FX_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        FX_HIP(hipEventElapsedTime(&ms, L.evk[0], L.evk[1]));
         stats_->probe_ms += ms;
-        FX_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+        FX_HIP(hipEventElapsedTime(&ms, L.evk[2], L.evk[3]));
         stats_->scatter_ms += ms;
-        FX_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
+        FX_HIP(hipEventElapsedTime(&ms, L.evk[4], L.evk[5]));
         stats_->greedy_ms += ms;
     }
 
     // ---- advance every query that took part
-    for (auto &qp : active_) {
+    for (auto &qp : act) {
         FxQuery &q = *qp;
         if (q.seg_l < 0) continue;
         const FxSummary &S = sums_h[q.slot];
@@ -682,6 +733,7 @@ fx_status FxEngine::step()
         q.alg_probe_credit += (double)(S.alg_probe - q.alg_probe_seen) * (double)taken / (double)q.seg_span;
         q.alg_probe_seen = S.alg_probe;
         q.steps++;
+        q.seg_l = -1;
         const uint64_t N = S.total_out;
         if (q.seg_kind == FX_SEG_INNER) {
             q.nparts[l + 1] = (int64_t)N;
@@ -701,8 +753,8 @@ fx_status FxEngine::step()
         }
     }
     // ---- retire finished queries, move FULL queries to their counting phase
-    for (size_t k = 0; k < active_.size();) {
-        FxQuery &q = *active_[k];
+    for (size_t k = 0; k < act.size();) {
+        FxQuery &q = *act[k];
         const FxSummary &S = sums_h[q.slot];
         bool fin = false;
         if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_VERDICT && (int64_t)S.support >= q.tau_eff) fin = true;
@@ -716,9 +768,9 @@ fx_status FxEngine::step()
             }
         }
         if (fin) {
-            FX_TRY(finish(q));
-            active_[k] = std::move(active_.back());
-            active_.pop_back();
+            FX_TRY(finish(q, sums_h));
+            act[k] = std::move(act.back());
+            act.pop_back();
         } else {
             k++;
         }

@@ -88,16 +88,27 @@ struct EngineParams {
     int32_t max_active = 4096;             // queries in flight
     uint32_t last_span_init = 4096;        // first last-vertex slice of the support phase
     int32_t items = 4;                     // candidates per thread in the expansion kernels (2, 4, 8)
+    int32_t lanes = 2;                     // pipeline lanes (1 or 2)
     bool timing = false;
     bool no_digest = false;
 };
 
-// Device and pinned buffers of one engine (a context's, or a server's).
+// Buffers of one of the engine's two pipeline lanes: what the host writes for
+// a lane's step, and the summaries read back after it.
+struct EngineLane {
+    DevBuf stage_d, inits_d;           // stage: workgroup starts, then the segment table
+    HostBuf stage_h, inits_h, sums_h;
+    hipEvent_t done = nullptr;  // recorded after the lane's summary copy
+    hipEvent_t evk[6] = {};     // kernel timing
+};
+
+// Device and pinned buffers of one engine (a context's, or a server's).  The
+// per-step scratch (flags, counts, offsets) is shared by the lanes: their
+// steps run one after the other on the engine's stream.
 struct EngineWork {
     RegionPool pool;
-    DevBuf flag, bcnt, boff, lsum, loff, segs_d, blk0_d, inits_d, sums_d;
-    HostBuf segs_h, blk0_h, inits_h, sums_h;
-    hipEvent_t evk[6] = {};
+    DevBuf flag, bcnt, boff, lsum, loff, sums_d;
+    EngineLane lane[2];
     ~EngineWork();
     fx_status init_events();
 };
@@ -155,8 +166,12 @@ struct FxRequest {
 struct FxQuery;
 
 // The multi-query engine: requests are added at any time; each step() admits
-// pending requests while slots and memory allow, runs one device step for all
-// active ones and reports finished requests through on_done.
+// pending requests while slots and memory allow, runs one device step for the
+// active ones and reports finished requests through on_done.  Queries are
+// split into two lanes by slot parity, and step() serves the lanes in turn:
+// it waits for a lane's previous device step, advances its queries and
+// launches its next step while the other lane's step runs on the device, so
+// the host's work between steps is hidden behind device work.
 class FxEngine {
 public:
     FxEngine(fx_graph *G, EngineWork *W, hipStream_t s, const EngineParams &p, fx_stats *stats);
@@ -172,9 +187,11 @@ public:
     std::function<void(FxRequest *)> on_done;
 
 private:
-    fx_status admit();
+    fx_status admit(int g);
     fx_status promote(FxQuery &q, int64_t new_cap);
-    fx_status finish(FxQuery &q);
+    fx_status finish(FxQuery &q, const FxSummary *sums);
+    fx_status collect(int g, double &waited);
+    fx_status launch(int g);
     void done(FxRequest *r);
     fx_graph *G_;
     EngineWork *W_;
@@ -182,9 +199,12 @@ private:
     EngineParams P_;
     fx_stats *stats_;
     std::deque<std::unique_ptr<FxQuery>> pending_;
-    std::vector<std::unique_ptr<FxQuery>> active_;
-    std::vector<int> free_slots_;
-    size_t rot_ = 0;
+    std::vector<std::unique_ptr<FxQuery>> active_[2];  // by lane
+    std::vector<int> free_slots_[2];
+    size_t rot_[2] = {0, 0};
+    bool in_flight_[2] = {false, false};
+    int any_greedy_[2] = {0, 0};
+    int lane_ = 0;  // the lane the next step() serves
     std::chrono::steady_clock::time_point t0_;
     bool buffers_ready_ = false;
 };

@@ -584,7 +584,10 @@ __global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ seg
 // marks a slot taken by a selected embedding; an undecided embedding that
 // meets one is dropped.  The lowest-ranked undecided embedding always wins
 // its round, so a chunk ends after at most (embeddings) rounds, and the
-// selection equals the sequential greedy's.
+// selection equals the sequential greedy's.  The rounds touch LDS only; the
+// chunk's selections go to U, the support count and the selection list in
+// one pass after it.  The first chunk skips the U test: the probe has just
+// tested every embedding against the same U.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint32_t lds_hash(int32_t v)
@@ -651,7 +654,8 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
     __shared__ unsigned long long hval[FX_GREEDY_H];
     __shared__ uint16_t slot[FX_GREEDY_VN];
     __shared__ uint8_t state[FX_GREEDY_VN];  // 0 undecided, 1 selected, 2 out, 3 selected by the tail
-    __shared__ uint32_t undecided;
+    __shared__ uint32_t undecided, nsel;
+    __shared__ unsigned long long sel_base;
     const FxSeg &S = segs[blockIdx.x];
     if (S.kind != FX_SEG_GREEDY) return;
     const int32_t n = S.n;
@@ -666,11 +670,15 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
             hkey[k] = -1;
             hval[k] = ~0ULL;
         }
+        if (threadIdx.x == 0) nsel = 0;
         __syncthreads();
         for (uint32_t e = threadIdx.x; e < nb; e += FX_BS) {
             const int32_t *row = rows + (c0 + e) * n;
+            // the probe tested every embedding against U as it stood before
+            // this launch; only selections of earlier chunks can have changed it
             bool out = false;
-            for (int j = 0; j < n; j++) out = out || used_coherent(S.U, row[j]);
+            if (c0 > 0)
+                for (int j = 0; j < n; j++) out = out || used_coherent(S.U, row[j]);
             state[e] = out ? 2 : 0;
             if (!out) {
                 for (int j = 0; j < n; j++) {
@@ -686,6 +694,7 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
             }
         }
         __syncthreads();
+        // rounds touch LDS only; the selections are written out after the chunk
         bool tail = false;
         uint32_t prev_und = nb;
         for (uint32_t r = 0; r <= nb; r++) {  // a chunk needs at most nb rounds
@@ -710,17 +719,7 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
                 for (int j = 0; j < n; j++) mine = mine && (hval[slot[e * n + j]] == key);
                 if (mine) {
                     state[e] = 1;
-                    const int32_t *row = rows + (c0 + e) * n;
-                    for (int j = 0; j < n; j++) {
-                        hval[slot[e * n + j]] = 0ULL;
-                        const uint32_t v = (uint32_t)row[j];
-                        atomicOr(&S.U[v >> 5], 1u << (v & 31u));
-                    }
-                    const unsigned long long pos = atomicAdd(&S.sum->support, 1ULL);
-                    if (S.sel_rows) {  // selections are kept only when the caller asked for them
-                        for (int j = 0; j < n; j++) S.sel_rows[pos * n + j] = row[j];
-                        S.sel_rank[pos] = S.rank_base + (int64_t)(c0 + e);
-                    }
+                    for (int j = 0; j < n; j++) hval[slot[e * n + j]] = 0ULL;
                 } else {
                     mine_undecided++;
                 }
@@ -742,18 +741,39 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
         if (tail) {  // uniform
             if (threadIdx.x < 64) greedy_tail(state, slot, hval, nb, n);
             __syncthreads();
-            for (uint32_t e = threadIdx.x; e < nb; e += FX_BS) {
-                if (state[e] != 3) continue;
+        }
+        // write out the chunk's selections: U bits, the support count and,
+        // when asked for, the selected rows with their ranks
+        constexpr int kPer = (FX_GREEDY_VN + FX_BS - 1) / FX_BS;  // embeddings of a chunk per thread
+        uint32_t my_pos[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            const uint32_t e = threadIdx.x + (uint32_t)k * FX_BS;
+            my_pos[k] = 0xffffffffu;
+            if (e >= nb || (state[e] != 1 && state[e] != 3)) continue;
+            const int32_t *row = rows + (c0 + e) * n;
+            for (int j = 0; j < n; j++) {
+                const uint32_t v = (uint32_t)row[j];
+                atomicOr(&S.U[v >> 5], 1u << (v & 31u));
+            }
+            my_pos[k] = atomicAdd(&nsel, 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long c = nsel;
+            sel_base = c ? atomicAdd(&S.sum->support, c) : 0ULL;
+        }
+        if (S.sel_rows) {  // selections are kept only when the caller asked for them
+            __syncthreads();
+            const unsigned long long base = sel_base;
+#pragma unroll
+            for (int k = 0; k < kPer; k++) {
+                const uint32_t e = threadIdx.x + (uint32_t)k * FX_BS;
+                if (my_pos[k] == 0xffffffffu) continue;
                 const int32_t *row = rows + (c0 + e) * n;
-                for (int j = 0; j < n; j++) {
-                    const uint32_t v = (uint32_t)row[j];
-                    atomicOr(&S.U[v >> 5], 1u << (v & 31u));
-                }
-                const unsigned long long pos = atomicAdd(&S.sum->support, 1ULL);
-                if (S.sel_rows) {
-                    for (int j = 0; j < n; j++) S.sel_rows[pos * n + j] = row[j];
-                    S.sel_rank[pos] = S.rank_base + (int64_t)(c0 + e);
-                }
+                const unsigned long long pos = base + my_pos[k];
+                for (int j = 0; j < n; j++) S.sel_rows[pos * n + j] = row[j];
+                S.sel_rank[pos] = S.rank_base + (int64_t)(c0 + e);
             }
         }
         __syncthreads();

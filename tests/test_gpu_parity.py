@@ -397,6 +397,40 @@ def test_autotune_keeps_results(torch_cuda, er1k, tmp_path):
                 assert r[k] == want[k], (p, k)
         t2 = dg.autotune(batch, 20, 1.0, fx.MODE_FULL, cache_path=cache)
         assert t2["from_cache"] == 1
-        for k in ("slice_rows", "step_candidates", "items_per_thread", "last_span_init"):
+        for k in ("slice_rows", "step_candidates", "items_per_thread", "last_span_init", "lanes"):
             assert t2[k] == t1[k]
+        assert t1["lanes"] in (1, 2)
     c.close()
+
+
+def test_launch_shapes_agree(torch_cuda, er1k, tmp_path):
+    """Every launch shape the tuner may pick (candidates per thread, one or two
+    pipeline lanes, small slices and greedy slices) gives the same results;
+    each shape is applied through a tuning-cache entry."""
+    g = er1k
+    cands = _mining_candidates(g, 20, 1.0, 2)
+    batch = fx.PatternBatch(cands)
+    ref = None
+    for items, lanes, slice_rows, last in ((2, 1, 1 << 15, 1024), (8, 2, 1 << 15, 16384), (4, 1, 1 << 17, 4096)):
+        c = fx.Context(device=0)
+        with c.load_graph(g) as dg:
+            cache = str(tmp_path / f"shape_{items}_{lanes}.txt")
+            dg.autotune(batch, 20, 1.0, fx.MODE_FULL, cache_path=cache)  # writes the key
+            key = open(cache).read().split()[0]
+            with open(cache, "w") as f:
+                f.write(f"{key} {slice_rows} {1 << 22} {items} {last} {lanes} 1.0\n")
+            t = dg.autotune(batch, 20, 1.0, fx.MODE_FULL, cache_path=cache)
+            assert t["from_cache"] == 1 and t["lanes"] == lanes and t["items_per_thread"] == items
+            _say("shape", items, lanes, slice_rows, last)
+            got = dg.support_batch(cands, [20] * len(cands), [1.0] * len(cands), fx.MODE_FULL)
+            ver = dg.support_batch(cands, [20] * len(cands), [0.5] * len(cands), fx.MODE_VERDICT)
+        c.close()
+        row = [(r["support"], r["frequent"], r["embedding_count"], tuple(r["digest"])) for r in got]
+        row += [(r["support"], r["frequent"]) for r in ver]
+        if ref is None:
+            ref = row
+            for p, r in zip(cands, got):
+                want = O.query(g, p, 20, 1.0, O.FULL)
+                for k in ("support", "frequent", "embedding_count", "digest"):
+                    assert r[k] == want[k], (p, k)
+        assert row == ref
