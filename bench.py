@@ -286,6 +286,8 @@ def main():
     ap.add_argument("--mode", default="full", choices=["full", "verdict"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--count-cap", type=int, default=0, help="embedding count cap (0: 2^62)")
+    ap.add_argument("--no-run-index", action="store_true",
+                    help="no label-run index: candidate runs and edge tests by binary search in the rows")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (untimed) before the timed steps")
@@ -345,7 +347,7 @@ def main():
         f"({time.perf_counter() - t:.1f} s)")
     torch.cuda.set_device(0)
     ctx = fx.Context(device=0, kernel_timing=not args.no_timing, no_digest=not args.digest,
-                     count_cap=args.count_cap)
+                     count_cap=args.count_cap, run_index_bytes=-1 if args.no_run_index else 0)
     dg = ctx.load_graph(g)
     t = time.perf_counter()
     cands, per_level = build_candidates(dg, g, spec)
@@ -437,6 +439,7 @@ def main():
         "config": {"workload": args.workload, "description": spec["desc"], "patterns": P,
                    "patterns_per_level": per_level, "sigma": spec["sigma"], "lambda": spec["lam"],
                    "mode": args.mode, "count_cap": ctx.count_cap, "digest": bool(args.digest),
+                   "run_index": not args.no_run_index,
                    "form": "batched (all candidates of the batch in flight, one segment each per step)",
                    "tuned": tuned},
         "embeddings_per_s": round(emb * args.steps / dt, 1),

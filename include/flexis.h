@@ -49,8 +49,15 @@ enum {
 
 /* Result modes (Section 3.1.1, early termination at tau). */
 enum {
-    FX_MODE_FULL = 0,   /* exact support, verdict, embedding count and digest */
-    FX_MODE_VERDICT = 1 /* verdict only; the search stops as soon as it is decided */
+    FX_MODE_FULL = 0,    /* exact support, verdict, embedding count and digest */
+    FX_MODE_VERDICT = 1, /* verdict only; the search stops as soon as it is decided */
+    FX_MODE_MNI = 2      /* the minimum-image support of Section 2.4.4 instead of the
+                            greedy: support = min over pattern vertices v of the
+                            number of distinct data vertices v is mapped to by the
+                            embeddings; tau = sigma (lambda is not used: it belongs
+                            to the greedy metric); frequent = support >= max(sigma, 1);
+                            embedding count and digest as in FULL (every embedding is
+                            enumerated, the count cap only caps the reported count) */
 };
 
 #define FX_MAX_PATTERN_VERTICES 16
@@ -185,7 +192,8 @@ fx_status fx_tau(int64_t sigma, double lambda, int32_t n, int64_t *tau_out);
  * Section 2.1.4 (non-induced).  They are ranked lexicographically by
  * (f(0), ..., f(n-1)) and the greedy keeps every embedding that shares no
  * data vertex with an earlier kept one; support is the number kept.
- *   sigma >= 1, 0 <= lambda <= 1, mode FX_MODE_FULL or FX_MODE_VERDICT.
+ *   sigma >= 1, 0 <= lambda <= 1, mode FX_MODE_FULL, FX_MODE_VERDICT or
+ *   FX_MODE_MNI (then support is the minimum-image count, see above). 
  *   selected (optional, host, [selected_cap * n] int32): FULL mode receives the
  *   first min(support, selected_cap) kept embeddings in rank order. */
 fx_status fx_support(fx_graph *g, const fx_pattern *p, int64_t sigma, double lambda, int32_t mode,

@@ -225,7 +225,8 @@ extern "C" fx_status fx_support(fx_graph *g, const fx_pattern *p, int64_t sigma,
     if (!g || !out) return fx_fail(FX_EINVAL, "NULL argument");
     if (sigma < 1) return fx_fail(FX_EINVAL, "sigma must be >= 1");
     if (!(lambda >= 0.0 && lambda <= 1.0)) return fx_fail(FX_EINVAL, "lambda must lie in [0, 1]");
-    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT) return fx_fail(FX_EINVAL, "unknown mode %d", mode);
+    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI)
+        return fx_fail(FX_EINVAL, "unknown mode %d", mode);
     if (selected_cap < 0 || (selected_cap > 0 && !selected)) return fx_fail(FX_EINVAL, "bad selected buffer");
     FX_HIP(hipSetDevice(g->ctx->device));
     std::vector<FxRequest> reqs(1);
@@ -234,7 +235,7 @@ extern "C" fx_status fx_support(fx_graph *g, const fx_pattern *p, int64_t sigma,
     r.pattern = p;
     r.sigma = sigma;
     r.lambda = lambda;
-    r.kind = mode == FX_MODE_FULL ? FX_Q_FULL : FX_Q_VERDICT;
+    r.kind = mode == FX_MODE_FULL ? FX_Q_FULL : (mode == FX_MODE_MNI ? FX_Q_MNI : FX_Q_VERDICT);
     r.out = &res;
     r.selected = selected;
     r.selected_cap = selected_cap;
@@ -267,7 +268,8 @@ extern "C" fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_patter
                                       const double *lambda, int32_t mode, fx_result *out)
 {
     if (!g || npat < 0 || (npat > 0 && (!pats || !sigma || !lambda || !out))) return fx_fail(FX_EINVAL, "bad batch");
-    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT) return fx_fail(FX_EINVAL, "unknown mode %d", mode);
+    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI)
+        return fx_fail(FX_EINVAL, "unknown mode %d", mode);
     for (int32_t i = 0; i < npat; i++) {
         if (sigma[i] < 1) return fx_fail(FX_EINVAL, "pattern %d: sigma must be >= 1", i);
         if (!(lambda[i] >= 0.0 && lambda[i] <= 1.0)) return fx_fail(FX_EINVAL, "pattern %d: lambda outside [0, 1]", i);
@@ -280,7 +282,7 @@ extern "C" fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_patter
         reqs[i].pattern = &pats[i];
         reqs[i].sigma = sigma[i];
         reqs[i].lambda = lambda[i];
-        reqs[i].kind = mode == FX_MODE_FULL ? FX_Q_FULL : FX_Q_VERDICT;
+        reqs[i].kind = mode == FX_MODE_FULL ? FX_Q_FULL : (mode == FX_MODE_MNI ? FX_Q_MNI : FX_Q_VERDICT);
         reqs[i].out = &res[i];
     }
     FX_TRY(fx_engine_run(g, reqs, g->ctx->params.max_active));

@@ -179,6 +179,8 @@ struct FxQuery {
     int64_t cap = 0;
     FxLevelDev lev[FX_MAXN + 1]{};
     uint32_t *U = nullptr;
+    uint32_t *img = nullptr;                 // image bitmaps (minimum-image support), after U
+    unsigned long long *mni = nullptr;       // per-vertex image counts [FX_MAXN], then the minimum
     FxPlan *plan = nullptr;
     int32_t *sel_rows = nullptr;
     int64_t *sel_rank = nullptr;
@@ -209,7 +211,8 @@ size_t region_size(const FxQuery &q, int64_t nv)
     for (int l = 1; l < n; l++)
         b += align256(C * l * 4) + align256(C * 8) + align256(C * 4) + align256(C) + align256((C + 1) * 8);
     b += align256(C * n * 4);  // complete embeddings
-    b += align256(((size_t)nv + 31) / 32 * 4) + align256(sizeof(FxPlan));
+    b += align256(((size_t)nv + 31) / 32 * 4 * (q.req->kind == FX_Q_MNI ? 1 + n : 1)) + align256(sizeof(FxPlan));
+    if (q.req->kind == FX_Q_MNI) b += align256((FX_MAXN + 1) * 8);
     if (wants_selection(*q.req)) {
         const size_t k = (size_t)nv / n + 1;
         b += align256(k * n * 4) + align256(k * 8);
@@ -241,7 +244,11 @@ void carve(FxQuery &q, int64_t nv)
     }
     q.lev[n] = FxLevelDev{};
     q.lev[n].rows = (int32_t *)take(C * n * 4);
-    q.U = (uint32_t *)take(((size_t)nv + 31) / 32 * 4);
+    const size_t words = ((size_t)nv + 31) / 32;
+    const bool mni = q.req->kind == FX_Q_MNI;
+    q.U = (uint32_t *)take(words * 4 * (mni ? 1 + n : 1));  // the image bitmaps follow U
+    q.img = mni ? q.U + words : nullptr;
+    q.mni = mni ? (unsigned long long *)take((FX_MAXN + 1) * 8) : nullptr;
     q.plan = (FxPlan *)take(sizeof(FxPlan));
     q.sel_rows = nullptr;
     q.sel_rank = nullptr;
@@ -325,6 +332,7 @@ void FxEngine::add(FxRequest *r)
     if (r->kind != FX_Q_LIST) {
         r->status = fx_tau_checked(r->sigma, r->lambda, q->n, &q->tau);
         if (r->status != FX_OK) return done(r);
+        if (r->kind == FX_Q_MNI) q->tau = r->sigma;  // the minimum-image threshold is sigma itself
         q->tau_eff = std::max<int64_t>(q->tau, 1);
     }
     fx_result res{};
@@ -345,7 +353,7 @@ void FxEngine::add(FxRequest *r)
         *r->out = res;
         return done(r);
     }
-    q->phase = r->kind == FX_Q_LIST ? PH_LIST : PH_SUPPORT;
+    q->phase = r->kind == FX_Q_LIST ? PH_LIST : (r->kind == FX_Q_MNI ? PH_COUNT : PH_SUPPORT);
     q->cap = P_.slice_rows;
     q->last_span = (uint32_t)std::min<int64_t>(P_.last_span_init, q->cap);
     for (auto &r : q->rate) r = 1.0;
@@ -371,6 +379,13 @@ fx_status FxEngine::finish(FxQuery &q, const FxSummary *sums)
             res.embedding_count = -1;
         } else {
             res.support = (int64_t)S.support;
+            if (r.kind == FX_Q_MNI) {
+                unsigned long long m = 0;
+                FX_HIP(fx_launch_mni(s_, q.img, ((uint64_t)G_->nv + 31) / 32, q.n, q.mni, q.mni + FX_MAXN));
+                FX_HIP(hipMemcpyAsync(&m, q.mni + FX_MAXN, 8, hipMemcpyDeviceToHost, s_));
+                FX_HIP(hipStreamSynchronize(s_));
+                res.support = (int64_t)m;
+            }
             res.frequent = res.support >= q.tau_eff;
             const bool sat = (int64_t)S.count >= P_.count_cap;
             res.count_saturated = sat;
@@ -439,7 +454,7 @@ fx_status FxEngine::admit(int g)
         I.lev0 = q.lev[0];
         I.U = q.U;
         I.sum = sums_d + q.slot;
-        I.u_words = u_words;
+        I.u_words = u_words * (q.req->kind == FX_Q_MNI ? 1 + (uint64_t)q.n : 1);  // U and the image bitmaps
         I.clear_u = 1;
         I.clear_sum = 1;
         restart_stack(q, G_);
@@ -499,7 +514,7 @@ fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
         FX_TRY(cp(q.lev[l].anc, old.lev[l].anc, np));
         FX_TRY(cp(q.lev[l].off, old.lev[l].off, (np + 1) * 8));
     }
-    FX_TRY(cp(q.U, old.U, ((size_t)nv + 31) / 32 * 4));
+    FX_TRY(cp(q.U, old.U, ((size_t)nv + 31) / 32 * 4 * (q.img ? 1 + (size_t)q.n : 1)));  // U and images
     FX_TRY(cp(q.plan, old.plan, sizeof(FxPlan)));
     if (q.sel_rows) {
         const size_t k = (size_t)nv / q.n + 1;
@@ -619,9 +634,13 @@ fx_status FxEngine::launch(int g)
         } else if (q.phase == PH_COUNT) {
             // without a digest, a leaf last vertex is counted in closed form
             // from the partials of vertex n-2 (level n-1 is never built)
-            const bool leaf = P_.no_digest && q.n >= 2 && q.hp.plan.nback[q.n - 1] == 1;
+            // (the minimum-image support needs every last-vertex image: no closed form)
+            const bool mni = q.req->kind == FX_Q_MNI;
+            const bool leaf = P_.no_digest && !mni && q.n >= 2 && q.hp.plan.nback[q.n - 1] == 1;
             const bool end = leaf ? (l == q.n - 2) : last;
-            flags = end ? (leaf ? FX_PROBE_LEAF : (FX_PROBE_COUNT | (P_.no_digest ? 0 : FX_PROBE_HASH))) : 0;
+            flags = end ? (leaf ? FX_PROBE_LEAF
+                                : (FX_PROBE_COUNT | (P_.no_digest ? 0 : FX_PROBE_HASH) | (mni ? FX_PROBE_IMAGES : 0)))
+                        : 0;
             kind = end ? FX_SEG_COUNT : FX_SEG_INNER;
         } else {
             kind = last ? FX_SEG_LIST : FX_SEG_INNER;
@@ -645,6 +664,8 @@ fx_status FxEngine::launch(int g)
         S.sum = sums_d + q.slot;
         S.sel_rows = q.sel_rows;
         S.sel_rank = q.sel_rank;
+        S.img = q.img;
+        S.img_words = ((uint64_t)G_->nv + 31) / 32;
         S.nparts = q.nparts[l];
         S.t0 = q.cur[l];
         S.rank_base = q.rank_base;
@@ -758,7 +779,8 @@ fx_status FxEngine::collect(int g, double &waited)
         const FxSummary &S = sums_h[q.slot];
         bool fin = false;
         if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_VERDICT && (int64_t)S.support >= q.tau_eff) fin = true;
-        if (q.phase == PH_COUNT && (int64_t)S.count >= P_.count_cap) fin = true;
+        // (the minimum-image support needs every embedding: the cap only caps its count)
+        if (q.phase == PH_COUNT && q.req->kind != FX_Q_MNI && (int64_t)S.count >= P_.count_cap) fin = true;
         if (!fin && deepest_open_level(q) < 0) {
             if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_FULL) {
                 q.phase = PH_COUNT;  // level 0 is unchanged; restart the cursors

@@ -105,6 +105,7 @@ enum : int32_t {
     FX_PROBE_LEAF = 4,      // candidates of vertex n-2: add the closed-form count of the last
                             // vertex, a leaf with a single earlier neighbour (no hashing)
     FX_PROBE_HASH = 8,      // with FX_PROBE_COUNT: also hash every counted embedding
+    FX_PROBE_IMAGES = 16,   // with FX_PROBE_COUNT: mark every counted embedding's images
 };
 
 struct FxSeg {
@@ -115,6 +116,8 @@ struct FxSeg {
     FxSummary *sum;
     int32_t *sel_rows;      // selected embeddings (append)
     int64_t *sel_rank;      // their ranks
+    uint32_t *img;          // image bitmaps of the pattern vertices (minimum-image support)
+    uint64_t img_words;     // words per image bitmap
     int64_t nparts;         // rows in level l
     uint64_t t0;            // first flattened candidate of the slice
     int64_t rank_base;      // rank of the first complete embedding this step writes
@@ -141,6 +144,10 @@ struct FxInit {
 
 // Launchers (fx_kernels.hip).  All return the hipError_t of the launches.
 hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *inits, int32_t ninit);
+// Minimum-image support from n image bitmaps of `words` words each: counts[j]
+// = set bits of bitmap j, then *out = min_j counts[j].
+hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int32_t n,
+                         unsigned long long *counts, unsigned long long *out);
 // One step: probe, scan, scatter (+ run-length prefix fix-up), greedy.  items
 // (2, 4 or 8) is the number of candidates per thread; segment j owns
 // ceil(span_j / (FX_BS * items)) consecutive workgroups starting at blk0s[j].

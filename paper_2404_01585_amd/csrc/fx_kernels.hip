@@ -259,6 +259,22 @@ __device__ __forceinline__ void tuple_hash(const Cand &x, int32_t l, uint64_t &h
     h2 = mix64(b ^ (uint64_t)(uint32_t)x.c);
 }
 
+// Marks the images of one embedding (x.v[0..l), x.c): data vertex f(k) in
+// the bitmap of pattern vertex k.  A word is read before the atomic OR, so a
+// vertex already marked (the common case: many embeddings share a partial)
+// costs no atomic.
+__device__ __forceinline__ void mark_images(uint32_t *img, uint64_t words, const Cand &x, int32_t l)
+{
+#pragma unroll
+    for (int k = 0; k < FX_MAXN; k++) {
+        if (k > l) break;
+        const uint32_t v = (uint32_t)(k == l ? x.c : x.v[k]);
+        uint32_t *w = img + (uint64_t)k * words + (v >> 5);
+        const uint32_t bit = 1u << (v & 31u);
+        if (!(*w & bit)) atomicOr(w, bit);
+    }
+}
+
 // Embeddings completing the partial (x.v[0..l), x.c) when the last pattern
 // vertex i = l + 1 is a leaf whose only earlier neighbour is a: every vertex
 // of the run of a's image with i's (label, edge label) is a valid image,
@@ -305,6 +321,7 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
     const bool count = (flags & FX_PROBE_COUNT) != 0;
     const bool leaf = (flags & FX_PROBE_LEAF) != 0;
     const bool hash = (flags & FX_PROBE_HASH) != 0;
+    const bool images = (flags & FX_PROBE_IMAGES) != 0;
     uint32_t passed = 0, bytes = 0, uout = 0;
     unsigned long long cnt = 0;
     uint64_t h1 = 0, h2 = 0;
@@ -335,6 +352,7 @@ __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__re
                         h1 += a;
                         h2 ^= b;
                     }
+                    if (images) mark_images(S.img, S.img_words, x, l);
                 }
                 if (leaf) cnt += leaf_count(g, S.plan, l, x, bytes);
                 mat = S.kind != FX_SEG_COUNT;
@@ -805,6 +823,33 @@ __global__ void k_init(FxGraphDev g, const FxInit *__restrict__ inits)
     }
 }
 
+// Set bits of image bitmap blockIdx.x.
+__global__ __launch_bounds__(1024) void k_mni_count(const uint32_t *__restrict__ img, uint64_t words,
+                                                    unsigned long long *counts)
+{
+    __shared__ unsigned long long part[1024 / 64];
+    const uint32_t *b = img + (uint64_t)blockIdx.x * words;
+    unsigned long long c = 0;
+    for (uint64_t k = threadIdx.x; k < words; k += 1024) c += (unsigned long long)__popc(b[k]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+    if (__lane_id() == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 1024 / 64; w++) t += part[w];
+        counts[blockIdx.x] = t;
+    }
+}
+
+__global__ void k_mni_min(const unsigned long long *__restrict__ counts, int32_t n, unsigned long long *out)
+{
+    if (threadIdx.x != 0) return;
+    unsigned long long m = counts[0];
+    for (int32_t j = 1; j < n; j++) m = counts[j] < m ? counts[j] : m;
+    *out = m;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -815,6 +860,15 @@ hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *init
 {
     if (ninit <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_init, dim3(ninit), dim3(256), 0, s, g, inits);
+    return hipGetLastError();
+}
+
+hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int32_t n,
+                         unsigned long long *counts, unsigned long long *out)
+{
+    if (n <= 0 || n > FX_MAXN) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mni_count, dim3(n), dim3(1024), 0, s, img, words, counts);
+    hipLaunchKernelGGL(k_mni_min, dim3(1), dim3(64), 0, s, counts, n, out);
     return hipGetLastError();
 }
 

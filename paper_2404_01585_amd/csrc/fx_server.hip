@@ -131,7 +131,8 @@ extern "C" fx_status fx_server_submit(fx_server *S, const fx_pattern *p, int64_t
     if (!S || !p || !ticket) return fx_fail(FX_EINVAL, "NULL argument");
     if (sigma < 1) return fx_fail(FX_EINVAL, "sigma must be >= 1");
     if (!(lambda >= 0.0 && lambda <= 1.0)) return fx_fail(FX_EINVAL, "lambda must lie in [0, 1]");
-    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT) return fx_fail(FX_EINVAL, "unknown mode %d", mode);
+    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI)
+        return fx_fail(FX_EINVAL, "unknown mode %d", mode);
     FX_TRY(fx_check_pattern(p));
     auto t = std::make_unique<ServerTicket>();
     t->vl.assign(p->vlabel, p->vlabel + p->n);
@@ -146,7 +147,7 @@ extern "C" fx_status fx_server_submit(fx_server *S, const fx_pattern *p, int64_t
     t->req.pattern = &t->pat;
     t->req.sigma = sigma;
     t->req.lambda = lambda;
-    t->req.kind = mode == FX_MODE_FULL ? FX_Q_FULL : FX_Q_VERDICT;
+    t->req.kind = mode == FX_MODE_FULL ? FX_Q_FULL : (mode == FX_MODE_MNI ? FX_Q_MNI : FX_Q_VERDICT);
     t->req.out = &t->res;
     t->req.user = t.get();
     std::lock_guard<std::mutex> lk(S->mu);

@@ -97,6 +97,47 @@ def test_running_example(ctx, ctx_small):
             list_match(dg, Dm, fx2["Pm"])
 
 
+def mni_match(dg, g, p, sigma):
+    """Minimum-image mode against the oracle: the MNI value, its verdict at
+    sigma, and the embedding count and digest of FULL mode."""
+    want = O.mni(g, p)
+    full = O.query(g, p, sigma, 1.0, O.FULL)
+    got = dg.support(p, sigma, 1.0, fx.MODE_MNI)
+    assert got["support"] == want, (got["support"], want)
+    assert got["tau"] == sigma and got["frequent"] == int(want >= max(sigma, 1))
+    assert got["embedding_count"] == full["embedding_count"] and got["digest"] == full["digest"]
+    assert full["support"] <= want  # the greedy support never exceeds MNI
+    return got
+
+
+def test_mni_mode(ctx, ctx_small, er1k):
+    """Minimum-image support (Section 2.4.4): the running example's printed
+    value, tiny random graphs (also against brute force), sampled patterns on
+    the 1K-vertex graph, alone and as a batch."""
+    fx1 = load_fixture("running_example.txt")
+    with ctx.load_graph(fx1["D"]) as dg:
+        _say("mni running example")
+        assert mni_match(dg, fx1["D"], fx1["P1"], 3)["support"] == 3
+    for idx, g, p in _tiny_cases(40, seed=404):
+        c = ctx if idx % 2 else ctx_small
+        with c.load_graph(g) as dg:
+            _say("mni tiny", idx, "nv", g.num_vertices, "n", p.n)
+            got = mni_match(dg, g, p, 2)
+            if p.n <= 4 and g.num_vertices <= 16:
+                assert got["support"] == O.brute_mni(O.brute_embeddings(g, p), p.n)
+    pats = sample_patterns(er1k, 24, seed=91, kmin=2, kmax=5)
+    for c in (ctx, ctx_small):
+        with c.load_graph(er1k) as dg:
+            alone = []
+            for i, p in enumerate(pats):
+                _say("mni er1k", i, "n", p.n)
+                alone.append(mni_match(dg, er1k, p, 20))
+            mix = dg.support_batch(pats, [20] * len(pats), [1.0] * len(pats), fx.MODE_MNI)
+            for a, b in zip(alone, mix):
+                for k in ("support", "frequent", "embedding_count", "digest", "tau"):
+                    assert a[k] == b[k], k
+
+
 def _tiny_cases(n_cases, seed):
     rng = np.random.default_rng(seed)
     for idx in range(n_cases):
