@@ -554,6 +554,7 @@ fx_status FxEngine::step()
         FX_TRY(W_->boff.ensure((max_blocks + 1) * 8));
         FX_TRY(W_->lsum.ensure(max_blocks * 8));
         FX_TRY(W_->loff.ensure((max_blocks + 1) * 8));
+        FX_TRY(W_->tmap.ensure(max_blocks * sizeof(FxTile)));
         FX_TRY(W_->sums_d.ensure((size_t)A * sizeof(FxSummary)));
         for (auto &L : W_->lane) {
             FX_TRY(L.stage_d.ensure(stage_bytes(A, A)));
@@ -694,9 +695,9 @@ fx_status FxEngine::launch(int g)
                           s_));
     hipEvent_t *ev = P_.timing ? L.evk : nullptr;
     FX_HIP(fx_launch_step(s_, G_->dev, (const FxSeg *)((char *)L.stage_d.p + seg_off), L.stage_d.as<uint32_t>(),
-                          nsegs, nblocks, P_.items,
-                          W_->flag.as<uint8_t>(), W_->bcnt.as<uint32_t>(), W_->boff.as<uint64_t>(),
-                          W_->lsum.as<uint64_t>(), W_->loff.as<uint64_t>(), ev ? ev[0] : nullptr,
+                          nsegs, nblocks, P_.items, W_->tmap.as<FxTile>(), W_->flag.as<uint8_t>(),
+                          W_->bcnt.as<uint32_t>(), W_->boff.as<uint64_t>(), W_->lsum.as<uint64_t>(),
+                          W_->loff.as<uint64_t>(), ev ? ev[0] : nullptr,
                           ev ? ev[1] : nullptr, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
                           ev ? ev[5] : nullptr, any_inner, any_greedy));
     int hi = 0;

@@ -107,7 +107,7 @@ struct EngineLane {
 // steps run one after the other on the engine's stream.
 struct EngineWork {
     RegionPool pool;
-    DevBuf flag, bcnt, boff, lsum, loff, sums_d;
+    DevBuf flag, bcnt, boff, lsum, loff, tmap, sums_d;
     EngineLane lane[2];
     ~EngineWork();
     fx_status init_events();

@@ -130,6 +130,14 @@ struct FxSeg {
     int32_t kind;           // FX_SEG_*
 };
 
+// Where an expansion workgroup's tile lies: its segment and the partials its
+// candidates belong to, [p0, p0 + np).  Found once per step by k_tile_map.
+struct FxTile {
+    int32_t seg;
+    int32_t np;
+    int64_t p0;
+};
+
 // Per-query initialisation at admission: plan upload, U and counters cleared,
 // level 0 set up.
 struct FxInit {
@@ -152,7 +160,7 @@ hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int
 // (2, 4 or 8) is the number of candidates per thread; segment j owns
 // ceil(span_j / (FX_BS * items)) consecutive workgroups starting at blk0s[j].
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                          int32_t nsegs, uint32_t nblocks, int32_t items, uint8_t *flag, uint32_t *bcnt,
+                          int32_t nsegs, uint32_t nblocks, int32_t items, FxTile *tmap, uint8_t *flag, uint32_t *bcnt,
                           uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
                           hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
                           hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy);

@@ -123,15 +123,11 @@ struct TileMap {
     bool staged;
 };
 
-__device__ __forceinline__ TileMap map_tile(const int64_t *__restrict__ off, int64_t nparts, uint64_t tfirst,
-                                            uint64_t tlast, int64_t *s_off, int64_t *s_meta)
+__device__ __forceinline__ TileMap map_tile(const int64_t *__restrict__ off, const FxTile &T, int64_t *s_off)
 {
-    if (threadIdx.x == 0) s_meta[0] = find_part(off, nparts, tfirst);
-    if (threadIdx.x == 64) s_meta[1] = find_part(off, nparts, tlast);
-    __syncthreads();
     TileMap m;
-    m.p0 = s_meta[0];
-    m.np = s_meta[1] - m.p0 + 1;
+    m.p0 = T.p0;
+    m.np = T.np;
     m.staged = m.np + 1 <= FX_LDSP;
     if (m.staged) {
         for (int64_t k = threadIdx.x; k <= m.np; k += FX_BS) s_off[k] = off[m.p0 + k];  // off[p1 + 1] exists
@@ -232,17 +228,33 @@ __device__ __forceinline__ uint64_t lanemask_lt()
 // Expansion: probe (test + per-block counts) and scatter (ordered write).
 // ---------------------------------------------------------------------------
 
-// Segment of workgroup b: the last s with blk0s[s] <= b.  The result is
-// uniform across the workgroup.
-__device__ __forceinline__ int32_t seg_of(const uint32_t *__restrict__ blk0s, int32_t nsegs, uint32_t b)
+// One thread per expansion workgroup b: its segment (the last s with
+// blk0s[s] <= b) and the partials of its tile, by binary searches over the
+// level's candidate offsets -- done here once instead of at the start of
+// every workgroup of the probe, the scatter and the offset fix-up.
+template <int ITEMS>
+__global__ __launch_bounds__(FX_BS) void k_tile_map(const FxSeg *__restrict__ segs, const uint32_t *__restrict__ blk0s,
+                                                    int32_t nsegs, uint32_t nblocks, FxTile *tmap)
 {
+    constexpr uint32_t TILE = FX_BS * ITEMS;
+    const uint32_t b = blockIdx.x * FX_BS + threadIdx.x;
+    if (b >= nblocks) return;
     int32_t lo = 0, hi = nsegs;
     while (hi - lo > 1) {
-        int32_t mid = (lo + hi) >> 1;
+        const int32_t mid = (lo + hi) >> 1;
         if (blk0s[mid] <= b) lo = mid;
         else hi = mid;
     }
-    return __builtin_amdgcn_readfirstlane(lo);
+    const FxSeg &S = segs[lo];
+    const uint32_t tile0 = (b - S.blk0) * TILE;
+    const uint32_t tile_n = min(TILE, S.span - tile0);
+    const int64_t p0 = find_part(S.in.off, S.nparts, S.t0 + tile0);
+    const int64_t p1 = find_part(S.in.off, S.nparts, S.t0 + tile0 + tile_n - 1);
+    FxTile t;
+    t.seg = lo;
+    t.np = (int32_t)(p1 - p0 + 1);
+    t.p0 = p0;
+    tmap[b] = t;
 }
 
 __device__ __forceinline__ void tuple_hash(const Cand &x, int32_t l, uint64_t &h1, uint64_t &h2)
@@ -266,12 +278,13 @@ __device__ __forceinline__ void tuple_hash(const Cand &x, int32_t l, uint64_t &h
 __device__ __forceinline__ void mark_images(uint32_t *img, uint64_t words, const Cand &x, int32_t l)
 {
 #pragma unroll
-    for (int k = 0; k < FX_MAXN; k++) {
-        if (k > l) break;
-        const uint32_t v = (uint32_t)(k == l ? x.c : x.v[k]);
-        uint32_t *w = img + (uint64_t)k * words + (v >> 5);
-        const uint32_t bit = 1u << (v & 31u);
-        if (!(*w & bit)) atomicOr(w, bit);
+    for (int k = 0; k < FX_MAXN; k++) {  // fully unrolled: x.v stays in registers
+        if (k <= l) {
+            const uint32_t v = (uint32_t)(k == l ? x.c : x.v[k]);
+            uint32_t *w = img + (uint64_t)k * words + (v >> 5);
+            const uint32_t bit = 1u << (v & 31u);
+            if (!(*w & bit)) atomicOr(w, bit);
+        }
     }
 }
 
@@ -304,19 +317,16 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
 // Writes a pass flag per candidate and the number of passes per workgroup.
 template <int ITEMS>
 __global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__restrict__ segs,
-                                                 const uint32_t *__restrict__ blk0s, int32_t nsegs, uint8_t *flag,
-                                                 uint32_t *bcnt)
+                                                 const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
     __shared__ int64_t s_off[FX_LDSP + 1];
-    __shared__ int64_t s_meta[2];
     __shared__ uint32_t wcnt[FX_BS / 64];
-    const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
-    const FxSeg &S = segs[si];
+    const FxTile T = tmap[blockIdx.x];
+    const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
     const int32_t l = S.l, n = S.n, flags = S.flags;
     const uint32_t tile0 = (blockIdx.x - S.blk0) * TILE;
-    const uint32_t tile_n = min((uint32_t)TILE, S.span - tile0);
-    const TileMap m = map_tile(S.in.off, S.nparts, S.t0 + tile0, S.t0 + tile0 + tile_n - 1, s_off, s_meta);
+    const TileMap m = map_tile(S.in.off, T, s_off);
     const bool ufilter = (flags & FX_PROBE_UFILTER) != 0;
     const bool count = (flags & FX_PROBE_COUNT) != 0;
     const bool leaf = (flags & FX_PROBE_LEAF) != 0;
@@ -435,17 +445,15 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt
 // than the level holds rows.
 template <int ITEMS>
 __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
-                                                   const uint32_t *__restrict__ blk0s, int32_t nsegs,
-                                                   const uint8_t *__restrict__ flag,
+                                                   const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
                                                    const uint64_t *__restrict__ boff, uint64_t *lsum)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
     __shared__ int64_t s_off[FX_LDSP + 1];
-    __shared__ int64_t s_meta[2];
     __shared__ uint32_t wcnt[ITEMS][FX_BS / 64];
     __shared__ unsigned long long ltot[ITEMS][FX_BS / 64];
-    const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
-    const FxSeg &S = segs[si];
+    const FxTile T = tmap[blockIdx.x];
+    const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
     const int32_t l = S.l, n = S.n;
     const uint64_t seg_base = boff[S.blk0];
     const uint64_t seg_pass = boff[S.blk0 + (S.span + TILE - 1) / TILE] - seg_base;
@@ -469,8 +477,7 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
         bal[it] = __ballot(f[it]);
         if (__lane_id() == 0) wcnt[it][wave] = (uint32_t)__popcll(bal[it]);
     }
-    const uint32_t tile_n = min((uint32_t)TILE, S.span - tile0);
-    const TileMap m = map_tile(S.in.off, S.nparts, S.t0 + tile0, S.t0 + tile0 + tile_n - 1, s_off, s_meta);
+    const TileMap m = map_tile(S.in.off, T, s_off);
     const int32_t w1 = l + 1;
     uint32_t bytes = 0;
     uint64_t pos = boff[blockIdx.x] - seg_base;
@@ -567,13 +574,11 @@ __global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__
 // run-length prefixes k_scatter wrote, and closes each inner level with
 // off[N] and the level's candidate total.
 template <int ITEMS>
-__global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ segs, const uint32_t *__restrict__ blk0s,
-                                                   int32_t nsegs, const uint64_t *__restrict__ boff,
-                                                   const uint64_t *__restrict__ loff)
+__global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap,
+                                                   const uint64_t *__restrict__ boff, const uint64_t *__restrict__ loff)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
-    const int32_t si = seg_of(blk0s, nsegs, blockIdx.x);
-    const FxSeg &S = segs[si];
+    const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(tmap[blockIdx.x].seg)];
     if (S.kind != FX_SEG_INNER) return;
     const uint64_t seg_base = boff[S.blk0];
     const uint64_t cap = S.out_cap;
@@ -874,22 +879,24 @@ hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int
 
 template <int ITEMS>
 hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                             int32_t nsegs, uint32_t nblocks, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
+                             int32_t nsegs, uint32_t nblocks, FxTile *tmap, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
                              uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin, hipEvent_t probe_end,
                              hipEvent_t scatter_begin, hipEvent_t scatter_end, hipEvent_t greedy_begin,
                              hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
 {
     hipError_t e;
+    hipLaunchKernelGGL(k_tile_map<ITEMS>, dim3((nblocks + FX_BS - 1) / FX_BS), dim3(FX_BS), 0, s, segs, blk0s, nsegs,
+                       nblocks, tmap);
     if (probe_begin && (e = hipEventRecord(probe_begin, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_probe<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, bcnt);
+    hipLaunchKernelGGL(k_probe<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, flag, bcnt);
     if (probe_end && (e = hipEventRecord(probe_end, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_blocks<uint32_t>, dim3(1), dim3(1024), 0, s, bcnt, nblocks, boff);
     if (scatter_begin && (e = hipEventRecord(scatter_begin, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scatter<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, blk0s, nsegs, flag, boff, lsum);
+    hipLaunchKernelGGL(k_scatter<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, flag, boff, lsum);
     if (scatter_end && (e = hipEventRecord(scatter_end, s)) != hipSuccess) return e;
     if (any_inner) {
         hipLaunchKernelGGL(k_scan_blocks<uint64_t>, dim3(1), dim3(1024), 0, s, lsum, nblocks, loff);
-        hipLaunchKernelGGL(k_fix_off<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, segs, blk0s, nsegs, boff, loff);
+        hipLaunchKernelGGL(k_fix_off<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, segs, tmap, boff, loff);
     }
     if (greedy_begin && (e = hipEventRecord(greedy_begin, s)) != hipSuccess) return e;
     if (any_greedy) hipLaunchKernelGGL(k_greedy, dim3(nsegs), dim3(FX_BS), 0, s, segs);
@@ -898,22 +905,22 @@ hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *se
 }
 
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                          int32_t nsegs, uint32_t nblocks, int32_t items, uint8_t *flag, uint32_t *bcnt,
-                          uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
+                          int32_t nsegs, uint32_t nblocks, int32_t items, FxTile *tmap, uint8_t *flag,
+                          uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
                           hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
                           hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
 {
     switch (items) {
     case 2:
-        return launch_step_items<2>(s, g, segs, blk0s, nsegs, nblocks, flag, bcnt, boff, lsum, loff, probe_begin,
+        return launch_step_items<2>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff, probe_begin,
                                     probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end, any_inner,
                                     any_greedy);
     case 8:
-        return launch_step_items<8>(s, g, segs, blk0s, nsegs, nblocks, flag, bcnt, boff, lsum, loff, probe_begin,
+        return launch_step_items<8>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff, probe_begin,
                                     probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end, any_inner,
                                     any_greedy);
     default:
-        return launch_step_items<4>(s, g, segs, blk0s, nsegs, nblocks, flag, bcnt, boff, lsum, loff, probe_begin,
+        return launch_step_items<4>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff, probe_begin,
                                     probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end, any_inner,
                                     any_greedy);
     }
