@@ -316,7 +316,7 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
 // the workgroup size so each item pass covers consecutive candidates).
 // Writes a pass flag per candidate and the number of passes per workgroup.
 template <int ITEMS>
-__global__ __launch_bounds__(FX_BS) void k_probe(FxGraphDev g, const FxSeg *__restrict__ segs,
+__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe(FxGraphDev g, const FxSeg *__restrict__ segs,
                                                  const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
