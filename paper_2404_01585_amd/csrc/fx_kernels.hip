@@ -444,7 +444,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt
 // probed again in a later step), so a slice may span many more candidates
 // than the level holds rows.
 template <int ITEMS>
-__global__ __launch_bounds__(FX_BS) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
+__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
                                                    const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
                                                    const uint64_t *__restrict__ boff, uint64_t *lsum)
 {
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ seg
 // is the bitmap of Section 3.2.2).  Embeddings are taken in chunks of at most
 // FX_GREEDY_VN vertices.  Per chunk: drop embeddings that meet U, hash their
 // data vertices into LDS slots (the overlap structure), then run rounds: every
-// undecided embedding writes ((~round) << 32 | rank) into its slots with an
+// undecided embedding writes ((~round) << 16 | rank) into its slots with an
 // atomic min, and is selected when it holds the minimum of all its slots --
 // i.e. it ranks below every undecided embedding it overlaps.  Slot value 0
 // marks a slot taken by a selected embedding; an undecided embedding that
@@ -635,7 +635,7 @@ __device__ __forceinline__ bool used_coherent(const uint32_t *U, int32_t v)
 // greedy (a selected embedding has no undecided lower-ranked neighbour), so
 // the result is still the sequential greedy's.  Selections are marked 3; the
 // caller writes them out.
-__device__ void greedy_tail(uint8_t *state, const uint16_t *slot, unsigned long long *hval, uint32_t nb, int32_t n)
+__device__ void greedy_tail(uint8_t *state, const uint16_t *slot, uint32_t *hval, uint32_t nb, int32_t n)
 {
     const uint32_t lane = threadIdx.x;  // wave 0
     for (uint32_t base = 0; base < nb; base += 64) {
@@ -646,7 +646,7 @@ __device__ void greedy_tail(uint8_t *state, const uint16_t *slot, unsigned long 
 #pragma unroll
         for (int j = 0; j < FX_MAXN; j++) {
             s[j] = (und && j < n) ? (uint32_t)slot[e * n + j] : 0xffffffffu;
-            if (und && j < n) blocked = blocked || hval[s[j]] == 0ULL;
+            if (und && j < n) blocked = blocked || hval[s[j]] == 0u;
         }
         if (und && blocked) state[e] = 2;
         uint64_t M = __ballot(und && !blocked);
@@ -658,7 +658,7 @@ __device__ void greedy_tail(uint8_t *state, const uint16_t *slot, unsigned long 
                 const uint32_t fs = slot[ef * n + j];
 #pragma unroll
                 for (int k = 0; k < FX_MAXN; k++) conf = conf || s[k] == fs;
-                if (lane == (uint32_t)j) hval[fs] = 0ULL;
+                if (lane == (uint32_t)j) hval[fs] = 0u;
             }
             const bool in_m = (M >> lane) & 1ull;
             const bool drop = in_m && lane != f && conf;
@@ -673,8 +673,11 @@ __device__ void greedy_tail(uint8_t *state, const uint16_t *slot, unsigned long 
 __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs)
 {
     static_assert(FX_GREEDY_H == 4096, "lds_hash takes the top 12 bits");
+    // 32-bit slot keys: a chunk's ranks and rounds (at most one per embedding)
+    // stay below 2^16, and no key is 0 (the taken mark)
+    static_assert(FX_GREEDY_VN < 0xffff, "rank and round must fit 16 bits");
     __shared__ int32_t hkey[FX_GREEDY_H];
-    __shared__ unsigned long long hval[FX_GREEDY_H];
+    __shared__ uint32_t hval[FX_GREEDY_H];  // (~round) << 16 | rank in chunk; 0 = taken
     __shared__ uint16_t slot[FX_GREEDY_VN];
     __shared__ uint8_t state[FX_GREEDY_VN];  // 0 undecided, 1 selected, 2 out, 3 selected by the tail
     __shared__ uint32_t undecided, nsel;
@@ -691,7 +694,7 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
         const uint32_t nb = (uint32_t)((N - c0) < B ? (N - c0) : B);
         for (uint32_t k = threadIdx.x; k < FX_GREEDY_H; k += FX_BS) {
             hkey[k] = -1;
-            hval[k] = ~0ULL;
+            hval[k] = ~0u;
         }
         if (threadIdx.x == 0) nsel = 0;
         __syncthreads();
@@ -725,24 +728,24 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
             for (uint32_t e = threadIdx.x; e < nb; e += FX_BS) {
                 if (state[e] != 0) continue;
                 bool out = false;
-                for (int j = 0; j < n; j++) out = out || (hval[slot[e * n + j]] == 0ULL);
+                for (int j = 0; j < n; j++) out = out || (hval[slot[e * n + j]] == 0u);
                 if (out) {
                     state[e] = 2;
                     continue;
                 }
-                const unsigned long long key = ((unsigned long long)(0xffffffffu - r) << 32) | e;
+                const uint32_t key = ((0xffffu - r) << 16) | e;
                 for (int j = 0; j < n; j++) atomicMin(&hval[slot[e * n + j]], key);
             }
             __syncthreads();
             uint32_t mine_undecided = 0;
             for (uint32_t e = threadIdx.x; e < nb; e += FX_BS) {
                 if (state[e] != 0) continue;
-                const unsigned long long key = ((unsigned long long)(0xffffffffu - r) << 32) | e;
+                const uint32_t key = ((0xffffu - r) << 16) | e;
                 bool mine = true;
                 for (int j = 0; j < n; j++) mine = mine && (hval[slot[e * n + j]] == key);
                 if (mine) {
                     state[e] = 1;
-                    for (int j = 0; j < n; j++) hval[slot[e * n + j]] = 0ULL;
+                    for (int j = 0; j < n; j++) hval[slot[e * n + j]] = 0u;
                 } else {
                     mine_undecided++;
                 }
