@@ -292,9 +292,10 @@ fx_status fx_server_destroy(fx_server *s);
  * given sample while it walks the tunables one at a time: candidates per
  * thread of the expansion kernels (2, 4, 8: the workgroup tile), candidates
  * per device step, the level capacity of a pattern's slice stack (the frontier
- * chunk), the complete embeddings per greedy slice and the number of pipeline
+ * chunk), the complete embeddings per greedy slice, the number of pipeline
  * lanes (1: one device step at a time; 2: the host prepares one lane's step
- * while the other lane's runs).  The fastest setting
+ * while the other lane's runs) and the patterns in flight at once.  The
+ * fastest setting
  * is kept in the context (later calls use it; results never depend on it).
  * cache_path (optional): a text file of tuned keys (architecture, graph shape,
  * largest pattern, mode); a cached key is applied without timing. */
@@ -308,7 +309,7 @@ typedef struct {
     int32_t trials;
     int32_t from_cache;
     int32_t lanes;
-    int32_t reserved;
+    int32_t max_active;
 } fx_tune_result;
 
 fx_status fx_autotune(fx_graph *g, int32_t npat, const fx_pattern *pats, const int64_t *sigma, const double *lambda,

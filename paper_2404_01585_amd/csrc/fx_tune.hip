@@ -30,7 +30,7 @@ std::string tune_key(const fx_graph *G, int32_t npat, const fx_pattern *pats, in
     for (int32_t i = 0; i < npat; i++) nmax = std::max(nmax, pats[i].n);
     std::ostringstream k;
     k << arch << "|nv=" << G->nv << "|adj=" << G->nadj << "|vl=" << G->vl_values.size() << "|el="
-      << G->el_values.size() << "|n=" << nmax << "|mode=" << mode << "|digest=" << (G->ctx->params.no_digest ? 0 : 1) << "|v2";
+      << G->el_values.size() << "|n=" << nmax << "|mode=" << mode << "|digest=" << (G->ctx->params.no_digest ? 0 : 1) << "|v3";
     return k.str();
 }
 
@@ -44,9 +44,10 @@ bool cache_lookup(const char *path, const std::string &key, EngineParams &p, dou
         std::istringstream in(line);
         std::string k;
         long long slice, step;
-        int items, last, lanes;
+        int items, last, lanes, active;
         double t;
-        if (in >> k >> slice >> step >> items >> last >> lanes >> t && k == key) {
+        if (in >> k >> slice >> step >> items >> last >> lanes >> active >> t && k == key) {
+            p.max_active = active;
             p.slice_rows = slice;
             p.step_candidates = (uint64_t)step;
             p.items = items;
@@ -64,7 +65,7 @@ void cache_store(const char *path, const std::string &key, const EngineParams &p
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     f << key << " " << p.slice_rows << " " << p.step_candidates << " " << p.items << " " << p.last_span_init << " "
-      << p.lanes << " " << ms << "\n";
+      << p.lanes << " " << p.max_active << " " << ms << "\n";
 }
 
 }  // namespace
@@ -92,6 +93,7 @@ extern "C" fx_status fx_autotune(fx_graph *g, int32_t npat, const fx_pattern *pa
         r.items_per_thread = cached.items;
         r.last_span_init = (int32_t)cached.last_span_init;
         r.lanes = cached.lanes;
+        r.max_active = cached.max_active;
         r.best_ms = cached_ms;
         r.from_cache = 1;
         *out = r;
@@ -142,6 +144,7 @@ extern "C" fx_status fx_autotune(fx_graph *g, int32_t npat, const fx_pattern *pa
     FX_TRY(sweep([](EngineParams &p, long long v) { p.slice_rows = v; }, {1ll << 15, 1ll << 16, 1ll << 17, 1ll << 18}));
     FX_TRY(sweep([](EngineParams &p, long long v) { p.last_span_init = (uint32_t)v; }, {1024, 4096, 16384}));
     FX_TRY(sweep([](EngineParams &p, long long v) { p.lanes = (int32_t)v; }, {1, 2}));
+    FX_TRY(sweep([](EngineParams &p, long long v) { p.max_active = (int32_t)v; }, {4096, 16384}));
     c->params = best;
     cache_store(cache_path, key, best, best_ms);
     r.slice_rows = best.slice_rows;
@@ -149,6 +152,7 @@ extern "C" fx_status fx_autotune(fx_graph *g, int32_t npat, const fx_pattern *pa
     r.items_per_thread = best.items;
     r.last_span_init = (int32_t)best.last_span_init;
     r.lanes = best.lanes;
+    r.max_active = best.max_active;
     r.best_ms = best_ms;
     *out = r;
     return FX_OK;

@@ -77,7 +77,7 @@ class TuneC(ctypes.Structure):
     _fields_ = [("slice_rows", ctypes.c_int64), ("step_candidates", ctypes.c_int64),
                 ("items_per_thread", ctypes.c_int32), ("last_span_init", ctypes.c_int32), ("best_ms", ctypes.c_double),
                 ("default_ms", ctypes.c_double), ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32),
-                ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32), ("max_active", ctypes.c_int32)]
 
     def to_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

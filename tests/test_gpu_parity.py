@@ -438,7 +438,7 @@ def test_autotune_keeps_results(torch_cuda, er1k, tmp_path):
                 assert r[k] == want[k], (p, k)
         t2 = dg.autotune(batch, 20, 1.0, fx.MODE_FULL, cache_path=cache)
         assert t2["from_cache"] == 1
-        for k in ("slice_rows", "step_candidates", "items_per_thread", "last_span_init", "lanes"):
+        for k in ("slice_rows", "step_candidates", "items_per_thread", "last_span_init", "lanes", "max_active"):
             assert t2[k] == t1[k]
         assert t1["lanes"] in (1, 2)
     c.close()
@@ -459,7 +459,7 @@ def test_launch_shapes_agree(torch_cuda, er1k, tmp_path):
             dg.autotune(batch, 20, 1.0, fx.MODE_FULL, cache_path=cache)  # writes the key
             key = open(cache).read().split()[0]
             with open(cache, "w") as f:
-                f.write(f"{key} {slice_rows} {1 << 22} {items} {last} {lanes} 1.0\n")
+                f.write(f"{key} {slice_rows} {1 << 22} {items} {last} {lanes} {64 if lanes == 1 else 4096} 1.0\n")
             t = dg.autotune(batch, 20, 1.0, fx.MODE_FULL, cache_path=cache)
             assert t["from_cache"] == 1 and t["lanes"] == lanes and t["items_per_thread"] == items
             _say("shape", items, lanes, slice_rows, last)
