@@ -53,6 +53,10 @@ WORKLOADS = {
                       desc="R-MAT scale 22 (4,194,304 vertices, 40M edges, a,b,c = 0.57,0.19,0.19), 50 Zipf(1.1) "
                            "vertex labels, 4 edge labels, int64 offsets; all candidates of mining levels 1-2 at "
                            "sigma=2000, lambda=1.0"),
+    "cl100k-v4": dict(graph="cl100k", sigma=200, lam=1.0, vertices=4,
+                      desc="Chung-Lu 100K vertices / 500K edges (gamma 2.1), 20 Zipf(1.2) vertex labels, "
+                           "3 edge labels; all candidates of the merge generator (levels by vertex count) up to "
+                           "4 vertices at sigma=200, lambda=1.0"),
     "er1k-l4": dict(graph="er1k", sigma=20, lam=1.0, levels=4,
                     desc="Erdos-Renyi 1K vertices / 4K edges, 5 uniform vertex labels, 1 edge label; all "
                          "candidates of mining levels 1-4 at sigma=20, lambda=1.0"),
@@ -75,6 +79,16 @@ def build_candidates(dg, g, spec):
         sm = spec["sample"]
         cands = sample_patterns(g, sm["count"], seed=sm["seed"], kmin=sm["kmin"], kmax=sm["kmax"])
         return cands, [len(cands)]
+
+    if "vertices" in spec:  # Algorithm 1 with the merge generator (Algorithms 2-4)
+        from paper_2404_01585_amd import generate
+
+        def ev(ps, sigma, lam):
+            return dg.support_batch(ps, [sigma] * len(ps), [lam] * len(ps), fx.MODE_VERDICT)
+
+        res = generate.mine_by_vertices(g, spec["sigma"], spec["lam"], spec["vertices"], ev, fx.tau)
+        cands = [p for lvl in res["levels"] for p in lvl]
+        return cands, [len(l) for l in res["levels"]]
 
     def evaluate(ps, sigma, lam):
         return dg.support_batch(ps, [sigma] * len(ps), [lam] * len(ps), fx.MODE_VERDICT)
@@ -328,8 +342,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in the design "
-                                   "notes but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (the library has no multi-GPU path; "
+                                   "sharding by pattern is described in the design notes)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     threads = max(1, min(16, len(os.sched_getaffinity(0))))

@@ -316,11 +316,12 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
 // the workgroup size so each item pass covers consecutive candidates).
 // Writes a pass flag per candidate and the number of passes per workgroup.
 template <int ITEMS>
-__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe(FxGraphDev g, const FxSeg *__restrict__ segs,
-                                                 const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt)
+__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe(
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
     __shared__ int64_t s_off[FX_LDSP + 1];
+    __shared__ uint8_t s_dead[FX_LDSP];
     __shared__ uint32_t wcnt[FX_BS / 64];
     const FxTile T = tmap[blockIdx.x];
     const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
@@ -328,11 +329,25 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     const uint32_t tile0 = (blockIdx.x - S.blk0) * TILE;
     const TileMap m = map_tile(S.in.off, T, s_off);
     const bool ufilter = (flags & FX_PROBE_UFILTER) != 0;
+    uint32_t bytes = 0;
+    // The used-set test of a partial's own vertices, once per partial of the
+    // tile (a partial with many candidates is tested once, not per candidate).
+    const bool pdead = ufilter && m.staged;
+    if (pdead) {
+        for (int64_t k = threadIdx.x; k < m.np; k += FX_BS) {
+            const int32_t *row = S.in.rows + (m.p0 + k) * l;
+            bool d = false;
+            for (int32_t j = 0; j < l; j++) d = d || is_used(S.U, row[j]);
+            s_dead[k] = d ? 1 : 0;
+            bytes += 4u * (uint32_t)l;
+        }
+        __syncthreads();
+    }
     const bool count = (flags & FX_PROBE_COUNT) != 0;
     const bool leaf = (flags & FX_PROBE_LEAF) != 0;
     const bool hash = (flags & FX_PROBE_HASH) != 0;
     const bool images = (flags & FX_PROBE_IMAGES) != 0;
-    uint32_t passed = 0, bytes = 0, uout = 0;
+    uint32_t passed = 0, uout = 0;
     unsigned long long cnt = 0;
     uint64_t h1 = 0, h2 = 0;
 #pragma unroll
@@ -342,15 +357,21 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
         if (tl < S.span) {
             const uint64_t t = S.t0 + tl;
             Cand x;
-            load_cand(g, S.in, l, tile_part(m, S.in.off, s_off, t), t, x);
+            const int64_t p = tile_part(m, S.in.off, s_off, t);
+            load_cand(g, S.in, l, p, t, x);
             // candidate entry + flag; the partial row and its run descriptor once
             bytes += (x.anc >= 0 ? 8u : 4u) + 1u;
             if (x.first || tl == tile0) bytes += 4u * (uint32_t)l + 21u;
             bool ok = true;
             if (ufilter) {
-                ok = !touches_used(S.U, x, l);
+                if (pdead) {
+                    ok = !s_dead[p - m.p0] && !is_used(S.U, x.c);
+                    bytes += 4u;
+                } else {
+                    ok = !touches_used(S.U, x, l);
+                    bytes += 4u * (uint32_t)(l + 1);
+                }
                 uout += ok ? 0u : 1u;
-                bytes += 4u * (uint32_t)(l + 1);
             }
             if (ok) ok = feasible(g, S.plan, n, l, x, bytes);
             if (ok) {

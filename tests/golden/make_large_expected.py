@@ -5,9 +5,10 @@ value here comes from the device path.  Each pattern is answered in a worker
 process under a time limit; patterns the oracle does not finish in time are
 left out of the file (the selection is recorded, not re-derived).
 
-    python tests/golden/make_large_expected.py [--workers 8] [--limit 120]
+    python tests/golden/make_large_expected.py [--workers 8] [--limit 120] [--set large|cl100k]
 
-Output: tests/golden/large_expected.json
+Output: tests/golden/large_expected.json (the 1M-vertex Chung-Lu and 4M-vertex
+R-MAT sets) or tests/golden/cl100k_expected.json (the 100K-vertex Chung-Lu set).
 """
 
 import argparse
@@ -53,6 +54,23 @@ def _answer(args):
                 oracle_s=round(time.time() - t, 3))
 
 
+def _cases_cl100k():
+    import numpy as np
+
+    from paper_2404_01585_amd.synth import sample_patterns, workload_graph
+
+    out = []
+    rng = np.random.default_rng(2027)
+    # 100K-vertex Chung-Lu with 3 edge labels: 200 sampled patterns of each size
+    # 2, 3 and 4 (the sizes of mining levels 1-3), sigma 200, lambda 0.3 or 1.0
+    g = workload_graph("cl100k")
+    for k in (2, 3, 4):
+        for p in sample_patterns(g, 200, seed=60 + k, kmin=k, kmax=k):
+            out.append(("cl100k", dict(vlabel=p.vlabel, edges=[list(e) for e in p.edges], elabel=p.elabel), 200,
+                        float(rng.choice([0.3, 1.0]))))
+    return out
+
+
 def _cases():
     import numpy as np
 
@@ -77,8 +95,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--limit", type=float, default=120.0, help="seconds per pattern")
+    ap.add_argument("--set", default="large", choices=["large", "cl100k"])
     args = ap.parse_args()
-    cases = _cases()
+    cases = _cases() if args.set == "large" else _cases_cl100k()
     for name in sorted({c[0] for c in cases}):
         _graph(name)  # built once here; the forked workers share it
     results, skipped = [], []
@@ -95,7 +114,8 @@ def main():
                     skipped.append(dict(graph=c[0], pattern=c[1]))
             pool.terminate()
         print(f"{start + len(chunk)}/{len(cases)} done, {len(skipped)} skipped", flush=True)
-    with open(os.path.join(HERE, "large_expected.json"), "w") as f:
+    name = "large_expected.json" if args.set == "large" else "cl100k_expected.json"
+    with open(os.path.join(HERE, name), "w") as f:
         json.dump(dict(count_cap=COUNT_CAP, results=results, skipped=skipped), f)
     print(len(results), "stored")
 

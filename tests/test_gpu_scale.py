@@ -1,8 +1,8 @@
-"""Parity at full size: sampled patterns on the 1M-vertex Chung-Lu graph and
-the 4M-vertex R-MAT graph, answered as one batch per graph (the way the
-benchmark runs them), against the oracle's answers stored in
-tests/golden/large_expected.json (written by make_large_expected.py, which
-calls only the oracle).  The embedding count is capped at the stored cap on
+"""Parity at full size: sampled patterns on the 100K- and 1M-vertex Chung-Lu
+graphs and the 4M-vertex R-MAT graph, answered as one batch per graph (the
+way the benchmark runs them), against the oracle's answers stored in
+tests/golden/cl100k_expected.json and large_expected.json (written by
+make_large_expected.py, which calls only the oracle).  The embedding count is capped at the stored cap on
 both sides; the digest is compared where the count did not saturate.
 
 Two launch configurations: with the digest (the count phase enumerates and
@@ -31,6 +31,12 @@ def _say(*a):
 @pytest.fixture(scope="module")
 def expected():
     with open(os.path.join(HERE, "golden", "large_expected.json")) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def expected_cl100k():
+    with open(os.path.join(HERE, "golden", "cl100k_expected.json")) as f:
         return json.load(f)
 
 
@@ -72,6 +78,13 @@ def _check(name, expected, no_digest):
         for k in ("tau", "support", "frequent"):
             assert gv[k] == wv[k], (name, i, k, gv[k], wv[k])
     _say(name, "ok", len(cases), "patterns")
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("no_digest", [False, True])
+def test_cl100k_sampled(torch_cuda, expected_cl100k, no_digest):
+    """200 sampled patterns of each of 2, 3 and 4 vertices (mining levels 1-3)."""
+    _check("cl100k", expected_cl100k, no_digest)
 
 
 @pytest.mark.timeout(600)
