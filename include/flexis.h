@@ -71,9 +71,12 @@ typedef struct fx_server fx_server;
  *   hip_stream        hipStream_t to run on; NULL means the null stream.
  *   slice_rows        capacity, in partial embeddings, of each level of a
  *                     pattern's slice stack (0 = default 2^17): one step
- *                     expands at most this many candidates of a level.  A
+ *                     writes at most this many partial embeddings of a level
+ *                     (it may probe more candidates when few of them pass).  A
  *                     pattern's stack takes about slice_rows * (4 l + 25)
- *                     bytes per level l.
+ *                     bytes per level l.  When few patterns are left, a
+ *                     long-running pattern's stack may be moved to a larger
+ *                     capacity (up to 2^23 rows, within mem_budget_bytes).
  *   count_cap         saturation cap of the embedding count (0 = 2^62).
  *   mem_budget_bytes  device memory the per-pattern stacks of one batch may
  *                     hold at once (0 = 64 GiB); patterns are admitted while
