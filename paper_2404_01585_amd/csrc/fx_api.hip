@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fx_host.h"
@@ -70,74 +71,6 @@ fx_status HostBuf::ensure(size_t want)
     }
     bytes = b;
     return FX_OK;
-}
-
-RegionPool::~RegionPool()
-{
-    for (auto &c : chunks)
-        if (c.base) (void)hipFree(c.base);
-}
-
-fx_status RegionPool::take(size_t bytes, void **out, bool quiet)
-{
-    bytes = (bytes + 255) & ~(size_t)255;
-    for (auto &c : chunks)
-        for (auto it = c.free_.begin(); it != c.free_.end(); ++it)
-            if (it->second >= bytes) {  // first fit
-                const size_t off = it->first, len = it->second;
-                c.free_.erase(it);
-                if (len > bytes) c.free_[off + bytes] = len - bytes;
-                *out = c.base + off;
-                in_use += bytes;
-                return FX_OK;
-            }
-    if (held + bytes > budget) {
-        *out = nullptr;
-        if (quiet) return FX_ENOMEM;
-        return fx_fail(FX_ENOMEM, "query region of %zu bytes does not fit in the %zu-byte budget", bytes, budget);
-    }
-    Chunk c;
-    c.size = std::min(std::max(bytes, kChunk), budget - held);
-    hipError_t e = hipMalloc((void **)&c.base, c.size);
-    if (e != hipSuccess) {
-        *out = nullptr;
-        (void)hipGetLastError();
-        if (quiet) return FX_ENOMEM;
-        return fx_fail(FX_ENOMEM, "hipMalloc(%zu) for query regions failed: %s", c.size, hipGetErrorString(e));
-    }
-    held += c.size;
-    if (c.size > bytes) c.free_[bytes] = c.size - bytes;
-    *out = c.base;
-    in_use += bytes;
-    chunks.push_back(std::move(c));
-    return FX_OK;
-}
-
-void RegionPool::give(void *p, size_t bytes)
-{
-    if (!p) return;
-    bytes = (bytes + 255) & ~(size_t)255;
-    for (auto &c : chunks) {
-        char *q = (char *)p;
-        if (q < c.base || q >= c.base + c.size) continue;
-        size_t off = (size_t)(q - c.base), len = bytes;
-        auto next = c.free_.lower_bound(off);
-        if (next != c.free_.end() && next->first == off + len) {  // merge with the following range
-            len += next->second;
-            next = c.free_.erase(next);
-        }
-        if (next != c.free_.begin()) {  // merge with the preceding range
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                off = prev->first;
-                len += prev->second;
-                c.free_.erase(prev);
-            }
-        }
-        c.free_[off] = len;
-        in_use -= bytes;
-        return;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -270,10 +203,31 @@ extern "C" fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_patter
     if (!g || npat < 0 || (npat > 0 && (!pats || !sigma || !lambda || !out))) return fx_fail(FX_EINVAL, "bad batch");
     if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI)
         return fx_fail(FX_EINVAL, "unknown mode %d", mode);
-    for (int32_t i = 0; i < npat; i++) {
-        if (sigma[i] < 1) return fx_fail(FX_EINVAL, "pattern %d: sigma must be >= 1", i);
-        if (!(lambda[i] >= 0.0 && lambda[i] <= 1.0)) return fx_fail(FX_EINVAL, "pattern %d: lambda outside [0, 1]", i);
-        FX_TRY(fx_check_pattern(&pats[i]));
+    {
+        // validate everything before any device work; large batches on several
+        // threads, the first bad pattern then re-checked here for its message
+        const int32_t nt = npat >= 4096 ? (int32_t)std::max(1u, std::min(16u, std::thread::hardware_concurrency())) : 1;
+        std::vector<int32_t> first_bad(nt, npat);
+        auto check = [&](int32_t t) {
+            for (int32_t i = t; i < npat; i += nt) {
+                const bool ok = sigma[i] >= 1 && lambda[i] >= 0.0 && lambda[i] <= 1.0 && fx_check_pattern(&pats[i]) == FX_OK;
+                if (!ok) {
+                    first_bad[t] = i;
+                    return;
+                }
+            }
+        };
+        std::vector<std::thread> th;
+        for (int32_t t = 1; t < nt; t++) th.emplace_back(check, t);
+        check(0);
+        for (auto &x : th) x.join();
+        const int32_t i = *std::min_element(first_bad.begin(), first_bad.end());
+        if (i < npat) {
+            if (sigma[i] < 1) return fx_fail(FX_EINVAL, "pattern %d: sigma must be >= 1", i);
+            if (!(lambda[i] >= 0.0 && lambda[i] <= 1.0))
+                return fx_fail(FX_EINVAL, "pattern %d: lambda outside [0, 1]", i);
+            FX_TRY(fx_check_pattern(&pats[i]));
+        }
     }
     FX_HIP(hipSetDevice(g->ctx->device));
     std::vector<FxRequest> reqs(npat);

@@ -23,6 +23,7 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <thread>
 
 #include "fx_host.h"
 
@@ -78,7 +79,7 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
     for (int i = 0; i < n; i++) {
         auto it = G->vl_map.find(p->vlabel[i]);
         if (it == G->vl_map.end()) hp.empty = true;
-        else P.vl[i] = it->second;
+        else P.vl[i] = (uint16_t)it->second;
     }
     for (int k = 0; k < p->m; k++) {
         int a = p->edges[2 * k], b = p->edges[2 * k + 1];
@@ -95,33 +96,34 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
         P.nback[i] = 0;
         for (int b = 0; b < i; b++)
             if (el[b][i] >= 0) {
-                P.back[i][P.nback[i]] = b;
-                P.bel[i][P.nback[i]] = (uint32_t)el[b][i];
+                P.back[i][P.nback[i]] = (int8_t)b;
+                P.bel[i][P.nback[i]] = (uint16_t)el[b][i];
                 P.nback[i]++;
             }
         // neighbour-label filter over later neighbours: worthwhile for the
         // root and for vertices that need two or more later neighbours
-        std::vector<std::pair<uint64_t, int>> need;
+        std::pair<uint32_t, int> need_buf[FX_MAXN];
+        int nneed = 0;
         int later = 0;
         for (int j = i + 1; j < n; j++)
             if (el[i][j] >= 0) {
                 later++;
-                uint64_t key = ((uint64_t)P.vl[j] << 48) | ((uint64_t)el[i][j] << 32);
+                const uint32_t key = ((uint32_t)P.vl[j] << 16) | (uint32_t)el[i][j];
                 bool found = false;
-                for (auto &q : need)
-                    if (q.first == key) {
-                        q.second++;
+                for (int q = 0; q < nneed; q++)
+                    if (need_buf[q].first == key) {
+                        need_buf[q].second++;
                         found = true;
                     }
-                if (!found) need.push_back({key, 1});
+                if (!found) need_buf[nneed++] = {key, 1};
             }
         P.nnlf[i] = 0;
         if (i < n - 1 && (i == 0 || later >= 2)) {
-            std::sort(need.begin(), need.end(), [](auto &x, auto &y) { return x.second > y.second; });
-            for (auto &q : need) {
+            std::stable_sort(need_buf, need_buf + nneed, [](auto &x, auto &y) { return x.second > y.second; });
+            for (int q = 0; q < nneed; q++) {
                 if (P.nnlf[i] == FX_NLF) break;
-                P.nlf_key[i][P.nnlf[i]] = q.first;
-                P.nlf_need[i][P.nnlf[i]] = q.second;
+                P.nlf_key[i][P.nnlf[i]] = need_buf[q].first;
+                P.nlf_need[i][P.nnlf[i]] = (uint8_t)need_buf[q].second;
                 P.nnlf[i]++;
             }
         }
@@ -129,11 +131,16 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
     // upper bound on any independent set: disjoint images (bound of Section 3.1.2)
     int64_t ub = G->nv / n;
     if (!hp.empty) {
-        std::unordered_map<uint32_t, int> cnt;
-        for (int i = 0; i < n; i++) cnt[P.vl[i]]++;
-        for (auto &kv : cnt) {
-            int64_t sz = G->bptr[kv.first + 1] - G->bptr[kv.first];
-            ub = std::min<int64_t>(ub, sz / kv.second);
+        for (int i = 0; i < n; i++) {  // label multiplicity, counted at its first vertex
+            int c = 0, first = i;
+            for (int j = 0; j < n; j++)
+                if (P.vl[j] == P.vl[i]) {
+                    c++;
+                    if (j < first) first = j;
+                }
+            if (first != i) continue;
+            const int64_t sz = G->bptr[P.vl[i] + 1] - G->bptr[P.vl[i]];
+            ub = std::min<int64_t>(ub, sz / c);
         }
     } else {
         ub = 0;
@@ -193,6 +200,7 @@ struct FxQuery {
     double alg_probe_credit = 0;           // of those, the share of the candidates taken
     uint64_t probed_support = 0;           // candidates probed in the support phase
     int32_t steps = 0;
+    int deep = -1;                         // deepest level with candidates left (-1: none)
     int64_t listed = 0;
     // the segment of the current step (-1: none)
     int seg_l = -1, seg_kind = 0;
@@ -272,9 +280,30 @@ void restart_stack(FxQuery &q, const fx_graph *G)
     for (int l = 0; l <= q.n; l++) q.T[l] = q.cur[l] = 0, q.nparts[l] = 0;
     q.T[0] = (uint64_t)(G->bptr[vl0 + 1] - G->bptr[vl0]);
     q.nparts[0] = 1;
+    q.deep = deepest_open_level(q);
 }
 
 }  // namespace
+
+namespace {
+
+bool hip_region_alloc(void **p, size_t bytes)
+{
+    if (hipMalloc(p, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+}
+
+void hip_region_free(void *p) { (void)hipFree(p); }
+
+}  // namespace
+
+EngineWork::EngineWork()
+{
+    pool.alloc_fn = hip_region_alloc;
+    pool.free_fn = hip_region_free;
+}
 
 EngineWork::~EngineWork()
 {
@@ -322,19 +351,43 @@ void FxEngine::done(FxRequest *r)
     if (on_done) on_done(r);
 }
 
-void FxEngine::add(FxRequest *r)
+std::unique_ptr<FxQuery> FxEngine::prepare(FxRequest *r) const
 {
     auto q = std::make_unique<FxQuery>();
     q->req = r;
     r->status = fx_build_plan(G_, r->pattern, q->hp);
-    if (r->status != FX_OK) return done(r);
+    if (r->status != FX_OK) return q;
     q->n = r->pattern->n;
     if (r->kind != FX_Q_LIST) {
         r->status = fx_tau_checked(r->sigma, r->lambda, q->n, &q->tau);
-        if (r->status != FX_OK) return done(r);
+        if (r->status != FX_OK) return q;
         if (r->kind == FX_Q_MNI) q->tau = r->sigma;  // the minimum-image threshold is sigma itself
         q->tau_eff = std::max<int64_t>(q->tau, 1);
     }
+    return q;
+}
+
+void FxEngine::add(FxRequest *r) { enqueue(prepare(r)); }
+
+void FxEngine::add_all(FxRequest *reqs, size_t count)
+{
+    std::vector<std::unique_ptr<FxQuery>> qs(count);
+    const size_t hw = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+    const size_t nt = count >= 2048 ? hw : 1;  // plans are cheap: threads only pay for big batches
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; t++)
+        th.emplace_back([&, t] {
+            for (size_t i = t; i < count; i += nt) qs[i] = prepare(&reqs[i]);
+        });
+    for (size_t i = 0; i < count; i += nt) qs[i] = prepare(&reqs[i]);
+    for (auto &x : th) x.join();
+    for (auto &q : qs) enqueue(std::move(q));
+}
+
+void FxEngine::enqueue(std::unique_ptr<FxQuery> q)
+{
+    FxRequest *r = q->req;
+    if (r->status != FX_OK) return done(r);
     fx_result res{};
     res.tau = q->tau;
     if (q->hp.empty) {  // some label never occurs: M is empty
@@ -434,11 +487,12 @@ fx_status FxEngine::admit(int g)
     while (!pending_.empty() && !free_slots_[g].empty()) {
         FxQuery &q = *pending_.front();
         const size_t bytes = region_size(q, nv);
-        fx_status st = W_->pool.take(bytes, &q.region);
-        if (st != FX_OK) {
+        if (!W_->pool.take(bytes, &q.region)) {
             // wait until running queries free their regions
             if (!active_[0].empty() || !active_[1].empty() || ninit > 0) break;
-            q.req->status = st;                       // it cannot fit even alone
+            // it cannot fit even alone
+            q.req->status = fx_fail(FX_ENOMEM, "query region of %zu bytes does not fit in the %zu-byte budget",
+                                    bytes, W_->pool.budget);
             FxRequest *r = q.req;
             pending_.pop_front();
             done(r);
@@ -489,7 +543,7 @@ fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
     q.cap = new_cap;
     const size_t bytes = region_size(q, nv);
     void *region = nullptr;
-    if (W_->pool.take(bytes, &region, true) != FX_OK) {
+    if (!W_->pool.take(bytes, &region)) {
         q.cap = old.cap;
         return FX_OK;
     }
@@ -504,7 +558,7 @@ fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
     FX_TRY(cp(q.lev[0].len, old.lev[0].len, 4));
     FX_TRY(cp(q.lev[0].anc, old.lev[0].anc, 1));
     FX_TRY(cp(q.lev[0].off, old.lev[0].off, 16));
-    const int deep = deepest_open_level(q);
+    const int deep = q.deep;
     for (int l = 1; l <= deep; l++) {
         const size_t np = (size_t)q.nparts[l];
         if (np == 0) continue;
@@ -593,12 +647,13 @@ fx_status FxEngine::launch(int g)
     uint32_t nblocks = 0;
     int any_inner = 0, any_greedy = 0;
     const size_t A = act.size();
-    uint64_t n_open = 0;  // over both lanes: a query gets a step of its lane every other step
+    uint64_t mine = 0;  // open queries of this lane; the other lane's count is from its last launch
     for (auto &qp : act) {
         qp->seg_l = -1;
-        n_open += deepest_open_level(*qp) >= 0;
+        mine += qp->deep >= 0;
     }
-    for (auto &qp : active_[g ^ 1]) n_open += deepest_open_level(*qp) >= 0;
+    nopen_[g] = mine;
+    const uint64_t n_open = mine + nopen_[g ^ 1];  // a query gets a step of its lane every other step
     // a query's fair share of the step; a slice may take more candidates
     // than its level holds rows when few of them pass (the row cap bounds
     // what is written, see k_scatter)
@@ -614,7 +669,7 @@ fx_status FxEngine::launch(int g)
         if (q.phase == PH_SUPPORT && (q.probed_support == 0 || sums_prev[q.slot].ufiltered * 64 > q.probed_support))
             continue;
         if (q.steps < kPromoteAfter || q.cap >= kPromoteCap || share < 4 * (uint64_t)q.cap) continue;
-        if (deepest_open_level(q) < 0) continue;
+        if (q.deep < 0) continue;
         uint64_t left = 0;  // largest candidate range still open: no slice needs more rows
         for (int l = 0; l < q.n; l++) left = std::max<uint64_t>(left, q.T[l] - q.cur[l]);
         int64_t nc = q.cap;
@@ -623,7 +678,7 @@ fx_status FxEngine::launch(int g)
     }
     for (size_t k = 0; k < A && budget > 0; k++) {
         FxQuery &q = *act[(rot_[g] + k) % A];
-        const int l = deepest_open_level(q);
+        const int l = q.deep;
         if (l < 0) continue;
         const bool last = (l == q.n - 1);
         int kind, flags = 0;
@@ -773,6 +828,7 @@ fx_status FxEngine::collect(int g, double &waited)
             }
             q.listed += (int64_t)N;
         }
+        q.deep = deepest_open_level(q);
     }
     // ---- retire finished queries, move FULL queries to their counting phase
     for (size_t k = 0; k < act.size();) {
@@ -782,7 +838,7 @@ fx_status FxEngine::collect(int g, double &waited)
         if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_VERDICT && (int64_t)S.support >= q.tau_eff) fin = true;
         // (the minimum-image support needs every embedding: the cap only caps its count)
         if (q.phase == PH_COUNT && q.req->kind != FX_Q_MNI && (int64_t)S.count >= P_.count_cap) fin = true;
-        if (!fin && deepest_open_level(q) < 0) {
+        if (!fin && q.deep < 0) {
             if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_FULL) {
                 q.phase = PH_COUNT;  // level 0 is unchanged; restart the cursors
                 restart_stack(q, G_);
@@ -807,7 +863,7 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
     EngineParams p = c->params;
     p.max_active = std::max<int32_t>(1, std::min<int32_t>(max_active, (int32_t)std::max<size_t>(reqs.size(), 1)));
     FxEngine eng(G, &c->work, c->stream, p, &c->stats);
-    for (auto &r : reqs) eng.add(&r);
+    eng.add_all(reqs.data(), reqs.size());
     while (!eng.idle()) FX_TRY(eng.step());
     return FX_OK;
 }

@@ -17,6 +17,7 @@
 
 #include "../../include/flexis.h"
 #include "fx_internal.h"
+#include "fx_pool.h"
 
 fx_status fx_fail(fx_status code, const char *fmt, ...);
 
@@ -60,26 +61,6 @@ struct HostBuf {
     T *as() const { return (T *)p; }
 };
 
-// Device memory for the per-query stacks: chunks allocated once (up to a byte
-// budget) and carved first-fit, with freed ranges merged back.  Admission
-// control of the engine is "can this query's region be carved".  Nothing is
-// returned to the runtime before the context is destroyed, so steady-state
-// admission makes no allocation call (hipFree would synchronise the device).
-struct RegionPool {
-    struct Chunk {
-        char *base = nullptr;
-        size_t size = 0;
-        std::map<size_t, size_t> free_;  // offset -> length, non-adjacent ranges
-    };
-    std::vector<Chunk> chunks;
-    size_t in_use = 0, held = 0, budget = 0;
-    static constexpr size_t kChunk = (size_t)4 << 30;
-    ~RegionPool();
-    // FX_ENOMEM when nothing fits within the budget (quiet: no error message is recorded)
-    fx_status take(size_t bytes, void **out, bool quiet = false);
-    void give(void *p, size_t bytes);
-};
-
 // Tunables of an engine.
 struct EngineParams {
     int64_t slice_rows = 1 << 17;          // level capacity of one query's stack
@@ -106,6 +87,7 @@ struct EngineLane {
 // per-step scratch (flags, counts, offsets) is shared by the lanes: their
 // steps run one after the other on the engine's stream.
 struct EngineWork {
+    EngineWork();  // the pool allocates its chunks with hipMalloc
     RegionPool pool;
     DevBuf flag, bcnt, boff, lsum, loff, tmap, sums_d;
     EngineLane lane[2];
@@ -182,11 +164,16 @@ public:
     // (invalid, a label absent from the graph, exact upper-bound reject) are
     // finished at once.
     void add(FxRequest *r);
+    // add() for a whole batch; the plans of a large batch are built on
+    // several host threads, then the requests are queued in order.
+    void add_all(FxRequest *reqs, size_t count);
     bool idle() const;
     fx_status step();
     std::function<void(FxRequest *)> on_done;
 
 private:
+    std::unique_ptr<FxQuery> prepare(FxRequest *r) const;  // plan and tau; touches no engine state
+    void enqueue(std::unique_ptr<FxQuery> q);
     fx_status admit(int g);
     fx_status promote(FxQuery &q, int64_t new_cap);
     fx_status finish(FxQuery &q, const FxSummary *sums);
@@ -204,6 +191,7 @@ private:
     size_t rot_[2] = {0, 0};
     bool in_flight_[2] = {false, false};
     int any_greedy_[2] = {0, 0};
+    uint64_t nopen_[2] = {0, 0};  // queries with candidates left, per lane, at its last launch
     int lane_ = 0;  // the lane the next step() serves
     std::chrono::steady_clock::time_point t0_;
     bool buffers_ready_ = false;

@@ -38,16 +38,18 @@
 #define FX_GREEDY_H 4096     // LDS hash slots of the per-query greedy
 #define FX_GREEDY_VN 2048    // embedding-vertices per greedy chunk (<= H / 2)
 
+// Dense labels fit 16 bits (more than 65535 distinct labels is FX_ELIMIT).
 struct FxPlan {
     int32_t n;
-    uint32_t vl[FX_MAXN];                 // dense vertex label of pattern vertex i
-    int32_t nback[FX_MAXN];               // number of earlier neighbours of i
-    int32_t back[FX_MAXN][FX_MAXN];       // earlier neighbours of i
-    uint32_t bel[FX_MAXN][FX_MAXN];       // dense edge label of (back[i][k], i)
-    int32_t nnlf[FX_MAXN];                // neighbour-label filter entries for i
-    uint64_t nlf_key[FX_MAXN][FX_NLF];    // (label << 48 | elabel << 32) of later neighbours
-    int32_t nlf_need[FX_MAXN][FX_NLF];    // how many such neighbours i needs
+    uint16_t vl[FX_MAXN];                 // dense vertex label of pattern vertex i
+    int8_t nback[FX_MAXN];                // number of earlier neighbours of i
+    int8_t nnlf[FX_MAXN];                 // neighbour-label filter entries for i
+    int8_t back[FX_MAXN][FX_MAXN];        // earlier neighbours of i
+    uint16_t bel[FX_MAXN][FX_MAXN];       // dense edge label of (back[i][k], i)
+    uint32_t nlf_key[FX_MAXN][FX_NLF];    // (label << 16 | elabel) of later neighbours
+    uint8_t nlf_need[FX_MAXN][FX_NLF];    // how many such neighbours i needs
 };
+static_assert(sizeof(FxPlan) % 4 == 0, "the plan is copied in 32-bit words");
 
 struct FxGraphDev {
     int64_t nv;

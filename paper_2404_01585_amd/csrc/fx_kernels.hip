@@ -202,7 +202,8 @@ __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__re
         for (int k = 0; k < nf; k++) {
             int64_t lo;
             int32_t len;
-            run_of(g, x.c, plan->nlf_key[i][k], lo, len, bytes);
+            const uint32_t nk = plan->nlf_key[i][k];
+            run_of(g, x.c, run_key(nk >> 16, nk & 0xffffu), lo, len, bytes);
             if (len < plan->nlf_need[i][k]) return false;
         }
     }
@@ -634,9 +635,11 @@ __global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ seg
 // tested every embedding against the same U.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ uint32_t lds_hash(int32_t v)
+// Slot of data vertex v in a table of 2^bits slots (Fibonacci hashing: the
+// top bits of the product with 2^64 / golden ratio).
+__device__ __forceinline__ uint32_t lds_hash(int32_t v, uint32_t bits)
 {
-    return (uint32_t)(((uint64_t)(uint32_t)v * 0x9e3779b97f4a7c15ULL) >> 52);  // top 12 bits: FX_GREEDY_H = 4096
+    return (uint32_t)(((uint64_t)(uint32_t)v * 0x9e3779b97f4a7c15ULL) >> (64 - bits));
 }
 
 __device__ __forceinline__ bool used_coherent(const uint32_t *U, int32_t v)
@@ -693,7 +696,7 @@ __device__ void greedy_tail(uint8_t *state, const uint16_t *slot, uint32_t *hval
 
 __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs)
 {
-    static_assert(FX_GREEDY_H == 4096, "lds_hash takes the top 12 bits");
+    static_assert(FX_GREEDY_H == 4096 && 2 * FX_GREEDY_VN <= FX_GREEDY_H, "a chunk's vertices fill at most half");
     // 32-bit slot keys: a chunk's ranks and rounds (at most one per embedding)
     // stay below 2^16, and no key is 0 (the taken mark)
     static_assert(FX_GREEDY_VN < 0xffff, "rank and round must fit 16 bits");
@@ -713,7 +716,12 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
     uint32_t rounds_total = 0;
     for (uint64_t c0 = 0; c0 < N; c0 += B) {
         const uint32_t nb = (uint32_t)((N - c0) < B ? (N - c0) : B);
-        for (uint32_t k = threadIdx.x; k < FX_GREEDY_H; k += FX_BS) {
+        // a table of at least twice the chunk's vertices (at least 64 slots):
+        // small chunks clear and probe only that part of the LDS table
+        uint32_t hbits = 6;
+        while ((1u << hbits) < 2 * nb * (uint32_t)n) hbits++;
+        const uint32_t hmask = (1u << hbits) - 1;
+        for (uint32_t k = threadIdx.x; k <= hmask; k += FX_BS) {
             hkey[k] = -1;
             hval[k] = ~0u;
         }
@@ -730,11 +738,11 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
             if (!out) {
                 for (int j = 0; j < n; j++) {
                     const int32_t v = row[j];
-                    uint32_t h = lds_hash(v);
+                    uint32_t h = lds_hash(v, hbits);
                     while (true) {  // linear probing; at most H/2 keys per chunk
                         const int32_t prev = atomicCAS(&hkey[h], -1, v);
                         if (prev == -1 || prev == v) break;
-                        h = (h + 1) & (FX_GREEDY_H - 1);
+                        h = (h + 1) & hmask;
                     }
                     slot[e * n + j] = (uint16_t)h;
                 }

@@ -1,0 +1,24 @@
+"""Host logic of the library tested on the CPU: the stack-memory pool
+(first-fit chunks with merging, an exact-size cache of freed regions),
+built with the host compiler under AddressSanitizer and run with a
+malloc-backed allocator."""
+
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="no host C++ compiler")
+def test_region_pool(tmp_path):
+    exe = str(tmp_path / "pool_test")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                           "-I", os.path.join(ROOT, "paper_2404_01585_amd", "csrc"),
+                           os.path.join(HERE, "host_pool_test.cpp"), "-o", exe])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "ok"
