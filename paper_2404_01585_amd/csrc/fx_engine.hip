@@ -201,6 +201,7 @@ struct FxQuery {
     uint64_t probed_support = 0;           // candidates probed in the support phase
     int32_t steps = 0;
     int deep = -1;                         // deepest level with candidates left (-1: none)
+    int lane = 0;
     int64_t listed = 0;
     // the segment of the current step (-1: none)
     int seg_l = -1, seg_kind = 0;
@@ -312,6 +313,11 @@ EngineWork::~EngineWork()
         for (auto &e : L.evk)
             if (e) (void)hipEventDestroy(e);
     }
+    if (start_ev) (void)hipEventDestroy(start_ev);
+    if (own_stream) {
+        (void)hipStreamSynchronize(own_stream);
+        (void)hipStreamDestroy(own_stream);
+    }
 }
 
 fx_status EngineWork::init_events()
@@ -321,11 +327,13 @@ fx_status EngineWork::init_events()
         for (auto &e : L.evk)
             if (!e) FX_HIP(hipEventCreate(&e));
     }
+    if (!start_ev) FX_HIP(hipEventCreateWithFlags(&start_ev, hipEventDisableTiming));
+    if (!own_stream) FX_HIP(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
     return FX_OK;
 }
 
 FxEngine::FxEngine(fx_graph *G, EngineWork *W, hipStream_t s, const EngineParams &p, fx_stats *stats)
-    : G_(G), W_(W), s_(s), P_(p), stats_(stats), t0_(std::chrono::steady_clock::now())
+    : G_(G), W_(W), s_(s), ls_{s, s}, P_(p), stats_(stats), t0_(std::chrono::steady_clock::now())
 {
     if (P_.max_active < 1) P_.max_active = 1;
     // a segment's span is a 32-bit count
@@ -338,10 +346,15 @@ FxEngine::~FxEngine()
 {
     // after an error, queries may still be running: let their work finish
     // before their stack memory goes back to the pool
-    if (!active_[0].empty() || !active_[1].empty()) (void)hipStreamSynchronize(s_);
+    if (!active_[0].empty() || !active_[1].empty() || !deferred_[0].empty() || !deferred_[1].empty()) {
+        (void)hipStreamSynchronize(ls_[0]);
+        (void)hipStreamSynchronize(ls_[1]);
+    }
     for (auto &A : active_)
         for (auto &q : A)
             if (q->region) W_->pool.give(q->region, q->region_bytes);
+    for (auto &D : deferred_)
+        for (auto &r : D) W_->pool.give(r.first, r.second);
 }
 
 bool FxEngine::idle() const { return pending_.empty() && active_[0].empty() && active_[1].empty(); }
@@ -434,9 +447,10 @@ fx_status FxEngine::finish(FxQuery &q, const FxSummary *sums)
             res.support = (int64_t)S.support;
             if (r.kind == FX_Q_MNI) {
                 unsigned long long m = 0;
-                FX_HIP(fx_launch_mni(s_, q.img, ((uint64_t)G_->nv + 31) / 32, q.n, q.mni, q.mni + FX_MAXN));
-                FX_HIP(hipMemcpyAsync(&m, q.mni + FX_MAXN, 8, hipMemcpyDeviceToHost, s_));
-                FX_HIP(hipStreamSynchronize(s_));
+                hipStream_t st = ls_[q.lane];
+                FX_HIP(fx_launch_mni(st, q.img, ((uint64_t)G_->nv + 31) / 32, q.n, q.mni, q.mni + FX_MAXN));
+                FX_HIP(hipMemcpyAsync(&m, q.mni + FX_MAXN, 8, hipMemcpyDeviceToHost, st));
+                FX_HIP(hipStreamSynchronize(st));
                 res.support = (int64_t)m;
             }
             res.frequent = res.support >= q.tau_eff;
@@ -451,9 +465,10 @@ fx_status FxEngine::finish(FxQuery &q, const FxSummary *sums)
                 const int64_t k = (int64_t)S.support;
                 std::vector<int32_t> rows((size_t)k * q.n);
                 std::vector<int64_t> rank(k);
-                FX_HIP(hipMemcpyAsync(rows.data(), q.sel_rows, rows.size() * 4, hipMemcpyDeviceToHost, s_));
-                FX_HIP(hipMemcpyAsync(rank.data(), q.sel_rank, rank.size() * 8, hipMemcpyDeviceToHost, s_));
-                FX_HIP(hipStreamSynchronize(s_));
+                hipStream_t st = ls_[q.lane];
+                FX_HIP(hipMemcpyAsync(rows.data(), q.sel_rows, rows.size() * 4, hipMemcpyDeviceToHost, st));
+                FX_HIP(hipMemcpyAsync(rank.data(), q.sel_rank, rank.size() * 8, hipMemcpyDeviceToHost, st));
+                FX_HIP(hipStreamSynchronize(st));
                 std::vector<int64_t> idx(k);
                 std::iota(idx.begin(), idx.end(), 0);
                 std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return rank[a] < rank[b]; });
@@ -501,6 +516,7 @@ fx_status FxEngine::admit(int g)
         q.region_bytes = bytes;
         carve(q, nv);
         q.slot = free_slots_[g].back();
+        q.lane = g;
         free_slots_[g].pop_back();
         FxInit &I = inits[ninit++];
         I.plan = q.hp.plan;
@@ -516,8 +532,8 @@ fx_status FxEngine::admit(int g)
         pending_.pop_front();
     }
     if (ninit) {
-        FX_HIP(hipMemcpyAsync(L.inits_d.p, inits, (size_t)ninit * sizeof(FxInit), hipMemcpyHostToDevice, s_));
-        FX_HIP(fx_launch_init(s_, G_->dev, L.inits_d.as<FxInit>(), ninit));
+        FX_HIP(hipMemcpyAsync(L.inits_d.p, inits, (size_t)ninit * sizeof(FxInit), hipMemcpyHostToDevice, ls_[g]));
+        FX_HIP(fx_launch_init(ls_[g], G_->dev, L.inits_d.as<FxInit>(), ninit));
     }
     return FX_OK;
 }
@@ -551,7 +567,7 @@ fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
     q.region_bytes = bytes;
     carve(q, nv);
     auto cp = [&](void *dst, const void *src, size_t b) -> fx_status {
-        if (b) FX_HIP(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, s_));
+        if (b) FX_HIP(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, ls_[q.lane]));
         return FX_OK;
     };
     FX_TRY(cp(q.lev[0].lo, old.lev[0].lo, 8));
@@ -575,9 +591,10 @@ fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
         FX_TRY(cp(q.sel_rows, old.sel_rows, k * q.n * 4));
         FX_TRY(cp(q.sel_rank, old.sel_rank, k * 8));
     }
-    // later work on the stream is ordered after these copies, so the old
-    // region may be handed out again at once
-    W_->pool.give(old.region, old.region_bytes);
+    // the copies read the old region on this lane's stream: it goes back to
+    // the pool once the lane's next step has been waited for (the other lane
+    // runs on another stream and could reuse it too early)
+    deferred_[q.lane].push_back({old.region, old.region_bytes});
     q.last_span = (uint32_t)std::min<int64_t>(P_.last_span_init, q.cap);
     stats_->promotions++;
     return FX_OK;
@@ -603,14 +620,14 @@ fx_status FxEngine::step()
         const int32_t A = P_.max_active;
         const uint64_t tile = (uint64_t)FX_BS * P_.items;
         const uint64_t max_blocks = (P_.step_candidates + tile - 1) / tile + (uint64_t)A;
-        FX_TRY(W_->flag.ensure(max_blocks * tile));
-        FX_TRY(W_->bcnt.ensure(max_blocks * 4));
-        FX_TRY(W_->boff.ensure((max_blocks + 1) * 8));
-        FX_TRY(W_->lsum.ensure(max_blocks * 8));
-        FX_TRY(W_->loff.ensure((max_blocks + 1) * 8));
-        FX_TRY(W_->tmap.ensure(max_blocks * sizeof(FxTile)));
         FX_TRY(W_->sums_d.ensure((size_t)A * sizeof(FxSummary)));
         for (auto &L : W_->lane) {
+            FX_TRY(L.flag.ensure(max_blocks * tile));
+            FX_TRY(L.bcnt.ensure(max_blocks * 4));
+            FX_TRY(L.boff.ensure((max_blocks + 1) * 8));
+            FX_TRY(L.lsum.ensure(max_blocks * 8));
+            FX_TRY(L.loff.ensure((max_blocks + 1) * 8));
+            FX_TRY(L.tmap.ensure(max_blocks * sizeof(FxTile)));
             FX_TRY(L.stage_d.ensure(stage_bytes(A, A)));
             FX_TRY(L.stage_h.ensure(stage_bytes(A, A)));
             FX_TRY(L.inits_d.ensure((size_t)A * sizeof(FxInit)));
@@ -618,6 +635,12 @@ fx_status FxEngine::step()
             FX_TRY(L.sums_h.ensure((size_t)A * sizeof(FxSummary)));
         }
         FX_TRY(W_->init_events());
+        if (P_.lanes == 2) {
+            // lane 1 starts after whatever the caller queued on the engine's stream
+            ls_[1] = W_->own_stream;
+            FX_HIP(hipEventRecord(W_->start_ev, s_));
+            FX_HIP(hipStreamWaitEvent(ls_[1], W_->start_ev, 0));
+        }
         buffers_ready_ = true;
     }
     const int g = lane_;
@@ -746,19 +769,19 @@ fx_status FxEngine::launch(int g)
     rot_[g]++;
     if (nsegs == 0) return fx_fail(FX_EDEVICE, "engine stalled with %zu active queries", A);
     blk0[nsegs] = nblocks;
+    hipStream_t st = ls_[g];
     FX_HIP(hipMemcpyAsync(L.stage_d.p, L.stage_h.p, seg_off + (size_t)nsegs * sizeof(FxSeg), hipMemcpyHostToDevice,
-                          s_));
+                          st));
     hipEvent_t *ev = P_.timing ? L.evk : nullptr;
-    FX_HIP(fx_launch_step(s_, G_->dev, (const FxSeg *)((char *)L.stage_d.p + seg_off), L.stage_d.as<uint32_t>(),
-                          nsegs, nblocks, P_.items, W_->tmap.as<FxTile>(), W_->flag.as<uint8_t>(),
-                          W_->bcnt.as<uint32_t>(), W_->boff.as<uint64_t>(), W_->lsum.as<uint64_t>(),
-                          W_->loff.as<uint64_t>(), ev ? ev[0] : nullptr,
+    FX_HIP(fx_launch_step(st, G_->dev, (const FxSeg *)((char *)L.stage_d.p + seg_off), L.stage_d.as<uint32_t>(),
+                          nsegs, nblocks, P_.items, L.tmap.as<FxTile>(), L.flag.as<uint8_t>(), L.bcnt.as<uint32_t>(),
+                          L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>(), ev ? ev[0] : nullptr,
                           ev ? ev[1] : nullptr, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
                           ev ? ev[5] : nullptr, any_inner, any_greedy));
     int hi = 0;
     for (auto &qp : act) hi = std::max(hi, qp->slot + 1);
-    FX_HIP(hipMemcpyAsync(L.sums_h.p, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, s_));
-    FX_HIP(hipEventRecord(L.done, s_));
+    FX_HIP(hipMemcpyAsync(L.sums_h.p, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, st));
+    FX_HIP(hipEventRecord(L.done, st));
     in_flight_[g] = true;
     any_greedy_[g] = any_greedy;
     return FX_OK;
@@ -776,6 +799,8 @@ fx_status FxEngine::collect(int g, double &waited)
         waited += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
     }
     in_flight_[g] = false;
+    for (auto &r : deferred_[g]) W_->pool.give(r.first, r.second);
+    deferred_[g].clear();
     const FxSummary *sums_h = L.sums_h.as<FxSummary>();
     stats_->steps++;
     stats_->syncs++;
@@ -823,8 +848,8 @@ fx_status FxEngine::collect(int g, double &waited)
             const int64_t take = std::min<int64_t>((int64_t)N, std::max<int64_t>(0, r.list_cap - q.listed));
             if (take > 0) {
                 FX_HIP(hipMemcpyAsync(r.list_rows + q.listed * q.n, q.lev[q.n].rows, (size_t)take * q.n * 4,
-                                      hipMemcpyDeviceToHost, s_));
-                FX_HIP(hipStreamSynchronize(s_));
+                                      hipMemcpyDeviceToHost, ls_[g]));
+                FX_HIP(hipStreamSynchronize(ls_[g]));
             }
             q.listed += (int64_t)N;
         }

@@ -78,19 +78,22 @@ struct EngineParams {
 // a lane's step, and the summaries read back after it.
 struct EngineLane {
     DevBuf stage_d, inits_d;           // stage: workgroup starts, then the segment table
+    DevBuf flag, bcnt, boff, lsum, loff, tmap;  // per-step scratch of the expansion kernels
     HostBuf stage_h, inits_h, sums_h;
     hipEvent_t done = nullptr;  // recorded after the lane's summary copy
     hipEvent_t evk[6] = {};     // kernel timing
 };
 
-// Device and pinned buffers of one engine (a context's, or a server's).  The
-// per-step scratch (flags, counts, offsets) is shared by the lanes: their
-// steps run one after the other on the engine's stream.
+// Device and pinned buffers of one engine (a context's, or a server's).  Lane
+// 0 runs on the engine's stream, lane 1 on a stream of its own, so the two
+// lanes' steps overlap on the device; each lane has its own scratch.
 struct EngineWork {
     EngineWork();  // the pool allocates its chunks with hipMalloc
     RegionPool pool;
-    DevBuf flag, bcnt, boff, lsum, loff, tmap, sums_d;
+    DevBuf sums_d;
     EngineLane lane[2];
+    hipStream_t own_stream = nullptr;  // lane 1 (non-blocking, default priority)
+    hipEvent_t start_ev = nullptr;     // orders lane 1 after earlier work on the engine's stream
     ~EngineWork();
     fx_status init_events();
 };
@@ -183,6 +186,8 @@ private:
     fx_graph *G_;
     EngineWork *W_;
     hipStream_t s_;
+    hipStream_t ls_[2];                                    // each lane's stream
+    std::vector<std::pair<void *, size_t>> deferred_[2];   // regions freed once the lane's work passed them
     EngineParams P_;
     fx_stats *stats_;
     std::deque<std::unique_ptr<FxQuery>> pending_;
