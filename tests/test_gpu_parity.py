@@ -293,6 +293,30 @@ def _mining_candidates(g, sigma, lam, levels):
     return [p for lvl in r["levels"] for p in lvl]
 
 
+def test_merge_generator_mining(ctx, er1k):
+    """Algorithm 1 with the merge generator (levels by vertex count, up to 4
+    vertices) gives the same candidates and verdicts with the device's
+    verdicts as with the oracle's."""
+    from paper_2404_01585_amd import generate
+
+    g = er1k
+
+    def ev_oracle(ps, s, l):
+        return [O.query(g, p, s, l, mode=O.VERDICT) for p in ps]
+
+    want = generate.mine_by_vertices(g, 20, 1.0, 4, ev_oracle, O.tau)
+    with ctx.load_graph(g) as dg:
+        def ev_dev(ps, s, l):
+            return dg.support_batch(ps, [s] * len(ps), [l] * len(ps), fx.MODE_VERDICT)
+
+        got = generate.mine_by_vertices(g, 20, 1.0, 4, ev_dev, fx.tau)
+    assert len(got["levels"]) == len(want["levels"])
+    for lv, (a, b) in enumerate(zip(got["levels"], want["levels"])):
+        _say("merge mining level", lv, len(a))
+        assert [(p.vlabel, p.edges, p.elabel) for p in a] == [(p.vlabel, p.edges, p.elabel) for p in b]
+        assert [r["frequent"] for r in got["results"][lv]] == [r["frequent"] for r in want["results"][lv]]
+
+
 def test_er1k_mining_batch(ctx, er1k):
     """Every candidate of the first three mining levels on the 1K-vertex graph,
     as one batch, FULL and VERDICT, against the oracle pattern by pattern."""
