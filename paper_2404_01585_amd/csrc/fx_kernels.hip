@@ -428,31 +428,43 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
 }
 
 // Exclusive scan of per-workgroup values over the whole launch (one
-// workgroup of 1024 threads); boff[nblocks] receives the total.
+// workgroup of 16 waves); boff[nblocks] receives the total.  Wave w owns a
+// contiguous range of the values: it sums the range with coalesced loads, the
+// 16 totals give each wave its starting offset, then the wave scans its range
+// 64 values at a time (a shuffle scan per chunk plus a running carry).
 template <class T>
 __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt, uint32_t nblocks, uint64_t *boff)
 {
-    __shared__ uint64_t part[1024];
-    const uint32_t per = (nblocks + 1023) / 1024;
-    const uint32_t beg = threadIdx.x * per;
-    uint64_t s = 0;
-    for (uint32_t k = 0; k < per; k++)
-        if (beg + k < nblocks) s += bcnt[beg + k];
-    part[threadIdx.x] = s;
+    constexpr uint32_t W = 1024 / 64;
+    __shared__ unsigned long long wtot[W];
+    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
+    const uint32_t per = (nblocks + W * 64 - 1) / (W * 64) * 64;  // a multiple of 64
+    const uint32_t beg = wave * per;
+    const uint32_t end = beg < nblocks ? min(beg + per, nblocks) : beg;
+    unsigned long long s = 0;
+    for (uint32_t k = beg + lane; k < end; k += 64) s += (unsigned long long)bcnt[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) wtot[wave] = s;
     __syncthreads();
-    for (uint32_t o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan
-        uint64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    unsigned long long carry = 0, total = 0;
+    for (uint32_t w = 0; w < W; w++) {
+        carry += w < wave ? wtot[w] : 0ULL;
+        total += wtot[w];
     }
-    uint64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-    for (uint32_t k = 0; k < per; k++)
-        if (beg + k < nblocks) {
-            boff[beg + k] = run;
-            run += bcnt[beg + k];
+    for (uint32_t k0 = beg; k0 < end; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        const unsigned long long v = k < end ? (unsigned long long)bcnt[k] : 0ULL;
+        unsigned long long inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long u = __shfl_up(inc, o);
+            if (lane >= (uint32_t)o) inc += u;
         }
-    if (threadIdx.x == 1023) boff[nblocks] = part[1023];
+        if (k < end) boff[k] = carry + inc - v;
+        carry += __shfl(inc, 63);
+    }
+    if (threadIdx.x == 0) boff[nblocks] = total;
 }
 
 // Ordered write of the passing candidates of each segment into its level l+1
