@@ -67,7 +67,7 @@ struct EngineParams {
     int64_t count_cap = (int64_t)1 << 62;
     uint64_t step_candidates = 1ull << 25;  // flattened candidates per step, all queries together
     int32_t max_active = 4096;             // queries in flight
-    uint32_t last_span_init = 4096;        // first last-vertex slice of the support phase
+    uint32_t last_span_init = 4096;        // complete embeddings per greedy slice (support phase)
     int32_t items = 4;                     // candidates per thread in the expansion kernels (2, 4, 8)
     int32_t lanes = 2;                     // pipeline lanes (1 or 2)
     bool timing = false;
