@@ -500,6 +500,12 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     }
     if (S.kind != FX_SEG_INNER && threadIdx.x == 0) lsum[blockIdx.x] = 0;
     if (S.kind == FX_SEG_COUNT) return;  // nothing is written for a counting segment
+    // a tile without passing candidates, or whose passes all fall past the row
+    // cap, writes nothing (its run-length total is 0); uniform per workgroup
+    if (boff[blockIdx.x + 1] == boff[blockIdx.x] || boff[blockIdx.x] - seg_base >= cap) {
+        if (threadIdx.x == 0) lsum[blockIdx.x] = 0;
+        return;
+    }
     const uint32_t tile0 = (blockIdx.x - S.blk0) * TILE;
     const uint32_t wave = threadIdx.x >> 6;
     uint64_t bal[ITEMS];
