@@ -442,6 +442,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt
     const uint32_t beg = wave * per;
     const uint32_t end = beg < nblocks ? min(beg + per, nblocks) : beg;
     unsigned long long s = 0;
+#pragma unroll 8
     for (uint32_t k = beg + lane; k < end; k += 64) s += (unsigned long long)bcnt[k];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
@@ -452,6 +453,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt
         carry += w < wave ? wtot[w] : 0ULL;
         total += wtot[w];
     }
+#pragma unroll 4
     for (uint32_t k0 = beg; k0 < end; k0 += 64) {
         const uint32_t k = k0 + lane;
         const unsigned long long v = k < end ? (unsigned long long)bcnt[k] : 0ULL;
