@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "fx_host.h"
+#include "fx_workers.h"
 
 namespace {
 thread_local std::string g_last_error;
@@ -25,6 +26,23 @@ fx_status fx_fail(fx_status code, const char *fmt, ...)
     va_end(ap);
     g_last_error = buf;
     return code;
+}
+
+// ---------------------------------------------------------------------------
+// Host worker threads
+// ---------------------------------------------------------------------------
+
+void fx_parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &fn)
+{
+    if (n <= 0) return;
+    grain = std::max<int64_t>(grain, 1);
+    if (n <= grain) {
+        fn(0, n);
+        return;
+    }
+    // never destroyed: the parked workers simply end with the process
+    static HostWorkers *w = new HostWorkers();
+    w->run(n, grain, fn);
 }
 
 // ---------------------------------------------------------------------------
@@ -203,31 +221,11 @@ extern "C" fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_patter
     if (!g || npat < 0 || (npat > 0 && (!pats || !sigma || !lambda || !out))) return fx_fail(FX_EINVAL, "bad batch");
     if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI)
         return fx_fail(FX_EINVAL, "unknown mode %d", mode);
-    {
-        // validate everything before any device work; large batches on several
-        // threads, the first bad pattern then re-checked here for its message
-        const int32_t nt = npat >= 4096 ? (int32_t)std::max(1u, std::min(16u, std::thread::hardware_concurrency())) : 1;
-        std::vector<int32_t> first_bad(nt, npat);
-        auto check = [&](int32_t t) {
-            for (int32_t i = t; i < npat; i += nt) {
-                const bool ok = sigma[i] >= 1 && lambda[i] >= 0.0 && lambda[i] <= 1.0 && fx_check_pattern(&pats[i]) == FX_OK;
-                if (!ok) {
-                    first_bad[t] = i;
-                    return;
-                }
-            }
-        };
-        std::vector<std::thread> th;
-        for (int32_t t = 1; t < nt; t++) th.emplace_back(check, t);
-        check(0);
-        for (auto &x : th) x.join();
-        const int32_t i = *std::min_element(first_bad.begin(), first_bad.end());
-        if (i < npat) {
-            if (sigma[i] < 1) return fx_fail(FX_EINVAL, "pattern %d: sigma must be >= 1", i);
-            if (!(lambda[i] >= 0.0 && lambda[i] <= 1.0))
-                return fx_fail(FX_EINVAL, "pattern %d: lambda outside [0, 1]", i);
-            FX_TRY(fx_check_pattern(&pats[i]));
-        }
+    // sigma and lambda here; the patterns are checked when their plans are
+    // built, for the whole batch before any device work
+    for (int32_t i = 0; i < npat; i++) {
+        if (sigma[i] < 1) return fx_fail(FX_EINVAL, "pattern %d: sigma must be >= 1", i);
+        if (!(lambda[i] >= 0.0 && lambda[i] <= 1.0)) return fx_fail(FX_EINVAL, "pattern %d: lambda outside [0, 1]", i);
     }
     FX_HIP(hipSetDevice(g->ctx->device));
     std::vector<FxRequest> reqs(npat);

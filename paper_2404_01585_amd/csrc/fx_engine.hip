@@ -382,19 +382,21 @@ std::unique_ptr<FxQuery> FxEngine::prepare(FxRequest *r) const
 
 void FxEngine::add(FxRequest *r) { enqueue(prepare(r)); }
 
-void FxEngine::add_all(FxRequest *reqs, size_t count)
+fx_status FxEngine::add_all(FxRequest *reqs, size_t count)
 {
     std::vector<std::unique_ptr<FxQuery>> qs(count);
-    const size_t hw = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
-    const size_t nt = count >= 2048 ? hw : 1;  // plans are cheap: threads only pay for big batches
-    std::vector<std::thread> th;
-    for (size_t t = 1; t < nt; t++)
-        th.emplace_back([&, t] {
-            for (size_t i = t; i < count; i += nt) qs[i] = prepare(&reqs[i]);
-        });
-    for (size_t i = 0; i < count; i += nt) qs[i] = prepare(&reqs[i]);
-    for (auto &x : th) x.join();
+    fx_parallel_for((int64_t)count, 256, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; i++) qs[i] = prepare(&reqs[i]);
+    });
+    for (size_t i = 0; i < count; i++)
+        if (reqs[i].status != FX_OK) {
+            // again on this thread, for the error message
+            HostPlan hp;
+            const fx_status st = fx_build_plan(G_, reqs[i].pattern, hp);
+            return st != FX_OK ? st : reqs[i].status;
+        }
     for (auto &q : qs) enqueue(std::move(q));
+    return FX_OK;
 }
 
 void FxEngine::enqueue(std::unique_ptr<FxQuery> q)
@@ -668,7 +670,7 @@ fx_status FxEngine::launch(int g)
     int nsegs = 0;
     uint64_t budget = P_.step_candidates;
     uint32_t nblocks = 0;
-    int any_inner = 0, any_greedy = 0;
+    int any_inner = 0, any_greedy = 0, maxn = 1;
     const size_t A = act.size();
     uint64_t mine = 0;  // open queries of this lane; the other lane's count is from its last launch
     for (auto &qp : act) {
@@ -764,6 +766,7 @@ fx_status FxEngine::launch(int g)
         q.seg_span = (uint32_t)span;
         any_inner |= kind == FX_SEG_INNER;
         any_greedy |= kind == FX_SEG_GREEDY;
+        maxn = std::max(maxn, q.n);
         nsegs++;
     }
     rot_[g]++;
@@ -774,7 +777,7 @@ fx_status FxEngine::launch(int g)
                           st));
     hipEvent_t *ev = P_.timing ? L.evk : nullptr;
     FX_HIP(fx_launch_step(st, G_->dev, (const FxSeg *)((char *)L.stage_d.p + seg_off), L.stage_d.as<uint32_t>(),
-                          nsegs, nblocks, P_.items, L.tmap.as<FxTile>(), L.flag.as<uint8_t>(), L.bcnt.as<uint32_t>(),
+                          nsegs, nblocks, P_.items, maxn, L.tmap.as<FxTile>(), L.flag.as<uint8_t>(), L.bcnt.as<uint32_t>(),
                           L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>(), ev ? ev[0] : nullptr,
                           ev ? ev[1] : nullptr, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
                           ev ? ev[5] : nullptr, any_inner, any_greedy));
@@ -888,7 +891,7 @@ fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_a
     EngineParams p = c->params;
     p.max_active = std::max<int32_t>(1, std::min<int32_t>(max_active, (int32_t)std::max<size_t>(reqs.size(), 1)));
     FxEngine eng(G, &c->work, c->stream, p, &c->stats);
-    eng.add_all(reqs.data(), reqs.size());
+    FX_TRY(eng.add_all(reqs.data(), reqs.size()));
     while (!eng.idle()) FX_TRY(eng.step());
     return FX_OK;
 }

@@ -10,22 +10,15 @@
 
 namespace {
 
-int64_t parallel_for_chunks(int64_t n, const std::function<void(int64_t, int64_t)> &fn)
+// Per-vertex loops of the graph checks and index build: inline for small
+// graphs, else in blocks on the library's worker threads.
+void parallel_for_chunks(int64_t n, const std::function<void(int64_t, int64_t)> &fn)
 {
-    unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (n < 200000 || hw == 1) {
+    if (n < 200000) {
         fn(0, n);
-        return 1;
+        return;
     }
-    std::vector<std::thread> th;
-    int64_t per = (n + hw - 1) / hw;
-    for (unsigned t = 0; t < hw; t++) {
-        int64_t a = t * per, b = std::min(n, a + per);
-        if (a >= b) break;
-        th.emplace_back(fn, a, b);
-    }
-    for (auto &x : th) x.join();
-    return (int64_t)th.size();
+    fx_parallel_for(n, std::max<int64_t>(n / 256, 4096), fn);
 }
 
 }  // namespace

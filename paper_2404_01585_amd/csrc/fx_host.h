@@ -21,6 +21,13 @@
 
 fx_status fx_fail(fx_status code, const char *fmt, ...);
 
+// Runs fn(a, b) over the blocks [a, b) of `grain` indices of [0, n) on the
+// calling thread and the library's worker threads (started on first use, at
+// most 15, parked until the process ends).  Blocks are handed out through an
+// atomic counter, so their order of execution is unspecified.  Callers from
+// several threads take turns.  n <= grain runs inline.
+void fx_parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &fn);
+
 #define FX_HIP(call)                                                                                     \
     do {                                                                                                 \
         hipError_t e_ = (call);                                                                          \
@@ -169,7 +176,10 @@ public:
     void add(FxRequest *r);
     // add() for a whole batch; the plans of a large batch are built on
     // several host threads, then the requests are queued in order.
-    void add_all(FxRequest *reqs, size_t count);
+    // Plans every request (in parallel), then queues them all; if a pattern
+    // is invalid, returns the error of the first such request and queues
+    // nothing.
+    fx_status add_all(FxRequest *reqs, size_t count);
     bool idle() const;
     fx_status step();
     std::function<void(FxRequest *)> on_done;

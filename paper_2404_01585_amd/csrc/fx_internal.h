@@ -161,8 +161,11 @@ hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int
 // One step: probe, scan, scatter (+ run-length prefix fix-up), greedy.  items
 // (2, 4 or 8) is the number of candidates per thread; segment j owns
 // ceil(span_j / (FX_BS * items)) consecutive workgroups starting at blk0s[j].
+// maxn is the largest pattern size among the segments (it picks the register
+// width of a partial row).
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                          int32_t nsegs, uint32_t nblocks, int32_t items, FxTile *tmap, uint8_t *flag, uint32_t *bcnt,
+                          int32_t nsegs, uint32_t nblocks, int32_t items, int32_t maxn, FxTile *tmap, uint8_t *flag,
+                          uint32_t *bcnt,
                           uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
                           hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
                           hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy);

@@ -35,23 +35,67 @@ __device__ __forceinline__ uint64_t run_key(uint32_t vl, uint32_t el)
     return ((uint64_t)vl << 48) | ((uint64_t)el << 32);
 }
 
+// Binary search narrows a range down to at most SCAN entries; those are
+// then read with independent loads (one memory round trip instead of a chain
+// of dependent ones: most label runs are a few entries long).  The loads in
+// flight hold registers, so kernels with a wider partial row (W) scan fewer:
+// SCAN = 32 / W.
+template <int W>
+constexpr int scan_width() { return 32 / W; }
+
 // First index in adj[lo, hi) whose value is >= key.  `bytes` grows by the 8
 // bytes of every entry the search reads (its algorithmic traffic).
+template <int SCAN>
 __device__ __forceinline__ int64_t lower_bound64(const uint64_t *__restrict__ a, int64_t lo, int64_t hi, uint64_t key,
                                                  uint32_t &bytes)
 {
-    while (lo < hi) {
+    while (hi - lo > SCAN) {
         int64_t mid = lo + ((hi - lo) >> 1);
         bytes += 8;
         if (a[mid] < key) lo = mid + 1;
         else hi = mid;
     }
-    return lo;
+    const int64_t n = hi - lo;
+    uint64_t v[SCAN];
+#pragma unroll
+    for (int j = 0; j < SCAN; j++)
+        if (j < n) v[j] = a[lo + j];
+    int64_t below = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN; j++) below += (j < n && v[j] < key) ? 1 : 0;
+    bytes += 8u * (uint32_t)n;
+    return lo + below;
+}
+
+// Does the sorted range a[lo, hi) hold key?
+template <int SCAN>
+__device__ __forceinline__ bool contains64(const uint64_t *__restrict__ a, int64_t lo, int64_t hi, uint64_t key,
+                                           uint32_t &bytes)
+{
+    while (hi - lo > SCAN) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        const uint64_t m = a[mid];
+        bytes += 8;
+        if (m == key) return true;
+        if (m < key) lo = mid + 1;
+        else hi = mid;
+    }
+    const int64_t n = hi - lo;
+    uint64_t v[SCAN];
+#pragma unroll
+    for (int j = 0; j < SCAN; j++)
+        if (j < n) v[j] = a[lo + j];
+    bool found = false;
+#pragma unroll
+    for (int j = 0; j < SCAN; j++) found = found | (j < n && v[j] == key);
+    bytes += 8u * (uint32_t)n;
+    return found;
 }
 
 // The run of neighbours of u with the given (label, elabel) key: two offsets
 // of the label-run index when the graph has one, else two binary searches
 // over u's row.
+template <int SCAN>
 __device__ __forceinline__ void run_of(const FxGraphDev &g, int32_t u, uint64_t key, int64_t &lo, int32_t &len,
                                        uint32_t &bytes)
 {
@@ -66,28 +110,28 @@ __device__ __forceinline__ void run_of(const FxGraphDev &g, int32_t u, uint64_t 
     }
     int64_t a = g.rowp[u], b = g.rowp[u + 1];
     bytes += 16;
-    int64_t s = lower_bound64(g.adj, a, b, key, bytes);
-    int64_t e = lower_bound64(g.adj, s, b, key + (1ULL << 32), bytes);
+    int64_t s = lower_bound64<SCAN>(g.adj, a, b, key, bytes);
+    int64_t e = lower_bound64<SCAN>(g.adj, s, b, key + (1ULL << 32), bytes);
     lo = s;
     len = (int32_t)(e - s);
 }
 
 // Does the row of u contain the packed entry (label, elabel, id)?  A binary
 // search inside the entry's (label, elabel) run.
+template <int SCAN>
 __device__ __forceinline__ bool has_entry(const FxGraphDev &g, int32_t u, uint64_t entry, uint32_t &bytes)
 {
     int64_t lo, hi;
     if (g.runoff) {
         int32_t len;
-        run_of(g, u, entry & 0xffffffff00000000ULL, lo, len, bytes);
+        run_of<SCAN>(g, u, entry & 0xffffffff00000000ULL, lo, len, bytes);
         hi = lo + len;
     } else {
         lo = g.rowp[u];
         hi = g.rowp[u + 1];
         bytes += 16;
     }
-    int64_t k = lower_bound64(g.adj, lo, hi, entry, bytes);
-    return k < hi && g.adj[k] == entry;
+    return contains64<SCAN>(g.adj, lo, hi, entry, bytes);
 }
 
 __device__ __forceinline__ bool is_used(const uint32_t *__restrict__ U, int32_t v)
@@ -107,8 +151,12 @@ __device__ __forceinline__ int64_t find_part(const int64_t *__restrict__ off, in
     return lo;
 }
 
+// W: register width of the partial row, at least the largest pattern size of
+// the launch (4, 8 or FX_MAXN); a narrower row keeps fewer registers live and
+// unrolls fewer compares.
+template <int W>
 struct Cand {
-    int32_t v[FX_MAXN];  // the partial row (first l entries)
+    int32_t v[W];        // the partial row (first l entries)
     int32_t c;           // candidate for pattern vertex l
     int32_t anc;         // pattern vertex whose run produced c (-1: bucket)
     bool first;          // first candidate of its partial
@@ -158,13 +206,14 @@ __device__ __forceinline__ int64_t tile_part(const TileMap &m, const int64_t *__
 }
 
 // Loads partial p and its candidate at flattened index t.
+template <int W>
 __device__ __forceinline__ void load_cand(const FxGraphDev &g, const FxLevelDev &in, int32_t l, int64_t p,
-                                          uint64_t t, Cand &x)
+                                          uint64_t t, Cand<W> &x)
 {
     int64_t j = (int64_t)(t - (uint64_t)in.off[p]);
     const int32_t *row = in.rows + p * l;
 #pragma unroll
-    for (int k = 0; k < FX_MAXN; k++)
+    for (int k = 0; k < W; k++)
         x.v[k] = (k < l) ? row[k] : -1;
     x.anc = in.anc[p];
     x.first = (j == 0);
@@ -172,21 +221,23 @@ __device__ __forceinline__ void load_cand(const FxGraphDev &g, const FxLevelDev 
     x.c = x.anc >= 0 ? (int32_t)(uint32_t)(g.adj[base + j] & 0xffffffffULL) : g.bucket[base + j];
 }
 
-__device__ __forceinline__ int32_t pick(const int32_t (&v)[FX_MAXN], int32_t b)
+template <int W>
+__device__ __forceinline__ int32_t pick(const int32_t (&v)[W], int32_t b)
 {
     int32_t r = -1;
 #pragma unroll
-    for (int k = 0; k < FX_MAXN; k++)
+    for (int k = 0; k < W; k++)
         r = (k == b) ? v[k] : r;
     return r;
 }
 
 // Candidate test of Section 2.1.4 for pattern vertex i = l.
+template <int W>
 __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__restrict__ plan, int32_t n, int32_t l,
-                                         const Cand &x, uint32_t &bytes)
+                                         const Cand<W> &x, uint32_t &bytes)
 {
 #pragma unroll
-    for (int k = 0; k < FX_MAXN; k++)
+    for (int k = 0; k < W; k++)
         if (k < l && x.v[k] == x.c) return false;  // injective
     const int32_t i = l;
     const uint32_t vl = plan->vl[i];
@@ -195,7 +246,7 @@ __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__re
         int32_t b = plan->back[i][kk];
         if (b == x.anc) continue;  // the run it came from already matches
         uint64_t entry = run_key(vl, plan->bel[i][kk]) | (uint32_t)x.c;
-        if (!has_entry(g, pick(x.v, b), entry, bytes)) return false;
+        if (!has_entry<scan_width<W>()>(g, pick(x.v, b), entry, bytes)) return false;
     }
     if (i < n - 1) {  // neighbour-label filter for the later neighbours of i
         const int32_t nf = plan->nnlf[i];
@@ -203,18 +254,19 @@ __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__re
             int64_t lo;
             int32_t len;
             const uint32_t nk = plan->nlf_key[i][k];
-            run_of(g, x.c, run_key(nk >> 16, nk & 0xffffu), lo, len, bytes);
+            run_of<scan_width<W>()>(g, x.c, run_key(nk >> 16, nk & 0xffffu), lo, len, bytes);
             if (len < plan->nlf_need[i][k]) return false;
         }
     }
     return true;
 }
 
-__device__ __forceinline__ bool touches_used(const uint32_t *__restrict__ U, const Cand &x, int32_t l)
+template <int W>
+__device__ __forceinline__ bool touches_used(const uint32_t *__restrict__ U, const Cand<W> &x, int32_t l)
 {
     if (is_used(U, x.c)) return true;
 #pragma unroll
-    for (int k = 0; k < FX_MAXN; k++)
+    for (int k = 0; k < W; k++)
         if (k < l && is_used(U, x.v[k])) return true;
     return false;
 }
@@ -258,11 +310,12 @@ __global__ __launch_bounds__(FX_BS) void k_tile_map(const FxSeg *__restrict__ se
     tmap[b] = t;
 }
 
-__device__ __forceinline__ void tuple_hash(const Cand &x, int32_t l, uint64_t &h1, uint64_t &h2)
+template <int W>
+__device__ __forceinline__ void tuple_hash(const Cand<W> &x, int32_t l, uint64_t &h1, uint64_t &h2)
 {
     uint64_t a = kSeed1, b = kSeed2;
 #pragma unroll
-    for (int k = 0; k < FX_MAXN; k++) {
+    for (int k = 0; k < W; k++) {
         if (k < l) {
             a = mix64(a ^ (uint64_t)(uint32_t)x.v[k]);
             b = mix64(b ^ (uint64_t)(uint32_t)x.v[k]);
@@ -276,10 +329,11 @@ __device__ __forceinline__ void tuple_hash(const Cand &x, int32_t l, uint64_t &h
 // the bitmap of pattern vertex k.  A word is read before the atomic OR, so a
 // vertex already marked (the common case: many embeddings share a partial)
 // costs no atomic.
-__device__ __forceinline__ void mark_images(uint32_t *img, uint64_t words, const Cand &x, int32_t l)
+template <int W>
+__device__ __forceinline__ void mark_images(uint32_t *img, uint64_t words, const Cand<W> &x, int32_t l)
 {
 #pragma unroll
-    for (int k = 0; k < FX_MAXN; k++) {  // fully unrolled: x.v stays in registers
+    for (int k = 0; k < W; k++) {  // fully unrolled: x.v stays in registers (l < W)
         if (k <= l) {
             const uint32_t v = (uint32_t)(k == l ? x.c : x.v[k]);
             uint32_t *w = img + (uint64_t)k * words + (v >> 5);
@@ -293,8 +347,9 @@ __device__ __forceinline__ void mark_images(uint32_t *img, uint64_t words, const
 // vertex i = l + 1 is a leaf whose only earlier neighbour is a: every vertex
 // of the run of a's image with i's (label, edge label) is a valid image,
 // except the already-matched vertices that lie in that run (injectivity).
+template <int W>
 __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan *__restrict__ plan, int32_t l,
-                                               const Cand &x, uint32_t &bytes)
+                                               const Cand<W> &x, uint32_t &bytes)
 {
     const int32_t i = l + 1;
     const int32_t a = plan->back[i][0];
@@ -303,12 +358,12 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
     const int32_t u = (a == l) ? x.c : pick(x.v, a);
     int64_t lo;
     int32_t len;
-    run_of(g, u, key, lo, len, bytes);
+    run_of<scan_width<W>()>(g, u, key, lo, len, bytes);
     int64_t c = len;
     for (int k = 0; k <= l; k++) {
         if (k == a || plan->vl[k] != vl) continue;
         const int32_t w = (k == l) ? x.c : pick(x.v, k);
-        if (has_entry(g, u, key | (uint32_t)w, bytes)) c--;
+        if (has_entry<scan_width<W>()>(g, u, key | (uint32_t)w, bytes)) c--;
     }
     return (uint64_t)c;
 }
@@ -316,7 +371,7 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
 // Test every candidate of every segment (ITEMS per thread, strided by
 // the workgroup size so each item pass covers consecutive candidates).
 // Writes a pass flag per candidate and the number of passes per workgroup.
-template <int ITEMS>
+template <int ITEMS, int W>
 __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe(
     FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt)
 {
@@ -357,7 +412,7 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
         bool mat = false;
         if (tl < S.span) {
             const uint64_t t = S.t0 + tl;
-            Cand x;
+            Cand<W> x;
             const int64_t p = tile_part(m, S.in.off, s_off, t);
             load_cand(g, S.in, l, p, t, x);
             // candidate entry + flag; the partial row and its run descriptor once
@@ -479,7 +534,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt
 // and the summary records how many candidates that took (the rest are
 // probed again in a later step), so a slice may span many more candidates
 // than the level holds rows.
-template <int ITEMS>
+template <int ITEMS, int W>
 __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
                                                    const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
                                                    const uint64_t *__restrict__ boff, uint64_t *lsum)
@@ -523,13 +578,13 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     const int32_t w1 = l + 1;
     uint32_t bytes = 0;
     uint64_t pos = boff[blockIdx.x] - seg_base;
-    uint64_t p_out[ITEMS];
+    uint32_t p_out[ITEMS];  // row of the candidate in the segment's output (< out_cap when written)
     int32_t lens[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
         lens[it] = 0;
-        p_out[it] = pos + (uint64_t)__popcll(bal[it] & lanemask_lt());
+        p_out[it] = (uint32_t)(pos + (uint64_t)__popcll(bal[it] & lanemask_lt()));
         for (uint32_t w = 0; w < wave; w++) p_out[it] += wcnt[it][w];
         if (f[it] && overflow && p_out[it] == cap - 1) S.sum->consumed = tl + 1;  // the last row that fits
         f[it] = f[it] && p_out[it] < cap;
@@ -537,11 +592,11 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
         bytes += (tl < S.span ? 1u : 0u) + (f[it] ? 4u * (uint32_t)w1 : 0u) + ((f[it] && w1 < n) ? 21u : 0u);
         if (f[it]) {
             const uint64_t t = S.t0 + tl;
-            Cand x;
+            Cand<W> x;
             load_cand(g, S.in, l, tile_part(m, S.in.off, s_off, t), t, x);
-            int32_t *dst = S.out.rows + p_out[it] * w1;
+            int32_t *dst = S.out.rows + (uint64_t)p_out[it] * (uint32_t)w1;
 #pragma unroll
-            for (int k = 0; k < FX_MAXN; k++)
+            for (int k = 0; k < W; k++)
                 if (k < l) dst[k] = x.v[k];
             dst[l] = x.c;
             if (w1 < n) {
@@ -564,7 +619,7 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
                         int32_t u = (b == l) ? x.c : pick(x.v, b);
                         int64_t lo;
                         int32_t len;
-                        run_of(g, u, run_key(vl, plan->bel[i2][kk]), lo, len, bytes);
+                        run_of<scan_width<W>()>(g, u, run_key(vl, plan->bel[i2][kk]), lo, len, bytes);
                         if (len < best_len) {
                             best_len = len;
                             best_lo = lo;
@@ -581,27 +636,30 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
         for (uint32_t w = 0; w < FX_BS / 64; w++) pos += wcnt[it][w];
     }
     if (S.kind == FX_SEG_INNER) {  // uniform across the workgroup
-        // exclusive prefix of the run lengths in output order (item, wave, lane)
-        long long inc[ITEMS];
+        // exclusive prefix of the run lengths in output order (item, wave,
+        // lane): wave totals first, then each lane's scan within its wave
+        // (recomputed rather than kept across the barrier: fewer registers)
         const uint32_t lane = __lane_id();
 #pragma unroll
         for (int it = 0; it < ITEMS; it++) {
-            inc[it] = lens[it];
+            unsigned long long tot = (unsigned long long)lens[it];
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const long long u = __shfl_up(inc[it], o);
-                if (lane >= (uint32_t)o) inc[it] += u;
-            }
-            const long long tot = __shfl(inc[it], 63);
-            if (lane == 0) ltot[it][wave] = (unsigned long long)tot;
+            for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o);
+            if (lane == 0) ltot[it][wave] = tot;
         }
         __syncthreads();
         uint64_t before = 0;
 #pragma unroll
         for (int it = 0; it < ITEMS; it++) {
+            long long inc = lens[it];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const long long u = __shfl_up(inc, o);
+                if (lane >= (uint32_t)o) inc += u;
+            }
             uint64_t mine = before;
             for (uint32_t w = 0; w < wave; w++) mine += ltot[it][w];
-            if (f[it]) S.out.off[p_out[it]] = (int64_t)(mine + (uint64_t)(inc[it] - lens[it]));
+            if (f[it]) S.out.off[p_out[it]] = (int64_t)(mine + (uint64_t)(inc - lens[it]));
             for (uint32_t w = 0; w < FX_BS / 64; w++) before += ltot[it][w];
         }
         if (threadIdx.x == 0) lsum[blockIdx.x] = before;
@@ -929,7 +987,7 @@ hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int
     return hipGetLastError();
 }
 
-template <int ITEMS>
+template <int ITEMS, int W>
 hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
                              int32_t nsegs, uint32_t nblocks, FxTile *tmap, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
                              uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin, hipEvent_t probe_end,
@@ -940,11 +998,11 @@ hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *se
     hipLaunchKernelGGL(k_tile_map<ITEMS>, dim3((nblocks + FX_BS - 1) / FX_BS), dim3(FX_BS), 0, s, segs, blk0s, nsegs,
                        nblocks, tmap);
     if (probe_begin && (e = hipEventRecord(probe_begin, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_probe<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, flag, bcnt);
+    hipLaunchKernelGGL((k_probe<ITEMS, W>), dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, flag, bcnt);
     if (probe_end && (e = hipEventRecord(probe_end, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_blocks<uint32_t>, dim3(1), dim3(1024), 0, s, bcnt, nblocks, boff);
     if (scatter_begin && (e = hipEventRecord(scatter_begin, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scatter<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, flag, boff, lsum);
+    hipLaunchKernelGGL((k_scatter<ITEMS, W>), dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, flag, boff, lsum);
     if (scatter_end && (e = hipEventRecord(scatter_end, s)) != hipSuccess) return e;
     if (any_inner) {
         hipLaunchKernelGGL(k_scan_blocks<uint64_t>, dim3(1), dim3(1024), 0, s, lsum, nblocks, loff);
@@ -956,24 +1014,45 @@ hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *se
     return hipGetLastError();
 }
 
+template <int W>
+hipError_t launch_step_width(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
+                             int32_t nsegs, uint32_t nblocks, int32_t items, FxTile *tmap, uint8_t *flag,
+                             uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
+                             hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
+                             hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
+{
+    switch (items) {
+    case 2:
+        return launch_step_items<2, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff,
+                                       probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                       any_inner, any_greedy);
+    case 8:
+        return launch_step_items<8, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff,
+                                       probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                       any_inner, any_greedy);
+    default:
+        return launch_step_items<4, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff,
+                                       probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                       any_inner, any_greedy);
+    }
+}
+
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                          int32_t nsegs, uint32_t nblocks, int32_t items, FxTile *tmap, uint8_t *flag,
+                          int32_t nsegs, uint32_t nblocks, int32_t items, int32_t maxn, FxTile *tmap, uint8_t *flag,
                           uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
                           hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
                           hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
 {
-    switch (items) {
-    case 2:
-        return launch_step_items<2>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff, probe_begin,
-                                    probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end, any_inner,
-                                    any_greedy);
-    case 8:
-        return launch_step_items<8>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff, probe_begin,
-                                    probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end, any_inner,
-                                    any_greedy);
-    default:
-        return launch_step_items<4>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff, probe_begin,
-                                    probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end, any_inner,
-                                    any_greedy);
-    }
+    if (maxn < 1 || maxn > FX_MAXN) return hipErrorInvalidValue;
+    if (maxn <= 4)
+        return launch_step_width<4>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, flag, bcnt, boff, lsum, loff,
+                                    probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                    any_inner, any_greedy);
+    if (maxn <= 8)
+        return launch_step_width<8>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, flag, bcnt, boff, lsum, loff,
+                                    probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                    any_inner, any_greedy);
+    return launch_step_width<FX_MAXN>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, flag, bcnt, boff, lsum, loff,
+                                      probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                      any_inner, any_greedy);
 }

@@ -222,6 +222,27 @@ def test_count_cap_saturation(torch_cuda, er1k):
         c.close()
 
 
+@pytest.mark.timeout(300)
+def test_wide_patterns_on_hubs(torch_cuda):
+    # 5- to 13-vertex patterns (every register width of a partial row: up to
+    # 4, 8 and 16 vertices) on a small power-law graph whose hubs have label
+    # runs long enough for the binary searches; the count is capped so the
+    # enumeration stays small, the support is exact
+    from paper_2404_01585_amd.synth import chung_lu
+    g = chung_lu(3000, 9000, 2.1, 11, 4, None, 2)
+    pats = (sample_patterns(g, 6, seed=4, kmin=5, kmax=8, shapes=("cycle", "chord", "tree"))
+            + sample_patterns(g, 12, seed=5, kmin=9, kmax=13, shapes=("cycle", "chord", "tree")))
+    cap = 1 << 20
+    for which, c in (("index", fx.Context(device=0, count_cap=cap)),
+                     ("search", fx.Context(device=0, count_cap=cap, slice_rows=256, run_index_bytes=-1))):
+        with c.load_graph(g) as dg:
+            for i, p in enumerate(pats):
+                _say("wide", which, i, "n", p.n)
+                full_match(dg, g, p, 2, 1.0, count_cap=cap)
+                verdict_match(dg, g, p, 5, 0.5)
+        c.close()
+
+
 def test_edge_cases(ctx):
     # isolated vertices, an empty adjacency, single-vertex patterns, absent labels
     g = csr_from_edges(6, [0, 1], [1, 2], [0, 0], [0, 0, 1, 1, 2, 2])
