@@ -296,9 +296,9 @@ fx_status fx_server_destroy(fx_server *s);
  * thread of the expansion kernels (2, 4, 8: the workgroup tile), candidates
  * per device step, the level capacity of a pattern's slice stack (the frontier
  * chunk), the complete embeddings per greedy slice (last_span_init), the
- * number of pipeline lanes (1: one device step at a time; 2: two lanes on two
- * streams, the host preparing one lane's step while the other lane's runs)
- * and the patterns in flight at once.  The fastest setting is kept in the
+ * number of pipeline lanes (1: one device step at a time; 2 or 3: lanes on
+ * their own streams, the host preparing one lane's step while the others'
+ * run) and the patterns in flight at once.  The fastest setting is kept in the
  * context (later calls use it; results never depend on it).
  * cache_path (optional): a text file of tuned keys (architecture, graph shape,
  * largest pattern, mode); a cached key is applied without timing. */

@@ -314,10 +314,11 @@ EngineWork::~EngineWork()
             if (e) (void)hipEventDestroy(e);
     }
     if (start_ev) (void)hipEventDestroy(start_ev);
-    if (own_stream) {
-        (void)hipStreamSynchronize(own_stream);
-        (void)hipStreamDestroy(own_stream);
-    }
+    for (auto &st : own_stream)
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
 }
 
 fx_status EngineWork::init_events()
@@ -328,28 +329,30 @@ fx_status EngineWork::init_events()
             if (!e) FX_HIP(hipEventCreate(&e));
     }
     if (!start_ev) FX_HIP(hipEventCreateWithFlags(&start_ev, hipEventDisableTiming));
-    if (!own_stream) FX_HIP(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+    for (auto &st : own_stream)
+        if (!st) FX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     return FX_OK;
 }
 
 FxEngine::FxEngine(fx_graph *G, EngineWork *W, hipStream_t s, const EngineParams &p, fx_stats *stats)
-    : G_(G), W_(W), s_(s), ls_{s, s}, P_(p), stats_(stats), t0_(std::chrono::steady_clock::now())
+    : G_(G), W_(W), s_(s), P_(p), stats_(stats), t0_(std::chrono::steady_clock::now())
 {
+    for (auto &st : ls_) st = s;
     if (P_.max_active < 1) P_.max_active = 1;
     // a segment's span is a 32-bit count
     P_.step_candidates = std::min<uint64_t>(std::max<uint64_t>(P_.step_candidates, FX_MAX_TILE), 1ull << 31);
-    P_.lanes = P_.lanes == 1 ? 1 : 2;
-    for (int k = P_.max_active - 1; k >= 0; k--) free_slots_[P_.lanes == 1 ? 0 : (k & 1)].push_back(k);
+    P_.lanes = std::min<int32_t>(std::max<int32_t>(P_.lanes, 1), FX_MAX_LANES);
+    for (int k = P_.max_active - 1; k >= 0; k--) free_slots_[k % P_.lanes].push_back(k);
 }
 
 FxEngine::~FxEngine()
 {
     // after an error, queries may still be running: let their work finish
     // before their stack memory goes back to the pool
-    if (!active_[0].empty() || !active_[1].empty() || !deferred_[0].empty() || !deferred_[1].empty()) {
-        (void)hipStreamSynchronize(ls_[0]);
-        (void)hipStreamSynchronize(ls_[1]);
-    }
+    bool busy = false;
+    for (int g = 0; g < FX_MAX_LANES; g++) busy = busy || !active_[g].empty() || !deferred_[g].empty();
+    if (busy)
+        for (int g = 0; g < P_.lanes; g++) (void)hipStreamSynchronize(ls_[g]);
     for (auto &A : active_)
         for (auto &q : A)
             if (q->region) W_->pool.give(q->region, q->region_bytes);
@@ -357,7 +360,13 @@ FxEngine::~FxEngine()
         for (auto &r : D) W_->pool.give(r.first, r.second);
 }
 
-bool FxEngine::idle() const { return pending_.empty() && active_[0].empty() && active_[1].empty(); }
+bool FxEngine::idle() const
+{
+    if (!pending_.empty()) return false;
+    for (const auto &A : active_)
+        if (!A.empty()) return false;
+    return true;
+}
 
 void FxEngine::done(FxRequest *r)
 {
@@ -506,7 +515,9 @@ fx_status FxEngine::admit(int g)
         const size_t bytes = region_size(q, nv);
         if (!W_->pool.take(bytes, &q.region)) {
             // wait until running queries free their regions
-            if (!active_[0].empty() || !active_[1].empty() || ninit > 0) break;
+            bool running = ninit > 0;
+            for (const auto &A : active_) running = running || !A.empty();
+            if (running) break;
             // it cannot fit even alone
             q.req->status = fx_fail(FX_ENOMEM, "query region of %zu bytes does not fit in the %zu-byte budget",
                                     bytes, W_->pool.budget);
@@ -594,8 +605,8 @@ fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
         FX_TRY(cp(q.sel_rank, old.sel_rank, k * 8));
     }
     // the copies read the old region on this lane's stream: it goes back to
-    // the pool once the lane's next step has been waited for (the other lane
-    // runs on another stream and could reuse it too early)
+    // the pool once the lane's next step has been waited for (the other lanes
+    // run on other streams and could reuse it too early)
     deferred_[q.lane].push_back({old.region, old.region_bytes});
     q.last_span = (uint32_t)std::min<int64_t>(P_.last_span_init, q.cap);
     stats_->promotions++;
@@ -623,7 +634,8 @@ fx_status FxEngine::step()
         const uint64_t tile = (uint64_t)FX_BS * P_.items;
         const uint64_t max_blocks = (P_.step_candidates + tile - 1) / tile + (uint64_t)A;
         FX_TRY(W_->sums_d.ensure((size_t)A * sizeof(FxSummary)));
-        for (auto &L : W_->lane) {
+        for (int g = 0; g < P_.lanes; g++) {
+            EngineLane &L = W_->lane[g];
             FX_TRY(L.flag.ensure(max_blocks * tile));
             FX_TRY(L.bcnt.ensure(max_blocks * 4));
             FX_TRY(L.boff.ensure((max_blocks + 1) * 8));
@@ -637,16 +649,18 @@ fx_status FxEngine::step()
             FX_TRY(L.sums_h.ensure((size_t)A * sizeof(FxSummary)));
         }
         FX_TRY(W_->init_events());
-        if (P_.lanes == 2) {
-            // lane 1 starts after whatever the caller queued on the engine's stream
-            ls_[1] = W_->own_stream;
+        if (P_.lanes > 1) {
+            // lanes 1.. start after whatever the caller queued on the engine's stream
             FX_HIP(hipEventRecord(W_->start_ev, s_));
-            FX_HIP(hipStreamWaitEvent(ls_[1], W_->start_ev, 0));
+            for (int g = 1; g < P_.lanes; g++) {
+                ls_[g] = W_->own_stream[g - 1];
+                FX_HIP(hipStreamWaitEvent(ls_[g], W_->start_ev, 0));
+            }
         }
         buffers_ready_ = true;
     }
     const int g = lane_;
-    lane_ = P_.lanes == 1 ? 0 : (lane_ ^ 1);
+    lane_ = (lane_ + 1) % P_.lanes;
     if (in_flight_[g]) FX_TRY(collect(g, waited));
     FX_TRY(admit(g));
     if (!active_[g].empty()) FX_TRY(launch(g));
@@ -672,13 +686,15 @@ fx_status FxEngine::launch(int g)
     uint32_t nblocks = 0;
     int any_inner = 0, any_greedy = 0, maxn = 1;
     const size_t A = act.size();
-    uint64_t mine = 0;  // open queries of this lane; the other lane's count is from its last launch
+    uint64_t mine = 0;  // open queries of this lane; the other lanes' counts are from their last launches
     for (auto &qp : act) {
         qp->seg_l = -1;
         mine += qp->deep >= 0;
     }
     nopen_[g] = mine;
-    const uint64_t n_open = mine + nopen_[g ^ 1];  // a query gets a step of its lane every other step
+    uint64_t n_open = mine;  // a query gets one step of its lane in every `lanes` steps
+    for (int h = 0; h < P_.lanes; h++)
+        if (h != g) n_open += nopen_[h];
     // a query's fair share of the step; a slice may take more candidates
     // than its level holds rows when few of them pass (the row cap bounds
     // what is written, see k_scatter)

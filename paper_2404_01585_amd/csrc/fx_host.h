@@ -21,6 +21,8 @@
 
 fx_status fx_fail(fx_status code, const char *fmt, ...);
 
+#define FX_MAX_LANES 3  // pipeline lanes of an engine (each with its own stream and scratch)
+
 // Runs fn(a, b) over the blocks [a, b) of `grain` indices of [0, n) on the
 // calling thread and the library's worker threads (started on first use, at
 // most 15, parked until the process ends).  Blocks are handed out through an
@@ -76,13 +78,13 @@ struct EngineParams {
     int32_t max_active = 4096;             // queries in flight
     uint32_t last_span_init = 4096;        // complete embeddings per greedy slice (support phase)
     int32_t items = 4;                     // candidates per thread in the expansion kernels (2, 4, 8)
-    int32_t lanes = 2;                     // pipeline lanes (1 or 2)
+    int32_t lanes = 2;                     // pipeline lanes (1 to FX_MAX_LANES)
     bool timing = false;
     bool no_digest = false;
 };
 
-// Buffers of one of the engine's two pipeline lanes: what the host writes for
-// a lane's step, and the summaries read back after it.
+// Buffers of one of the engine's pipeline lanes: what the host writes for a
+// lane's step, and the summaries read back after it.
 struct EngineLane {
     DevBuf stage_d, inits_d;           // stage: workgroup starts, then the segment table
     DevBuf flag, bcnt, boff, lsum, loff, tmap;  // per-step scratch of the expansion kernels
@@ -92,15 +94,15 @@ struct EngineLane {
 };
 
 // Device and pinned buffers of one engine (a context's, or a server's).  Lane
-// 0 runs on the engine's stream, lane 1 on a stream of its own, so the two
-// lanes' steps overlap on the device; each lane has its own scratch.
+// 0 runs on the engine's stream, every other lane on a stream of its own, so
+// the lanes' steps overlap on the device; each lane has its own scratch.
 struct EngineWork {
     EngineWork();  // the pool allocates its chunks with hipMalloc
     RegionPool pool;
     DevBuf sums_d;
-    EngineLane lane[2];
-    hipStream_t own_stream = nullptr;  // lane 1 (non-blocking, default priority)
-    hipEvent_t start_ev = nullptr;     // orders lane 1 after earlier work on the engine's stream
+    EngineLane lane[FX_MAX_LANES];
+    hipStream_t own_stream[FX_MAX_LANES - 1] = {};  // lanes 1.. (non-blocking, default priority)
+    hipEvent_t start_ev = nullptr;  // orders those lanes after earlier work on the engine's stream
     ~EngineWork();
     fx_status init_events();
 };
@@ -160,9 +162,9 @@ struct FxQuery;
 // The multi-query engine: requests are added at any time; each step() admits
 // pending requests while slots and memory allow, runs one device step for the
 // active ones and reports finished requests through on_done.  Queries are
-// split into two lanes by slot parity, and step() serves the lanes in turn:
-// it waits for a lane's previous device step, advances its queries and
-// launches its next step while the other lane's step runs on the device, so
+// split into lanes by slot (slot mod lanes), and step() serves the lanes in
+// turn: it waits for a lane's previous device step, advances its queries and
+// launches its next step while the other lanes' steps run on the device, so
 // the host's work between steps is hidden behind device work.
 class FxEngine {
 public:
@@ -174,10 +176,9 @@ public:
     // (invalid, a label absent from the graph, exact upper-bound reject) are
     // finished at once.
     void add(FxRequest *r);
-    // add() for a whole batch; the plans of a large batch are built on
-    // several host threads, then the requests are queued in order.
-    // Plans every request (in parallel), then queues them all; if a pattern
-    // is invalid, returns the error of the first such request and queues
+    // add() for a whole batch: plans every request (on the worker threads
+    // for a large batch), then queues them in order; if a pattern is
+    // invalid, returns the error of the first such request and queues
     // nothing.
     fx_status add_all(FxRequest *reqs, size_t count);
     bool idle() const;
@@ -196,17 +197,17 @@ private:
     fx_graph *G_;
     EngineWork *W_;
     hipStream_t s_;
-    hipStream_t ls_[2];                                    // each lane's stream
-    std::vector<std::pair<void *, size_t>> deferred_[2];   // regions freed once the lane's work passed them
+    hipStream_t ls_[FX_MAX_LANES];                                   // each lane's stream
+    std::vector<std::pair<void *, size_t>> deferred_[FX_MAX_LANES];  // regions freed once the lane's work passed them
     EngineParams P_;
     fx_stats *stats_;
     std::deque<std::unique_ptr<FxQuery>> pending_;
-    std::vector<std::unique_ptr<FxQuery>> active_[2];  // by lane
-    std::vector<int> free_slots_[2];
-    size_t rot_[2] = {0, 0};
-    bool in_flight_[2] = {false, false};
-    int any_greedy_[2] = {0, 0};
-    uint64_t nopen_[2] = {0, 0};  // queries with candidates left, per lane, at its last launch
+    std::vector<std::unique_ptr<FxQuery>> active_[FX_MAX_LANES];  // by lane
+    std::vector<int> free_slots_[FX_MAX_LANES];
+    size_t rot_[FX_MAX_LANES] = {};
+    bool in_flight_[FX_MAX_LANES] = {};
+    int any_greedy_[FX_MAX_LANES] = {};
+    uint64_t nopen_[FX_MAX_LANES] = {};  // queries with candidates left, per lane, at its last launch
     int lane_ = 0;  // the lane the next step() serves
     std::chrono::steady_clock::time_point t0_;
     bool buffers_ready_ = false;

@@ -143,7 +143,7 @@ extern "C" fx_status fx_autotune(fx_graph *g, int32_t npat, const fx_pattern *pa
                  {1ll << 23, 1ll << 24, 1ll << 25, 1ll << 26}));
     FX_TRY(sweep([](EngineParams &p, long long v) { p.slice_rows = v; }, {1ll << 15, 1ll << 16, 1ll << 17, 1ll << 18}));
     FX_TRY(sweep([](EngineParams &p, long long v) { p.last_span_init = (uint32_t)v; }, {1024, 4096, 16384}));
-    FX_TRY(sweep([](EngineParams &p, long long v) { p.lanes = (int32_t)v; }, {1, 2}));
+    FX_TRY(sweep([](EngineParams &p, long long v) { p.lanes = (int32_t)v; }, {1, 2, 3}));
     FX_TRY(sweep([](EngineParams &p, long long v) { p.max_active = (int32_t)v; }, {4096, 16384}));
     c->params = best;
     cache_store(cache_path, key, best, best_ms);
