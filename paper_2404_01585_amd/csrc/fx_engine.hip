@@ -26,6 +26,7 @@
 #include <thread>
 
 #include "fx_host.h"
+#include "fx_sym.h"
 
 // ---------------------------------------------------------------------------
 // Pattern plan
@@ -128,6 +129,8 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
             }
         }
     }
+    fx_symmetry_constraints(n, p->vlabel, el, P.sym_lt);
+    for (int i = 0; i < n; i++) hp.symmetric = hp.symmetric || P.sym_lt[i] != 0;
     // upper bound on any independent set: disjoint images (bound of Section 3.1.2)
     int64_t ub = G->nv / n;
     if (!hp.empty) {
@@ -495,7 +498,7 @@ fx_status FxEngine::finish(FxQuery &q, const FxSummary *sums)
     stats_->queries++;
     W_->pool.give(q.region, q.region_bytes);
     q.region = nullptr;
-    free_slots_[q.slot & 1].push_back(q.slot);
+    free_slots_[q.slot % P_.lanes].push_back(q.slot);  // slots stay with their lane (slot mod lanes)
     q.slot = -1;
     done(&r);
     return FX_OK;
@@ -725,7 +728,7 @@ fx_status FxEngine::launch(int g)
         int kind, flags = 0;
         uint64_t out_cap = (uint64_t)q.cap;  // rows the segment may write
         if (q.phase == PH_SUPPORT) {
-            flags = FX_PROBE_UFILTER;
+            flags = FX_PROBE_UFILTER | (q.hp.symmetric ? FX_PROBE_SYM : 0);
             kind = last ? FX_SEG_GREEDY : FX_SEG_INNER;
             if (last) out_cap = std::min<uint64_t>(q.last_span, (uint64_t)q.cap);
         } else if (q.phase == PH_COUNT) {

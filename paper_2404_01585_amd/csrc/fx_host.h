@@ -132,6 +132,7 @@ struct fx_graph {
 struct HostPlan {
     FxPlan plan{};
     bool empty = false;       // a label of the pattern does not occur in the graph
+    bool symmetric = false;   // the plan has symmetry-breaking constraints
     int64_t upper_bound = 0;  // support <= min(nv / n, min_l |V_l| / cnt_l)
 };
 

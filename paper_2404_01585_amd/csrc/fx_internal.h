@@ -48,6 +48,7 @@ struct FxPlan {
     uint16_t bel[FX_MAXN][FX_MAXN];       // dense edge label of (back[i][k], i)
     uint32_t nlf_key[FX_MAXN][FX_NLF];    // (label << 16 | elabel) of later neighbours
     uint8_t nlf_need[FX_MAXN][FX_NLF];    // how many such neighbours i needs
+    uint16_t sym_lt[FX_MAXN];             // bit j: f(j) < f(i) (support phase only)
 };
 static_assert(sizeof(FxPlan) % 4 == 0, "the plan is copied in 32-bit words");
 
@@ -108,6 +109,7 @@ enum : int32_t {
                             // vertex, a leaf with a single earlier neighbour (no hashing)
     FX_PROBE_HASH = 8,      // with FX_PROBE_COUNT: also hash every counted embedding
     FX_PROBE_IMAGES = 16,   // with FX_PROBE_COUNT: mark every counted embedding's images
+    FX_PROBE_SYM = 32,      // apply the plan's symmetry-breaking constraints (support phase)
 };
 
 struct FxSeg {

@@ -234,11 +234,17 @@ __device__ __forceinline__ int32_t pick(const int32_t (&v)[W], int32_t b)
 // Candidate test of Section 2.1.4 for pattern vertex i = l.
 template <int W>
 __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__restrict__ plan, int32_t n, int32_t l,
-                                         const Cand<W> &x, uint32_t &bytes)
+                                         bool sym, const Cand<W> &x, uint32_t &bytes)
 {
 #pragma unroll
     for (int k = 0; k < W; k++)
         if (k < l && x.v[k] == x.c) return false;  // injective
+    if (sym) {  // only the smallest embedding of each automorphism orbit
+        const uint32_t lt = plan->sym_lt[l];
+#pragma unroll
+        for (int k = 0; k < W; k++)
+            if (k < l && ((lt >> k) & 1u) && x.v[k] >= x.c) return false;
+    }
     const int32_t i = l;
     const uint32_t vl = plan->vl[i];
     const int32_t nb = plan->nback[i];
@@ -403,6 +409,7 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     const bool leaf = (flags & FX_PROBE_LEAF) != 0;
     const bool hash = (flags & FX_PROBE_HASH) != 0;
     const bool images = (flags & FX_PROBE_IMAGES) != 0;
+    const bool sym = (flags & FX_PROBE_SYM) != 0;
     uint32_t passed = 0, uout = 0;
     unsigned long long cnt = 0;
     uint64_t h1 = 0, h2 = 0;
@@ -429,7 +436,7 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
                 }
                 uout += ok ? 0u : 1u;
             }
-            if (ok) ok = feasible(g, S.plan, n, l, x, bytes);
+            if (ok) ok = feasible(g, S.plan, n, l, sym, x, bytes);
             if (ok) {
                 if (count) {
                     cnt++;

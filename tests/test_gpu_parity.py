@@ -222,6 +222,35 @@ def test_count_cap_saturation(torch_cuda, er1k):
         c.close()
 
 
+def test_symmetric_patterns(ctx, ctx_small):
+    # patterns with large automorphism groups (the support phase enumerates
+    # one embedding per orbit): stars, paths with equal ends, cycles, cliques,
+    # in several vertex numberings, on a graph with two vertex labels
+    rng = np.random.default_rng(21)
+    g = tiny_random_graph(rng, 300, 0.03, 2, 1)
+    pats = [Pattern([0, 0, 0, 0], [(0, 1), (0, 2), (0, 3)], [0] * 3),
+            Pattern([0, 0, 0, 0], [(3, 0), (3, 1), (3, 2)], [0] * 3),
+            Pattern([1, 0, 0, 1], [(0, 1), (1, 2), (2, 3)], [0] * 3),
+            Pattern([0, 1, 0], [(0, 1), (1, 2)], [0] * 2),
+            Pattern([0, 0, 0], [(0, 1), (1, 2), (0, 2)], [0] * 3),
+            Pattern([0, 0, 0, 0], [(0, 1), (1, 2), (2, 3), (3, 0)], [0] * 4),
+            Pattern([0, 0, 0, 0], [(0, 2), (2, 1), (1, 3), (3, 0)], [0] * 4),
+            Pattern([0, 0, 0, 0], [(a, b) for a in range(4) for b in range(a + 1, 4)], [0] * 6),
+            Pattern([0, 0, 1, 0, 0], [(2, 0), (2, 1), (2, 3), (2, 4)], [0] * 4)]
+    for which, c in (("default", ctx), ("small", ctx_small)):
+        with c.load_graph(g) as dg:
+            for i, p in enumerate(pats):
+                _say("symmetric", which, i)
+                full_match(dg, g, p, 2, 1.0)
+                for sigma in (1, 5, 40):
+                    verdict_match(dg, g, p, sigma, 0.5)
+            got = dg.support_batch(pats, [3] * len(pats), [1.0] * len(pats), fx.MODE_FULL)
+            for p, r in zip(pats, got):
+                want = O.query(g, p, 3, 1.0, O.FULL)
+                for k in ("support", "frequent", "embedding_count", "digest"):
+                    assert r[k] == want[k], (k, r[k], want[k])
+
+
 @pytest.mark.timeout(300)
 def test_wide_patterns_on_hubs(torch_cuda):
     # 5- to 13-vertex patterns (every register width of a partial row: up to
