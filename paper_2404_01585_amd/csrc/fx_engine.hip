@@ -164,6 +164,7 @@ constexpr double kFill = 0.8;                // aim a slice at this fraction of 
 constexpr int64_t kPromoteCap = 1 << 23;     // largest slice capacity a stack is moved to
 constexpr int32_t kPromoteAfter = 16;        // steps a query has run before its stack may grow
 constexpr uint64_t kLoneQueries = 2;         // open queries at or below which support stacks grow freely
+constexpr int32_t kLoneAfter = 1024;         // ... for VERDICT queries that have run this many steps
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -709,15 +710,17 @@ fx_status FxEngine::launch(int g)
     // larger slices expand partials that a selection would have removed
     // (measured: twice the probe work on cl1m).  A support-phase stack grows
     // only while U has removed under 1/64 of its candidates -- or, for a
-    // VERDICT query, once at most kLoneQueries queries are left: then the
-    // device is idle between their small steps, and fewer, larger steps
-    // finish sooner despite the extra expansion (cl1m: half the steps, 40%
-    // more patterns/s).  FULL queries keep the rule: their batch tail also
-    // holds other queries' counting, and the extra expansion cost 10% there.
-    const bool lone = n_open <= kLoneQueries;
+    // VERDICT query that has run kLoneAfter steps, once at most kLoneQueries
+    // queries are left: then the device is idle between their small steps,
+    // and fewer, larger steps finish sooner despite the extra expansion (cl1m:
+    // half the steps, 40% more patterns/s).  FULL queries keep the rule: their
+    // batch tail also holds other queries' counting, and the extra expansion
+    // cost 10% there; short queries keep it too (a single VERDICT call grew
+    // from the start and ran 3x slower).
+    const bool lone = P_.lone_growth && n_open <= kLoneQueries;
     for (auto &qp : act) {
         FxQuery &q = *qp;
-        const bool free_growth = lone && q.req->kind == FX_Q_VERDICT;
+        const bool free_growth = lone && q.req->kind == FX_Q_VERDICT && q.steps >= kLoneAfter;
         if (!free_growth && q.phase == PH_SUPPORT &&
             (q.probed_support == 0 || sums_prev[q.slot].ufiltered * 64 > q.probed_support))
             continue;

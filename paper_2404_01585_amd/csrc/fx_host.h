@@ -81,6 +81,7 @@ struct EngineParams {
     int32_t lanes = 2;                     // pipeline lanes (1 to FX_MAX_LANES)
     bool timing = false;
     bool no_digest = false;
+    bool lone_growth = true;  // long VERDICT queries left nearly alone may grow their support stacks
 };
 
 // Buffers of one of the engine's pipeline lanes: what the host writes for a
