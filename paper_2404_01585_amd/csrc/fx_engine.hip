@@ -23,7 +23,6 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
-#include <thread>
 
 #include "fx_host.h"
 #include "fx_sym.h"

@@ -3,7 +3,6 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
-#include <thread>
 #include <vector>
 
 #include "fx_host.h"
