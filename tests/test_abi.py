@@ -58,3 +58,17 @@ def test_null_arguments(lib):
     assert lib.fx_graph_destroy(None) == fx.FX_EINVAL
     assert lib.fx_support(None, None, 1, 0.5, 0, None, None, 0) == fx.FX_EINVAL
     assert lib.fx_enumerate(None, None, None, 0, None) == fx.FX_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark is single-GPU: asking for more exits with a message before
+    # touching any device
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 2
+    line = json.loads(out.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
