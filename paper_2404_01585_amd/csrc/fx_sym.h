@@ -53,15 +53,18 @@ struct AutSearch {
 // shrunk to the stabiliser of the vertices already walked, every vertex w in
 // the orbit of v (always w > v) gets the constraint f(v) < f(w); the members
 // that meet all constraints are exactly the smallest ones.  Sets lt[w] bit v
-// for each constraint.  A subset of the constraints (the search budget ran
-// out) still keeps every smallest member, so the result stays exact.
-inline void fx_symmetry_constraints(int n, const int32_t *vl, const int32_t (*el)[FX_MAXN], uint16_t *lt)
+// for each constraint.  A subset of the constraints (the search budget, in
+// search nodes for the whole pattern, ran out) still keeps every smallest
+// member, so the result stays exact.  The default budget bounds a plan's
+// search at about a millisecond.
+inline void fx_symmetry_constraints(int n, const int32_t *vl, const int32_t (*el)[FX_MAXN], uint16_t *lt,
+                                    int64_t budget = 50000)
 {
     AutSearch A;
     A.n = n;
     A.vl = vl;
     A.el = el;
-    A.budget = 200000;
+    A.budget = budget;
     for (int i = 0; i < n; i++)
         for (int j = 0; j < n; j++) A.deg[i] += el[i][j] >= 0;
     bool fixed[FX_MAXN] = {};

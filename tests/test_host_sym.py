@@ -57,13 +57,13 @@ def sym_exe(tmp_path_factory):
     return exe
 
 
-def _run(exe, pats):
+def _run(exe, pats, budget=0):
     lines = [str(len(pats))]
     for p in pats:
         el = [[-1] * p.n for _ in range(p.n)]
         for (a, b), l in zip(p.edges, p.elabel):
             el[a][b] = el[b][a] = l
-        lines.append(" ".join(map(str, [p.n] + list(p.vlabel) + [x for row in el for x in row])))
+        lines.append(" ".join(map(str, [budget, p.n] + list(p.vlabel) + [x for row in el for x in row])))
     out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr
     return [list(map(int, ln.split())) for ln in out.stdout.strip().splitlines()]
@@ -116,3 +116,26 @@ def test_constraints_keep_the_smallest_of_each_orbit(sym_exe):
             assert meets == (r == min(orbit)), (p, r, lt)
         nonempty += cnt > 0 and any(lt)
     assert nonempty > 20
+
+
+def test_cut_short_search_keeps_a_subset(sym_exe):
+    # with a tiny search budget the masks are a subset of the full ones (every
+    # kept constraint is one the smallest member meets), never something else
+    rng = np.random.default_rng(12)
+    pats = [random_connected_pattern(rng, int(rng.integers(3, 8)), 1, 1, extra_edge_p=0.3) for _ in range(120)]
+    full = _run(sym_exe, pats)
+    for budget in (1, 5, 20, 60):
+        part = _run(sym_exe, pats, budget)
+        for f, g in zip(full, part):
+            assert all((x & y) == x for x, y in zip(g, f)), (budget, f, g)
+        assert sum(map(sum, part)) <= sum(map(sum, full))
+    assert _run(sym_exe, pats, 1) != full  # the budget does cut
+
+
+def test_rigid_sixteen_vertex_pattern_returns(sym_exe):
+    # a 16-vertex pattern with one label and no symmetry: the search ends (by
+    # exhausting it or the budget) and keeps no constraint
+    edges = [(i, i + 1) for i in range(15)] + [(0, 2), (1, 4), (3, 7), (5, 11)]
+    rigid = Pattern([0] * 16, edges, [0] * len(edges))
+    (got,) = _run(sym_exe, [rigid])
+    assert got == [0] * 16
