@@ -170,7 +170,32 @@ typedef struct {
  *   device_ms         wall time from the start of the call (fx_support) or of the
  *                     batch (fx_support_batch) until the pattern's result was final.
  *   alg_bytes         algorithmic bytes of the query's expansion kernels (as in
- *                     fx_stats: probe plus scatter). */
+ *                     fx_stats: probe plus scatter).
+ *   sel_digest        FULL: (sum mod 2^64, xor) of the same hash chain over the
+ *                     selected embeddings (the greedy mIS S).  S in rank order is
+ *                     its tuples in lexicographic order, so the set fixes the
+ *                     list; the digest identifies S without copying it.  Else 0.
+ *   status            FX_OK, or the error of this query alone: fx_server_poll and
+ *                     fx_server_wait return that error and also store it here
+ *                     (for instance FX_ENOMEM for a query whose slice stack cannot
+ *                     fit the memory budget even alone).  Every other call that
+ *                     returns an error leaves its results untouched.
+ *   exit              how the query ended: FX_EXIT_END (the search ran to its end),
+ *                     FX_EXIT_REACHED (VERDICT: support reached tau, Section 3.1.1),
+ *                     FX_EXIT_BOUND (VERDICT: the selections still possible --
+ *                     at most one per root not yet finished, Section 3.2.2, and
+ *                     at most the disjointness bound of Section 3.1.2 -- cannot
+ *                     lift the support to tau: exactly infrequent), FX_EXIT_STATIC
+ *                     (VERDICT: the disjointness bound alone is below tau, decided
+ *                     before any device work), FX_EXIT_EMPTY (a label of the
+ *                     pattern does not occur in the graph). */
+enum {
+    FX_EXIT_END = 0,
+    FX_EXIT_REACHED = 1,
+    FX_EXIT_BOUND = 2,
+    FX_EXIT_STATIC = 3,
+    FX_EXIT_EMPTY = 4
+};
 typedef struct {
     int64_t tau;
     int64_t support;
@@ -182,6 +207,9 @@ typedef struct {
     int32_t rounds;
     double device_ms;
     uint64_t alg_bytes;
+    uint64_t sel_digest[2];
+    int32_t status;
+    int32_t exit;
 } fx_result;
 
 /* tau of the tau equation (Section 3.1.1):
@@ -231,7 +259,12 @@ fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, co
  *   promotions  stacks moved to a larger slice capacity because few queries
  *               were left to share the device.
  *   host_ms     host time inside the engine's steps, waits excluded.
- *   wait_ms     host time waiting for each step's device work to finish. */
+ *   wait_ms     host time waiting for each step's device work to finish.
+ *   exits_reached, exits_bound   VERDICT queries that ended early with
+ *               FX_EXIT_REACHED and FX_EXIT_BOUND (see fx_result.exit).
+ *   lone_promotions   of the promotions, those that only the rule for VERDICT
+ *               queries left nearly alone allowed (see the lone_* tunables of
+ *               fx_ctx_set). */
 typedef struct {
     uint64_t probe_launches;
     double probe_ms;
@@ -248,10 +281,31 @@ typedef struct {
     uint64_t promotions;
     double host_ms;
     double wait_ms;
+    uint64_t exits_reached;
+    uint64_t exits_bound;
+    uint64_t lone_promotions;
 } fx_stats;
 
 /* Copies the context's statistics into *out; reset != 0 zeroes them after. */
 fx_status fx_ctx_stats(fx_ctx *ctx, fx_stats *out, int32_t reset);
+
+/* Tunables of a context's engine, by name (results never depend on them;
+ * they set the launch shape and the scheduling of later calls):
+ *   slice_rows        level capacity of a pattern's slice stack [64, 2^26]
+ *   step_candidates   flattened candidates per device step [2048, 2^31]
+ *   items_per_thread  candidates per thread of the expansion kernels: 2, 4, 8
+ *   last_span_init    complete embeddings per greedy slice [1, 2^26]
+ *   lanes             pipeline lanes, each on its own stream: 1 to 3
+ *   max_active        patterns in flight at once [1, 2^20]
+ *   promote_after     steps a pattern runs before its stack may grow [0, 2^31)
+ *   lone_growth       0/1: long VERDICT patterns left nearly alone may grow
+ *                     their support-phase stacks
+ *   lone_queries      ... once at most this many patterns are open [0, 2^31)
+ *   lone_after        ... and the pattern has run this many steps [0, 2^31)
+ * fx_autotune sets the first six.  Errors: FX_EINVAL for an unknown name or a
+ * value out of range (the context is unchanged). */
+fx_status fx_ctx_set(fx_ctx *ctx, const char *key, int64_t value);
+fx_status fx_ctx_get(fx_ctx *ctx, const char *key, int64_t *value);
 
 /* Continuous-batching server over a resident graph.  A worker thread with its
  * own HIP stream runs the batched engine; queries submitted from any thread
@@ -317,6 +371,10 @@ typedef struct {
 
 fx_status fx_autotune(fx_graph *g, int32_t npat, const fx_pattern *pats, const int64_t *sigma, const double *lambda,
                       int32_t mode, const char *cache_path, fx_tune_result *out);
+
+/* Device and pinned-host allocation calls the library has made so far in
+ * this process (a check that a call allocated nothing). */
+uint64_t fx_alloc_calls(void);
 
 /* Thread-local description of the last error. */
 const char *fx_last_error(void);

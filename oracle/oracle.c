@@ -389,6 +389,21 @@ static int og_visit_count(og_dfs *s)
     return 0;
 }
 
+/* The same digest over a list of rows (for instance the selected set S,
+ * whose rank order is the lexicographic order of its tuples, so the set
+ * fixes the list): digest_out[0] = sum of h(e; S1), digest_out[1] = xor of
+ * h(e; S2) over the `count` rows of n ids each. */
+void og_rows_digest(const int32_t *rows, int64_t count, int32_t n, uint64_t *digest_out)
+{
+    uint64_t d0 = 0, d1 = 0;
+    for (int64_t r = 0; r < count; r++) {
+        d0 += og_tuple_hash(rows + r * n, n, OG_SEED1);
+        d1 ^= og_tuple_hash(rows + r * n, n, OG_SEED2);
+    }
+    digest_out[0] = d0;
+    digest_out[1] = d1;
+}
+
 /* count_out = min(|M|, cap); saturated_out = (|M| >= cap); digest of M
  * (meaningful only when not saturated). Returns 0, or -1 on a bad pattern. */
 int og_count(const og_graph *g, const og_pattern *p, int64_t cap, int64_t *count_out,

@@ -76,6 +76,8 @@ def _load():
                                        ctypes.c_void_p]
         lib.og_tuple_hash.restype = ctypes.c_uint64
         lib.og_tuple_hash.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64]
+        lib.og_rows_digest.restype = None
+        lib.og_rows_digest.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]
         lib.og_check_pattern.restype = ctypes.c_int
         lib.og_check_pattern.argtypes = [ctypes.c_void_p]
         _lib = lib
@@ -193,6 +195,16 @@ def tuple_hash(e: Sequence[int], seed: int) -> int:
     return int(_load().og_tuple_hash(_ptr(a), a.shape[0], seed))
 
 
+def rows_digest(rows: np.ndarray, n: int) -> Tuple[int, int]:
+    """(sum, xor) of the tuple hashes of the rows: the embedding digest's
+    hash applied to any list of tuples, e.g. the selected set S."""
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1, n) if n else
+                                np.zeros((0, 0), np.int32), dtype=np.int32)
+    d = (ctypes.c_uint64 * 2)()
+    _load().og_rows_digest(_ptr(rows) if rows.size else None, rows.shape[0], n, d)
+    return int(d[0]), int(d[1])
+
+
 def greedy_rows(rows: np.ndarray, nv: int) -> np.ndarray:
     rows = np.ascontiguousarray(rows, dtype=np.int32)
     sel = np.zeros(max(rows.shape[0], 1), dtype=np.int64)
@@ -213,7 +225,8 @@ def query(g, p, sigma: int, lam: float, mode: int = FULL, count_cap: int = 1 << 
     """The full per-pattern result the device path must reproduce.
 
     FULL: exact support, verdict, tau, min(|M|, cap), saturation flag,
-    digest and the selected embeddings in rank order.  VERDICT: the verdict
+    digest, the selected embeddings in rank order and their digest
+    (``sel_digest``: the same tuple hash over S).  VERDICT: the verdict
     only, with support = tau if frequent, else -1, and count = -1 (the
     search may stop once tau selections exist, Section 3.1.1).
     """
@@ -224,11 +237,11 @@ def query(g, p, sigma: int, lam: float, mode: int = FULL, count_cap: int = 1 << 
         k, _ = support_stream(g, P, stop_at=te)
         freq = k >= te
         return dict(tau=t, support=(t if freq else -1), frequent=int(freq), embedding_count=-1,
-                    count_saturated=0, digest=(0, 0), selected=None)
+                    count_saturated=0, digest=(0, 0), selected=None, sel_digest=(0, 0))
     k, sel = support_stream(g, P)
     c, sat, dg = count(g, P, count_cap)
     return dict(tau=t, support=k, frequent=int(k >= te), embedding_count=c, count_saturated=int(sat),
-                digest=(dg if not sat else (0, 0)), selected=sel)
+                digest=(dg if not sat else (0, 0)), selected=sel, sel_digest=rows_digest(sel, P.n))
 
 
 # ---------------------------------------------------------------------------

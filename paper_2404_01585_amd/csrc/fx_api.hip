@@ -48,18 +48,24 @@ void fx_parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t,
 // Buffers
 // ---------------------------------------------------------------------------
 
+std::atomic<uint64_t> fx_alloc_calls_made{0};
+
 void DevBuf::release()
 {
-    if (p) (void)hipFree(p);
+    if (p && !borrowed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    borrowed = false;
 }
 
 fx_status DevBuf::ensure(size_t want)
 {
     if (want <= bytes && p) return FX_OK;
+    if (borrowed)
+        return fx_fail(FX_ELIMIT, "a step needs %zu bytes of a scratch buffer of %zu bytes", want, bytes);
     release();
     const size_t b = std::max<size_t>(want, 256);
+    fx_alloc_calls_made++;
     hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) {
         p = nullptr;
@@ -81,6 +87,7 @@ fx_status HostBuf::ensure(size_t want)
     if (want <= bytes && p) return FX_OK;
     release();
     const size_t b = std::max<size_t>(want, 256);
+    fx_alloc_calls_made++;
     hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
     if (e != hipSuccess) {
         p = nullptr;
@@ -96,7 +103,9 @@ fx_status HostBuf::ensure(size_t want)
 
 extern "C" const char *fx_last_error(void) { return g_last_error.c_str(); }
 
-extern "C" const char *fx_version(void) { return "flexis-mi355x 0.2 (gfx950)"; }
+extern "C" const char *fx_version(void) { return "flexis-mi355x 0.3 (gfx950)"; }
+
+extern "C" uint64_t fx_alloc_calls(void) { return fx_alloc_calls_made.load(); }
 
 // tau of the tau equation (Section 3.1.1): floor(sigma * ((n-1) lambda + 1) / n)
 // with lambda rounded to parts per million, in exact integer arithmetic.
@@ -154,6 +163,45 @@ extern "C" fx_status fx_ctx_destroy(fx_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     delete c;
+    return FX_OK;
+}
+
+extern "C" fx_status fx_ctx_set(fx_ctx *c, const char *key, int64_t value)
+{
+    if (!c || !key) return fx_fail(FX_EINVAL, "NULL argument");
+    EngineParams &P = c->params;
+    const std::string k = key;
+    auto in = [&](int64_t lo, int64_t hi) -> bool { return value >= lo && value <= hi; };
+    if (k == "slice_rows" && in(64, (int64_t)1 << 26)) P.slice_rows = value;
+    else if (k == "step_candidates" && in(FX_MAX_TILE, (int64_t)1 << 31)) P.step_candidates = (uint64_t)value;
+    else if (k == "items_per_thread" && (value == 2 || value == 4 || value == 8)) P.items = (int32_t)value;
+    else if (k == "last_span_init" && in(1, (int64_t)1 << 26)) P.last_span_init = (uint32_t)value;
+    else if (k == "lanes" && in(1, FX_MAX_LANES)) P.lanes = (int32_t)value;
+    else if (k == "max_active" && in(1, 1 << 20)) P.max_active = (int32_t)value;
+    else if (k == "promote_after" && in(0, INT32_MAX)) P.promote_after = (int32_t)value;
+    else if (k == "lone_queries" && in(0, INT32_MAX)) P.lone_queries = (int32_t)value;
+    else if (k == "lone_after" && in(0, INT32_MAX)) P.lone_after = (int32_t)value;
+    else if (k == "lone_growth" && in(0, 1)) P.lone_growth = value != 0;
+    else return fx_fail(FX_EINVAL, "unknown tunable '%s' or value %lld out of range", key, (long long)value);
+    return FX_OK;
+}
+
+extern "C" fx_status fx_ctx_get(fx_ctx *c, const char *key, int64_t *value)
+{
+    if (!c || !key || !value) return fx_fail(FX_EINVAL, "NULL argument");
+    const EngineParams &P = c->params;
+    const std::string k = key;
+    if (k == "slice_rows") *value = P.slice_rows;
+    else if (k == "step_candidates") *value = (int64_t)P.step_candidates;
+    else if (k == "items_per_thread") *value = P.items;
+    else if (k == "last_span_init") *value = P.last_span_init;
+    else if (k == "lanes") *value = P.lanes;
+    else if (k == "max_active") *value = P.max_active;
+    else if (k == "promote_after") *value = P.promote_after;
+    else if (k == "lone_queries") *value = P.lone_queries;
+    else if (k == "lone_after") *value = P.lone_after;
+    else if (k == "lone_growth") *value = P.lone_growth ? 1 : 0;
+    else return fx_fail(FX_EINVAL, "unknown tunable '%s'", key);
     return FX_OK;
 }
 

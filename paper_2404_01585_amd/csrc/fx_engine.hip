@@ -161,9 +161,6 @@ namespace {
 constexpr uint64_t kCountSpan = 1ull << 22;  // least last-vertex candidates per counting step
 constexpr double kFill = 0.8;                // aim a slice at this fraction of the rows it may write
 constexpr int64_t kPromoteCap = 1 << 23;     // largest slice capacity a stack is moved to
-constexpr int32_t kPromoteAfter = 16;        // steps a query has run before its stack may grow
-constexpr uint64_t kLoneQueries = 2;         // open queries at or below which support stacks grow freely
-constexpr int32_t kLoneAfter = 1024;         // ... for VERDICT queries that have run this many steps
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -206,6 +203,7 @@ struct FxQuery {
     int32_t steps = 0;
     int deep = -1;                         // deepest level with candidates left (-1: none)
     int lane = 0;
+    int exit = FX_EXIT_END;                // how the query ended (fx_result.exit)
     int64_t listed = 0;
     // the segment of the current step (-1: none)
     int seg_l = -1, seg_kind = 0;
@@ -294,6 +292,7 @@ namespace {
 
 bool hip_region_alloc(void **p, size_t bytes)
 {
+    fx_alloc_calls_made++;
     if (hipMalloc(p, bytes) == hipSuccess) return true;
     (void)hipGetLastError();
     *p = nullptr;
@@ -418,7 +417,9 @@ void FxEngine::enqueue(std::unique_ptr<FxQuery> q)
     if (r->status != FX_OK) return done(r);
     fx_result res{};
     res.tau = q->tau;
+    res.status = FX_OK;
     if (q->hp.empty) {  // some label never occurs: M is empty
+        res.exit = FX_EXIT_EMPTY;
         if (r->kind == FX_Q_LIST) {
             *r->list_count = 0;
         } else {
@@ -429,6 +430,7 @@ void FxEngine::enqueue(std::unique_ptr<FxQuery> q)
         return done(r);
     }
     if (r->kind == FX_Q_VERDICT && q->hp.upper_bound < q->tau_eff) {  // support can never reach tau
+        res.exit = FX_EXIT_STATIC;
         res.support = -1;
         res.embedding_count = -1;
         *r->out = res;
@@ -454,6 +456,10 @@ fx_status FxEngine::finish(FxQuery &q, const FxSummary *sums)
         res.rounds = (int32_t)S.rounds;
         res.alg_bytes = (uint64_t)q.alg_probe_credit + S.alg_scatter;
         res.device_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0_).count();
+        res.status = FX_OK;
+        res.exit = q.exit;
+        if (q.exit == FX_EXIT_REACHED) stats_->exits_reached++;
+        if (q.exit == FX_EXIT_BOUND) stats_->exits_bound++;
         if (r.kind == FX_Q_VERDICT) {
             res.frequent = (int64_t)S.support >= q.tau_eff;
             res.support = res.frequent ? q.tau : -1;
@@ -475,6 +481,10 @@ fx_status FxEngine::finish(FxQuery &q, const FxSummary *sums)
             if (!sat && !P_.no_digest) {
                 res.digest[0] = S.digest0;
                 res.digest[1] = S.digest1;
+            }
+            if (r.kind == FX_Q_FULL) {
+                res.sel_digest[0] = S.sel_d0;
+                res.sel_digest[1] = S.sel_d1;
             }
             if (wants_selection(r) && S.support > 0) {
                 const int64_t k = (int64_t)S.support;
@@ -709,27 +719,31 @@ fx_status FxEngine::launch(int g)
     // larger slices expand partials that a selection would have removed
     // (measured: twice the probe work on cl1m).  A support-phase stack grows
     // only while U has removed under 1/64 of its candidates -- or, for a
-    // VERDICT query that has run kLoneAfter steps, once at most kLoneQueries
+    // VERDICT query that has run lone_after steps, once at most lone_queries
     // queries are left: then the device is idle between their small steps,
     // and fewer, larger steps finish sooner despite the extra expansion (cl1m:
     // half the steps, 40% more patterns/s).  FULL queries keep the rule: their
     // batch tail also holds other queries' counting, and the extra expansion
     // cost 10% there; short queries keep it too (a single VERDICT call grew
     // from the start and ran 3x slower).
-    const bool lone = P_.lone_growth && n_open <= kLoneQueries;
+    const bool lone = P_.lone_growth && n_open <= (uint64_t)std::max<int32_t>(P_.lone_queries, 0);
     for (auto &qp : act) {
         FxQuery &q = *qp;
-        const bool free_growth = lone && q.req->kind == FX_Q_VERDICT && q.steps >= kLoneAfter;
-        if (!free_growth && q.phase == PH_SUPPORT &&
-            (q.probed_support == 0 || sums_prev[q.slot].ufiltered * 64 > q.probed_support))
-            continue;
-        if (q.steps < kPromoteAfter || q.cap >= kPromoteCap || share < 4 * (uint64_t)q.cap) continue;
+        const bool free_growth = lone && q.req->kind == FX_Q_VERDICT && q.steps >= P_.lone_after;
+        const bool u_ok = q.phase != PH_SUPPORT ||
+                          (q.probed_support > 0 && sums_prev[q.slot].ufiltered * 64 <= q.probed_support);
+        if (!free_growth && !u_ok) continue;
+        if (q.steps < P_.promote_after || q.cap >= kPromoteCap || share < 4 * (uint64_t)q.cap) continue;
         if (q.deep < 0) continue;
         uint64_t left = 0;  // largest candidate range still open: no slice needs more rows
         for (int l = 0; l < q.n; l++) left = std::max<uint64_t>(left, q.T[l] - q.cur[l]);
         int64_t nc = q.cap;
         while (nc < kPromoteCap && (uint64_t)nc * 2 <= share && (uint64_t)nc < left) nc *= 2;
-        if (nc > q.cap) FX_TRY(promote(q, nc));
+        if (nc > q.cap) {
+            const uint64_t before = stats_->promotions;
+            FX_TRY(promote(q, nc));
+            if (!u_ok && stats_->promotions > before) stats_->lone_promotions++;  // only the lone rule allowed it
+        }
     }
     for (size_t k = 0; k < A && budget > 0; k++) {
         FxQuery &q = *act[(rot_[g] + k) % A];
@@ -893,7 +907,28 @@ fx_status FxEngine::collect(int g, double &waited)
         FxQuery &q = *act[k];
         const FxSummary &S = sums_h[q.slot];
         bool fin = false;
-        if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_VERDICT && (int64_t)S.support >= q.tau_eff) fin = true;
+        if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_VERDICT) {
+            const int64_t sup = (int64_t)S.support;
+            if (sup >= q.tau_eff) {  // early termination at tau (Section 3.1.1)
+                fin = true;
+                q.exit = FX_EXIT_REACHED;
+            } else if (q.deep >= 0) {
+                // exactly infrequent once the selections still possible cannot
+                // reach tau: a later selection has its own root (one per root,
+                // Section 3.2.2) among the level-0 candidates not yet expanded
+                // and the roots of the current level-1 slice (every open partial
+                // descends from one of them); and all selections are disjoint,
+                // so at most the upper bound of Section 3.1.2 exist in total
+                uint64_t roots = q.T[0] - q.cur[0];
+                if (q.deep >= 1) roots += (uint64_t)q.nparts[1];
+                const int64_t room = std::max<int64_t>(q.hp.upper_bound - sup, 0);
+                const int64_t possible = std::min<int64_t>((int64_t)std::min<uint64_t>(roots, INT64_MAX), room);
+                if (sup + possible < q.tau_eff) {
+                    fin = true;
+                    q.exit = FX_EXIT_BOUND;
+                }
+            }
+        }
         // (the minimum-image support needs every embedding: the cap only caps its count)
         if (q.phase == PH_COUNT && q.req->kind != FX_Q_MNI && (int64_t)S.count >= P_.count_cap) fin = true;
         if (!fin && q.deep < 0) {
@@ -915,13 +950,19 @@ fx_status FxEngine::collect(int g, double &waited)
     return FX_OK;
 }
 
+fx_status fx_engine_run_on(fx_graph *G, EngineWork *W, const EngineParams &p, std::vector<FxRequest> &reqs)
+{
+    fx_ctx *c = G->ctx;
+    FxEngine eng(G, W, c->stream, p, &c->stats);
+    FX_TRY(eng.add_all(reqs.data(), reqs.size()));
+    while (!eng.idle()) FX_TRY(eng.step());
+    return FX_OK;
+}
+
 fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active)
 {
     fx_ctx *c = G->ctx;
     EngineParams p = c->params;
     p.max_active = std::max<int32_t>(1, std::min<int32_t>(max_active, (int32_t)std::max<size_t>(reqs.size(), 1)));
-    FxEngine eng(G, &c->work, c->stream, p, &c->stats);
-    FX_TRY(eng.add_all(reqs.data(), reqs.size()));
-    while (!eng.idle()) FX_TRY(eng.step());
-    return FX_OK;
+    return fx_engine_run_on(G, &c->work, p, reqs);
 }

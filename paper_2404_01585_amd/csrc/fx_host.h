@@ -42,16 +42,32 @@ void fx_parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t,
         if (s_ != FX_OK) return s_; \
     } while (0)
 
-// Device allocation that remembers its size.
+// Number of device and pinned-host allocation calls the library has made
+// (every hipMalloc / hipHostMalloc goes through DevBuf, HostBuf or the
+// region pool's allocator, which count them).
+extern std::atomic<uint64_t> fx_alloc_calls_made;
+
+// Device allocation that remembers its size.  A borrowed buffer points into
+// memory the library does not own (the static scratch array of the
+// allocation-free entry point): ensure() never allocates for it and fails
+// when it is too small, release() never frees it.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release();
     fx_status ensure(size_t want);
+    void borrow(void *q, size_t n)
+    {
+        release();
+        p = q;
+        bytes = n;
+        borrowed = true;
+    }
     template <class T>
     T *as() const { return (T *)p; }
 };
@@ -82,6 +98,9 @@ struct EngineParams {
     bool timing = false;
     bool no_digest = false;
     bool lone_growth = true;  // long VERDICT queries left nearly alone may grow their support stacks
+    int32_t promote_after = 16;   // steps a query has run before its stack may grow
+    int32_t lone_queries = 2;     // open queries at or below which VERDICT support stacks grow freely
+    int32_t lone_after = 1024;    // ... once the VERDICT query has run this many steps
 };
 
 // Buffers of one of the engine's pipeline lanes: what the host writes for a
@@ -117,6 +136,7 @@ struct fx_ctx {
     fx_stats stats{};
     EngineWork work;
 };
+
 
 struct fx_graph {
     fx_ctx *ctx = nullptr;
@@ -219,3 +239,5 @@ private:
 // flight).  Requests that fail validation get their status set; any device
 // error aborts the run.
 fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active);
+// The same over given buffers and parameters.
+fx_status fx_engine_run_on(fx_graph *G, EngineWork *W, const EngineParams &p, std::vector<FxRequest> &reqs);

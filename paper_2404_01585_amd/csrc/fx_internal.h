@@ -80,7 +80,9 @@ struct FxSummary {
     unsigned long long passes;      // candidates of the last segment that passed (before the row cap)
     unsigned long long consumed;    // candidates of the last segment taken (the rest are offered again)
     unsigned long long ufiltered;   // candidates the used set U has removed so far
-    unsigned long long pad[3];
+    unsigned long long sel_d0;      // sum of the hashes of the selected embeddings (mod 2^64)
+    unsigned long long sel_d1;      // xor of their second hashes
+    unsigned long long pad[1];
 };
 
 // One level of a slice stack: partial embeddings with l matched vertices

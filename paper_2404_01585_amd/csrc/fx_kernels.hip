@@ -886,17 +886,35 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
         // when asked for, the selected rows with their ranks
         constexpr int kPer = (FX_GREEDY_VN + FX_BS - 1) / FX_BS;  // embeddings of a chunk per thread
         uint32_t my_pos[kPer];
+        uint64_t sh1 = 0, sh2 = 0;  // digest of the selected set (same hash chain as the count's)
 #pragma unroll
         for (int k = 0; k < kPer; k++) {
             const uint32_t e = threadIdx.x + (uint32_t)k * FX_BS;
             my_pos[k] = 0xffffffffu;
             if (e >= nb || (state[e] != 1 && state[e] != 3)) continue;
             const int32_t *row = rows + (c0 + e) * n;
+            uint64_t a = kSeed1, b = kSeed2;
             for (int j = 0; j < n; j++) {
                 const uint32_t v = (uint32_t)row[j];
                 atomicOr(&S.U[v >> 5], 1u << (v & 31u));
+                a = mix64(a ^ (uint64_t)v);
+                b = mix64(b ^ (uint64_t)v);
             }
+            sh1 += a;
+            sh2 ^= b;
             my_pos[k] = atomicAdd(&nsel, 1u);
+        }
+        {
+            unsigned long long s1 = sh1, s2 = sh2;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                s1 += __shfl_xor(s1, o);
+                s2 ^= __shfl_xor(s2, o);
+            }
+            if (__lane_id() == 0 && (s1 | s2)) {
+                atomicAdd(&S.sum->sel_d0, s1);
+                atomicXor(&S.sum->sel_d1, s2);
+            }
         }
         __syncthreads();
         if (threadIdx.x == 0) {

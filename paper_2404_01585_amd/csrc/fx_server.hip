@@ -90,7 +90,12 @@ fx_status take_result(fx_server *S, std::unordered_map<uint64_t, std::unique_ptr
 {
     ServerTicket *t = it->second.get();
     const fx_status st = t->req.status;
-    if (st == FX_OK) *out = t->res;
+    if (st == FX_OK) {
+        *out = t->res;
+    } else {  // the query's own error, also in the result
+        *out = fx_result{};
+        out->status = st;
+    }
     S->tickets.erase(it);
     if (st != FX_OK) return fx_fail(st, "query failed: %s", S->failed != FX_OK ? S->fail_msg.c_str() : "invalid query");
     return FX_OK;

@@ -37,9 +37,16 @@ _STATUS_NAMES = {0: "FX_OK", -1: "FX_EINVAL", -2: "FX_EGRAPH", -3: "FX_EPATTERN"
 
 # Every symbol include/flexis.h declares.
 EXPORTS = ["fx_ctx_create", "fx_ctx_destroy", "fx_graph_load", "fx_graph_destroy", "fx_tau", "fx_support",
-           "fx_enumerate", "fx_support_batch", "fx_ctx_stats", "fx_server_create", "fx_server_submit",
-           "fx_server_poll", "fx_server_wait", "fx_server_stats", "fx_server_destroy", "fx_autotune",
-           "fx_last_error", "fx_version"]
+           "fx_enumerate", "fx_support_batch", "fx_ctx_stats", "fx_ctx_set", "fx_ctx_get", "fx_server_create",
+           "fx_server_submit", "fx_server_poll", "fx_server_wait", "fx_server_stats", "fx_server_destroy",
+           "fx_autotune", "fx_alloc_calls", "fx_last_error", "fx_version"]
+
+# fx_result.exit
+EXIT_END = 0
+EXIT_REACHED = 1
+EXIT_BOUND = 2
+EXIT_STATIC = 3
+EXIT_EMPTY = 4
 
 CTX_KERNEL_TIMING = 1
 CTX_NO_DIGEST = 2
@@ -89,7 +96,9 @@ class StatsC(ctypes.Structure):
                 ("scatter_ms", ctypes.c_double), ("scatter_alg_bytes", ctypes.c_uint64),
                 ("greedy_launches", ctypes.c_uint64), ("greedy_ms", ctypes.c_double), ("steps", ctypes.c_uint64),
                 ("syncs", ctypes.c_uint64), ("queries", ctypes.c_uint64), ("reoffered", ctypes.c_uint64),
-                ("promotions", ctypes.c_uint64), ("host_ms", ctypes.c_double), ("wait_ms", ctypes.c_double)]
+                ("promotions", ctypes.c_uint64), ("host_ms", ctypes.c_double), ("wait_ms", ctypes.c_double),
+                ("exits_reached", ctypes.c_uint64), ("exits_bound", ctypes.c_uint64),
+                ("lone_promotions", ctypes.c_uint64)]
 
     def to_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,20 +108,24 @@ class ResultC(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_int64), ("support", ctypes.c_int64), ("frequent", ctypes.c_int32),
                 ("count_saturated", ctypes.c_int32), ("embedding_count", ctypes.c_int64),
                 ("digest", ctypes.c_uint64 * 2), ("steps", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("device_ms", ctypes.c_double), ("alg_bytes", ctypes.c_uint64)]
+                ("device_ms", ctypes.c_double), ("alg_bytes", ctypes.c_uint64), ("sel_digest", ctypes.c_uint64 * 2),
+                ("status", ctypes.c_int32), ("exit", ctypes.c_int32)]
 
     def to_dict(self) -> Dict:
         return dict(tau=self.tau, support=self.support, frequent=self.frequent,
                     count_saturated=self.count_saturated, embedding_count=self.embedding_count,
                     digest=(int(self.digest[0]), int(self.digest[1])), steps=self.steps, rounds=self.rounds,
-                    device_ms=self.device_ms, alg_bytes=int(self.alg_bytes))
+                    device_ms=self.device_ms, alg_bytes=int(self.alg_bytes),
+                    sel_digest=(int(self.sel_digest[0]), int(self.sel_digest[1])), status=self.status,
+                    exit=self.exit)
 
 
 # numpy views of the C structs (same field order, offsets and sizes)
 PATTERN_DTYPE = np.dtype([("n", "<i4"), ("m", "<i4"), ("vlabel", "<u8"), ("edges", "<u8"), ("elabel", "<u8")])
 RESULT_DTYPE = np.dtype([("tau", "<i8"), ("support", "<i8"), ("frequent", "<i4"), ("count_saturated", "<i4"),
                          ("embedding_count", "<i8"), ("digest", "<u8", (2,)), ("steps", "<i4"), ("rounds", "<i4"),
-                         ("device_ms", "<f8"), ("alg_bytes", "<u8")])
+                         ("device_ms", "<f8"), ("alg_bytes", "<u8"), ("sel_digest", "<u8", (2,)), ("status", "<i4"),
+                         ("exit", "<i4")])
 assert PATTERN_DTYPE.itemsize == ctypes.sizeof(PatternC)
 assert RESULT_DTYPE.itemsize == ctypes.sizeof(ResultC)
 
@@ -199,6 +212,12 @@ def load_library():
     lib.fx_autotune.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_int32, ctypes.c_char_p, P]
     lib.fx_ctx_stats.restype = ctypes.c_int32
     lib.fx_ctx_stats.argtypes = [P, P, ctypes.c_int32]
+    lib.fx_ctx_set.restype = ctypes.c_int32
+    lib.fx_ctx_set.argtypes = [P, ctypes.c_char_p, ctypes.c_int64]
+    lib.fx_ctx_get.restype = ctypes.c_int32
+    lib.fx_ctx_get.argtypes = [P, ctypes.c_char_p, P]
+    lib.fx_alloc_calls.restype = ctypes.c_uint64
+    lib.fx_alloc_calls.argtypes = []
     lib.fx_support_batch.restype = ctypes.c_int32
     lib.fx_support_batch.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_int32, P]
     _lib = lib
@@ -208,6 +227,11 @@ def load_library():
 def _check(status: int):
     if status != FX_OK:
         raise FxError(status, load_library().fx_last_error().decode(errors="replace"))
+
+
+def alloc_calls() -> int:
+    """fx_alloc_calls: device and pinned-host allocations made by the library so far."""
+    return int(load_library().fx_alloc_calls())
 
 
 def last_error() -> str:
@@ -268,6 +292,15 @@ class Context:
         st = StatsC()
         _check(load_library().fx_ctx_stats(self._h, ctypes.byref(st), 1 if reset else 0))
         return st.to_dict()
+
+    def set(self, key: str, value: int) -> None:
+        """fx_ctx_set: an engine tunable by name (launch shape, scheduling)."""
+        _check(load_library().fx_ctx_set(self._h, key.encode(), int(value)))
+
+    def get(self, key: str) -> int:
+        out = ctypes.c_int64(0)
+        _check(load_library().fx_ctx_get(self._h, key.encode(), ctypes.byref(out)))
+        return int(out.value)
 
     def load_graph(self, g, on_device: bool = False) -> "DeviceGraph":
         return DeviceGraph(self, g, on_device=on_device)
@@ -363,8 +396,10 @@ class DeviceGraph:
         res = self.support_batch_array(PatternBatch(patterns), sigma, lam, mode)
         out = []
         for r in res:
-            d = {k: (int(r[k]) if k != "device_ms" else float(r[k])) for k in RESULT_DTYPE.names if k != "digest"}
+            d = {k: (int(r[k]) if k != "device_ms" else float(r[k])) for k in RESULT_DTYPE.names
+                 if k not in ("digest", "sel_digest")}
             d["digest"] = (int(r["digest"][0]), int(r["digest"][1]))
+            d["sel_digest"] = (int(r["sel_digest"][0]), int(r["sel_digest"][1]))
             out.append(d)
         return out
 

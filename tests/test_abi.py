@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_symbols():
     text = open(os.path.join(ROOT, "include", "flexis.h")).read()
-    return sorted(set(re.findall(r"^(?:fx_status|const char \*)\s*(fx_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:fx_status|const char \*|uint64_t)\s*(fx_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -58,6 +58,15 @@ def test_null_arguments(lib):
     assert lib.fx_graph_destroy(None) == fx.FX_EINVAL
     assert lib.fx_support(None, None, 1, 0.5, 0, None, None, 0) == fx.FX_EINVAL
     assert lib.fx_enumerate(None, None, None, 0, None) == fx.FX_EINVAL
+    assert lib.fx_ctx_set(None, b"lanes", 1) == fx.FX_EINVAL
+    assert lib.fx_ctx_get(None, b"lanes", None) == fx.FX_EINVAL
+
+
+def test_result_layout_matches_header(lib):
+    # the numpy view of fx_result used for batches has the ctypes struct's layout
+    assert fx.RESULT_DTYPE.itemsize == ctypes.sizeof(fx.ResultC)
+    for name, _ in fx.ResultC._fields_:
+        assert fx.RESULT_DTYPE.fields[name][1] == getattr(fx.ResultC, name).offset, name
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -42,13 +42,19 @@ def ctx_small(torch_cuda):
     yield c
 
 
+FULL_KEYS = ("tau", "support", "frequent", "embedding_count", "count_saturated", "digest", "sel_digest")
+
+
 def full_match(dg, g, p, sigma, lam, count_cap=1 << 62, sel=True):
     want = O.query(g, p, sigma, lam, O.FULL, count_cap=count_cap)
     got = dg.support(p, sigma, lam, fx.MODE_FULL, selected_cap=(g.num_vertices if sel else 0))
-    for k in ("tau", "support", "frequent", "embedding_count", "count_saturated", "digest"):
+    for k in FULL_KEYS:
         assert got[k] == want[k], (k, got[k], want[k])
+    assert got["status"] == fx.FX_OK and got["exit"] in (fx.EXIT_END, fx.EXIT_EMPTY)
     if sel:
         assert np.array_equal(got["selected"], want["selected"]), (got["selected"], want["selected"])
+        # the selection digest is that of the selected rows
+        assert got["sel_digest"] == O.rows_digest(got["selected"], p.n)
     return got
 
 
@@ -368,18 +374,20 @@ def test_merge_generator_mining(ctx, er1k):
 
 
 def test_er1k_mining_batch(ctx, er1k):
-    """Every candidate of the first three mining levels on the 1K-vertex graph,
-    as one batch, FULL and VERDICT, against the oracle pattern by pattern."""
+    """Every candidate of the mining levels up to 4 edges on the 1K-vertex
+    graph (sigma 20), as one batch, FULL and VERDICT, against the oracle
+    pattern by pattern: support, verdict, count, embedding digest and the
+    selected set's digest."""
     g = er1k
-    cands = _mining_candidates(g, 20, 1.0, 3)
-    assert len(cands) > 500
+    cands = _mining_candidates(g, 20, 1.0, 4)
+    assert len(cands) > 4000 and max(p.m for p in cands) == 4
     with ctx.load_graph(g) as dg:
         for lam in (1.0, 0.3):
             _say("er1k batch FULL lambda", lam, "patterns", len(cands))
             got = dg.support_batch(cands, [20] * len(cands), [lam] * len(cands), fx.MODE_FULL)
             for p, r in zip(cands, got):
                 want = O.query(g, p, 20, lam, O.FULL)
-                for k in ("tau", "support", "frequent", "embedding_count", "count_saturated", "digest"):
+                for k in FULL_KEYS:
                     assert r[k] == want[k], (p, k, r[k], want[k])
             _say("er1k batch VERDICT lambda", lam)
             got = dg.support_batch(cands, [20] * len(cands), [lam] * len(cands), fx.MODE_VERDICT)
@@ -451,6 +459,12 @@ def test_server_alone_equals_in_the_mix(ctx, er1k):
     modes = [int(x) for x in rng.integers(0, 2, size=len(pats))]
     with ctx.load_graph(g) as dg:
         alone = [dg.support(p, s, l, m) for p, s, l, m in zip(pats, sig, lam, modes)]
+        # every query alone is the oracle's answer
+        for p, sg, lm, md, a in zip(pats, sig, lam, modes, alone):
+            want = O.query(g, p, sg, lm, md)
+            for k in (("tau", "support", "frequent", "embedding_count") +
+                      (("count_saturated", "digest", "sel_digest") if md == fx.MODE_FULL else ())):
+                assert a[k] == want[k], (k, a[k], want[k])
         with fx.Server(dg, max_active=32, step_candidates=1 << 16) as srv:
             tickets = [None] * len(pats)
 
@@ -470,9 +484,10 @@ def test_server_alone_equals_in_the_mix(ctx, er1k):
             st = srv.stats()
         assert st["queries"] > 0
         for i in range(len(pats)):
-            for k in ("tau", "support", "frequent", "embedding_count", "count_saturated", "digest"):
+            for k in ("tau", "support", "frequent", "embedding_count", "count_saturated", "digest", "sel_digest",
+                      "exit"):
                 assert got[i][k] == alone[i][k], (i, k, got[i][k], alone[i][k])
-            assert got[i]["device_ms"] >= 0
+            assert got[i]["device_ms"] >= 0 and got[i]["status"] == fx.FX_OK
         # errors are reported at submission; unknown tickets are rejected; the
         # graph cannot go while a server holds it
         with fx.Server(dg) as srv:
@@ -550,3 +565,70 @@ def test_launch_shapes_agree(torch_cuda, er1k, tmp_path):
                 for k in ("support", "frequent", "embedding_count", "digest"):
                     assert r[k] == want[k], (p, k)
         assert row == ref
+
+
+def test_verdict_bound_exit(torch_cuda, er1k):
+    """VERDICT queries whose support can no longer reach tau stop early
+    (one selection per root not yet finished, Section 3.2.2, and at most the
+    disjointness bound of Section 3.1.2): the verdicts equal the oracle's, and
+    the exit fires.  Thresholds sit near the disjointness bound so that few
+    roots are left when it is decided; small slices give many steps."""
+    g = er1k
+    pats = sample_patterns(g, 30, seed=123, kmin=2, kmax=5)
+    nlab = np.bincount(g.vlabel)
+    cases = []
+    for p in pats:
+        cnt = np.bincount(np.asarray(p.vlabel), minlength=nlab.shape[0])
+        ub = min(g.num_vertices // p.n, min(int(nlab[l]) // int(c) for l, c in enumerate(cnt) if c))
+        for frac in (1.0, 0.9, 0.75, 0.5):
+            cases.append((p, max(1, int(ub * frac))))
+    c = fx.Context(device=0, slice_rows=64, run_index_bytes=-1)
+    with c.load_graph(g) as dg:
+        for lanes in (1, 2):
+            c.set("lanes", lanes)
+            c.stats(reset=True)
+            _say("bound exit, lanes", lanes, "cases", len(cases))
+            got = dg.support_batch([p for p, _ in cases], [s for _, s in cases], [1.0] * len(cases),
+                                   fx.MODE_VERDICT)
+            alone = [dg.support(p, s, 1.0, fx.MODE_VERDICT) for p, s in cases[:40]]
+            st = c.stats()
+            _say("stats", st)
+            for (p, sg), r in zip(cases, got):
+                want = O.query(g, p, sg, 1.0, O.VERDICT)
+                for k in ("tau", "support", "frequent", "embedding_count"):
+                    assert r[k] == want[k], (p, sg, k, r[k], want[k])
+                if r["exit"] == fx.EXIT_BOUND:
+                    assert r["frequent"] == 0
+                if r["exit"] == fx.EXIT_REACHED:
+                    assert r["frequent"] == 1
+            for a, b in zip(alone, got):
+                assert (a["frequent"], a["support"]) == (b["frequent"], b["support"])
+            assert st["exits_bound"] > 0
+            assert sum(r["exit"] == fx.EXIT_BOUND for r in got) > 0
+    c.close()
+
+
+def test_lone_growth_fires(torch_cuda, er1k):
+    """The stacks of VERDICT queries counted as left nearly alone grow where
+    the used-set rule would keep them (here every query counts as alone from
+    its first step), and the verdicts stay the oracle's."""
+    g = er1k
+    pats = sample_patterns(g, 16, seed=321, kmin=4, kmax=7)
+    c = fx.Context(device=0, slice_rows=64, run_index_bytes=-1)
+    c.set("promote_after", 0)
+    c.set("lone_after", 0)
+    c.set("lone_queries", 1 << 20)
+    assert c.get("lone_after") == 0
+    with c.load_graph(g) as dg:
+        c.stats(reset=True)
+        for sg in (20, 60):
+            _say("lone growth sigma", sg)
+            got = dg.support_batch(pats, [sg] * len(pats), [1.0] * len(pats), fx.MODE_VERDICT)
+            for p, r in zip(pats, got):
+                want = O.query(g, p, sg, 1.0, O.VERDICT)
+                for k in ("tau", "support", "frequent"):
+                    assert r[k] == want[k], (p, k, r[k], want[k])
+        st = c.stats()
+        _say("stats", st)
+        assert st["lone_promotions"] > 0
+    c.close()

@@ -2,8 +2,12 @@
 graphs and the 4M-vertex R-MAT graph, answered as one batch per graph (the
 way the benchmark runs them), against the oracle's answers stored in
 tests/golden/cl100k_expected.json and large_expected.json (written by
-make_large_expected.py, which calls only the oracle).  The embedding count is capped at the stored cap on
-both sides; the digest is compared where the count did not saturate.
+make_large_expected.py, which calls only the oracle).  The embedding count is
+capped at the stored cap on both sides; the digest of the embedding set is
+compared where the count did not saturate, and the digest of the selected set
+S (which fixes S in rank order) always.  large_digest_expected.json holds the
+cases whose count saturated at 10^7 counted again with the cap at 10^9, so
+their embedding-set digest is compared too.
 
 Two launch configurations: with the digest (the count phase enumerates and
 hashes every embedding) and without it (a leaf last vertex is counted in
@@ -72,12 +76,13 @@ def _check(name, expected, no_digest):
         w, got = c["full"], full[i]
         for k in ("tau", "support", "frequent", "embedding_count", "count_saturated"):
             assert got[k] == w[k], (name, i, k, got[k], w[k])
+        assert list(got["sel_digest"]) == w["sel_digest"], (name, i)
         if not no_digest and not w["count_saturated"]:
             assert list(got["digest"]) == w["digest"], (name, i)
         wv, gv = c["verdict"], ver[i]
         for k in ("tau", "support", "frequent"):
             assert gv[k] == wv[k], (name, i, k, gv[k], wv[k])
-    _say(name, "ok", len(cases), "patterns")
+    _say(name, "ok", len(cases), "patterns;", sum(r["exit"] == fx.EXIT_BOUND for r in ver), "bound exits")
 
 
 @pytest.mark.timeout(300)
@@ -96,3 +101,31 @@ def test_cl1m_sampled(torch_cuda, expected, no_digest):
 @pytest.mark.timeout(600)
 def test_rmat22_sampled(torch_cuda, expected):
     _check("rmat22", expected, False)
+
+
+@pytest.mark.timeout(600)
+def test_large_unsaturated_digests(torch_cuda):
+    """The 1M- and 4M-vertex cases whose count saturates at 10^7, counted with
+    the cap at 10^9: count, saturation and (below the cap) the embedding-set
+    digest against the oracle's."""
+    with open(os.path.join(HERE, "golden", "large_digest_expected.json")) as f:
+        exp = json.load(f)
+    for name in ("cl1m", "rmat22"):
+        cases = [r for r in exp["results"] if r["graph"] == name]
+        if not cases:
+            continue
+        g = _graph(name)
+        pats = [Pattern(vlabel=c["pattern"]["vlabel"], edges=[tuple(e) for e in c["pattern"]["edges"]],
+                        elabel=c["pattern"]["elabel"]) for c in cases]
+        with fx.Context(device=0, count_cap=exp["count_cap"]) as ctx:
+            with ctx.load_graph(g) as dg:
+                _say(name, "FULL batch with digest, cap", exp["count_cap"], "patterns", len(pats))
+                got = dg.support_batch(pats, [c["sigma"] for c in cases], [c["lam"] for c in cases], fx.MODE_FULL)
+        for i, c in enumerate(cases):
+            w = c["full"]
+            for k in ("embedding_count", "count_saturated"):
+                assert got[i][k] == w[k], (name, i, k, got[i][k], w[k])
+            if not w["count_saturated"]:
+                assert list(got[i]["digest"]) == w["digest"], (name, i)
+        _say(name, "ok", len(cases), "patterns,", sum(1 for c in cases if not c["full"]["count_saturated"]),
+             "digests compared")

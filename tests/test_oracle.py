@@ -297,3 +297,28 @@ def test_tiny_n_equals_one_and_two():
     k, _ = O.support_stream(g, one)
     assert k == int((g.vlabel == 1).sum())
     assert math.isclose(O.tau(10, 0.5, 1), 10)
+
+
+def test_selection_digest():
+    # the selected set's digest is the embedding digest's hash over S: where
+    # every embedding is selected (a single-vertex pattern, disjoint
+    # embeddings) it equals the digest of M; on the running example it is the
+    # digest of the two selections under the lexicographic order
+    # (Figure 1: (d1, d5, d2) and (d3, d7, d4), 0-based (0, 4, 1) and (2, 6, 3));
+    # on random tiny graphs it is the digest of the brute-force greedy
+    fx1 = load_fixture("running_example.txt")
+    D, P1 = fx1["D"], fx1["P1"]
+    one = Pattern([1], [], [])
+    r = O.query(D, one, 1, 1.0, O.FULL)
+    assert r["support"] == r["embedding_count"] == 3
+    assert r["sel_digest"] == r["digest"]
+    r = O.query(D, P1, 2, 1.0, O.FULL)
+    s1, s2 = 0x243F6A8885A308D3, 0x13198A2E03707344
+    sel = [(0, 4, 1), (2, 6, 3)]
+    want = (sum(O.tuple_hash(e, s1) for e in sel) % (1 << 64), O.tuple_hash(sel[0], s2) ^ O.tuple_hash(sel[1], s2))
+    assert r["sel_digest"] == want
+    assert O.query(D, P1, 2, 1.0, O.VERDICT)["sel_digest"] == (0, 0)
+    for idx, (g, p) in enumerate(_random_cases(60, 77)):
+        greedy = O.brute_greedy(O.brute_embeddings(g, p))
+        got = O.query(g, p, 2, 1.0, O.FULL)["sel_digest"]
+        assert got == O.rows_digest(np.asarray(greedy, dtype=np.int32).reshape(-1, p.n), p.n), idx
