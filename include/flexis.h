@@ -372,6 +372,26 @@ typedef struct {
 fx_status fx_autotune(fx_graph *g, int32_t npat, const fx_pattern *pats, const int64_t *sigma, const double *lambda,
                       int32_t mode, const char *cache_path, fx_tune_result *out);
 
+/* Allocation-free variant of fx_support, for callers that cannot allocate
+ * device memory during a call: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Same arguments and results as
+ * fx_support without the selected list (modes FULL, VERDICT, MNI).  It makes
+ * no device or pinned-host allocation (no hipMalloc, hipFree, hipHostMalloc
+ * or allocating library routine): its device buffers -- per-step scratch, the
+ * query's counters and its slice stack with the used-vertex bitmap -- live in
+ * a static device array of FX_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends; its pinned staging and events are made by fx_ctx_create.  It
+ * runs one query at a time with a stack capacity of 2^14 partial embeddings
+ * per level and 2^22 candidates per device step (results never depend on
+ * either).  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU race.  Errors as fx_support, plus FX_ELIMIT when the query's
+ * stack (about 2^14 * sum over levels l of (4 l + 21) bytes, plus |V| / 8
+ * bytes of used-vertex bitmap, times (1 + n) bitmaps in MNI mode) does not
+ * fit the array. */
+#define FX_NOALLOC_SCRATCH_BYTES (64ull << 20)
+fx_status fx_support_noalloc(fx_graph *g, const fx_pattern *p, int64_t sigma, double lambda, int32_t mode,
+                             fx_result *out);
+
 /* Device and pinned-host allocation calls the library has made so far in
  * this process (a check that a call allocated nothing). */
 uint64_t fx_alloc_calls(void);

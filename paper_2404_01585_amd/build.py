@@ -11,7 +11,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libflexis.so")
-SOURCES = ["fx_api.hip", "fx_graph.hip", "fx_engine.hip", "fx_server.hip", "fx_tune.hip", "fx_kernels.hip"]
+SOURCES = ["fx_api.hip", "fx_graph.hip", "fx_engine.hip", "fx_server.hip", "fx_tune.hip", "fx_kernels.hip",
+           "fx_noalloc.hip"]
 ARCH = os.environ.get("FX_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -151,6 +151,11 @@ extern "C" fx_status fx_ctx_create(const fx_ctx_opts *opts, fx_ctx **out)
     if (o.run_index_bytes != 0) c->run_index_bytes = o.run_index_bytes;
     c->params.timing = (o.flags & FX_CTX_KERNEL_TIMING) != 0;
     c->params.no_digest = (o.flags & FX_CTX_NO_DIGEST) != 0;
+    const fx_status st = fx_noalloc_setup(c);  // the device is current here
+    if (st != FX_OK) {
+        delete c;
+        return st;
+    }
     *out = c;
     return FX_OK;
 }

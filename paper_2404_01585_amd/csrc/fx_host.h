@@ -135,8 +135,20 @@ struct fx_ctx {
     std::atomic<int> graphs{0};
     fx_stats stats{};
     EngineWork work;
+    // the allocation-free entry point's engine buffers: device buffers carved
+    // from the device's static scratch array, pinned host staging and events
+    // made once here (fx_noalloc.hip)
+    std::unique_ptr<EngineWork> na_work;
 };
 
+// Allocation-free support (fx_noalloc.hip).  fx_noalloc_setup runs once per
+// context at creation, with the context's device current: it resolves the
+// device address of that device's scratch array (once per device) and builds
+// ctx->na_work over it.  fx_noalloc_params: the engine parameters the
+// allocation-free path runs with (one query, one lane, a fixed step budget
+// and slice capacity, stacks never moved).
+fx_status fx_noalloc_setup(fx_ctx *c);
+EngineParams fx_noalloc_params(const EngineParams &base);
 
 struct fx_graph {
     fx_ctx *ctx = nullptr;

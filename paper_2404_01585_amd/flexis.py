@@ -39,7 +39,7 @@ _STATUS_NAMES = {0: "FX_OK", -1: "FX_EINVAL", -2: "FX_EGRAPH", -3: "FX_EPATTERN"
 EXPORTS = ["fx_ctx_create", "fx_ctx_destroy", "fx_graph_load", "fx_graph_destroy", "fx_tau", "fx_support",
            "fx_enumerate", "fx_support_batch", "fx_ctx_stats", "fx_ctx_set", "fx_ctx_get", "fx_server_create",
            "fx_server_submit", "fx_server_poll", "fx_server_wait", "fx_server_stats", "fx_server_destroy",
-           "fx_autotune", "fx_alloc_calls", "fx_last_error", "fx_version"]
+           "fx_autotune", "fx_support_noalloc", "fx_alloc_calls", "fx_last_error", "fx_version"]
 
 # fx_result.exit
 EXIT_END = 0
@@ -216,6 +216,8 @@ def load_library():
     lib.fx_ctx_set.argtypes = [P, ctypes.c_char_p, ctypes.c_int64]
     lib.fx_ctx_get.restype = ctypes.c_int32
     lib.fx_ctx_get.argtypes = [P, ctypes.c_char_p, P]
+    lib.fx_support_noalloc.restype = ctypes.c_int32
+    lib.fx_support_noalloc.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P]
     lib.fx_alloc_calls.restype = ctypes.c_uint64
     lib.fx_alloc_calls.argtypes = []
     lib.fx_support_batch.restype = ctypes.c_int32
@@ -360,6 +362,14 @@ class DeviceGraph:
         if selected_cap and mode == MODE_FULL:
             d["selected"] = sel[:min(selected_cap, max(res.support, 0))]
         return d
+
+    def support_noalloc(self, p, sigma: int, lam: float, mode: int = MODE_FULL) -> Dict:
+        """fx_support_noalloc: fx_support without any allocation (static scratch array)."""
+        ph = _PatternHolder.of(p)
+        res = ResultC()
+        _check(load_library().fx_support_noalloc(self._h, ctypes.byref(ph.c), int(sigma), float(lam), int(mode),
+                                                 ctypes.byref(res)))
+        return res.to_dict()
 
     def enumerate(self, p, cap: int) -> Tuple[int, np.ndarray]:
         """fx_enumerate: |M| and the first `cap` embeddings in rank order."""

@@ -60,6 +60,7 @@ def test_null_arguments(lib):
     assert lib.fx_enumerate(None, None, None, 0, None) == fx.FX_EINVAL
     assert lib.fx_ctx_set(None, b"lanes", 1) == fx.FX_EINVAL
     assert lib.fx_ctx_get(None, b"lanes", None) == fx.FX_EINVAL
+    assert lib.fx_support_noalloc(None, None, 1, 0.5, 0, None) == fx.FX_EINVAL
 
 
 def test_result_layout_matches_header(lib):
