@@ -256,6 +256,7 @@ fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, co
  *   steps, syncs, queries   host-side counts.
  *   reoffered   candidates probed in a slice that stopped at its row cap and
  *               offered again in a later step (wasted probe work).
+ *   probed      candidates offered to the probe in all steps.
  *   promotions  stacks moved to a larger slice capacity because few queries
  *               were left to share the device.
  *   host_ms     host time inside the engine's steps, waits excluded.
@@ -264,7 +265,19 @@ fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, co
  *               FX_EXIT_REACHED and FX_EXIT_BOUND (see fx_result.exit).
  *   lone_promotions   of the promotions, those that only the rule for VERDICT
  *               queries left nearly alone allowed (see the lone_* tunables of
- *               fx_ctx_set). */
+ *               fx_ctx_set).
+ *   *_ref_bytes reference algorithmic bytes, counted only with the ref_bytes
+ *               tunable: a per-unit model of what the matching must move, apart
+ *               from this implementation's own extras (4-byte ids, 1-byte
+ *               labels, 8-byte row offsets): per root candidate 20; per expanded
+ *               partial of level l, 4 l + 16 + 6 per neighbour read (the
+ *               anchor's label run: rows are label-sorted); per candidate that
+ *               reaches its adjacency tests, 4 ceil(log2(r + 1)) for each other
+ *               earlier neighbour, r its run length; per row written at level
+ *               l + 1, 4 (l + 1) (scatter); per complete embedding read by the
+ *               greedy and per selection written, 4 n.
+ *   probe_ref_row_bytes   the same model for plain rows: the anchor's whole row
+ *               read and r = its degree. */
 typedef struct {
     uint64_t probe_launches;
     double probe_ms;
@@ -284,6 +297,11 @@ typedef struct {
     uint64_t exits_reached;
     uint64_t exits_bound;
     uint64_t lone_promotions;
+    uint64_t probe_ref_bytes;
+    uint64_t scatter_ref_bytes;
+    uint64_t greedy_ref_bytes;
+    uint64_t probed;
+    uint64_t probe_ref_row_bytes;
 } fx_stats;
 
 /* Copies the context's statistics into *out; reset != 0 zeroes them after. */
@@ -302,6 +320,9 @@ fx_status fx_ctx_stats(fx_ctx *ctx, fx_stats *out, int32_t reset);
  *                     their support-phase stacks
  *   lone_queries      ... once at most this many patterns are open [0, 2^31)
  *   lone_after        ... and the pattern has run this many steps [0, 2^31)
+ *   kernel_timing     0/1: as FX_CTX_KERNEL_TIMING
+ *   ref_bytes         0/1: also count the reference algorithmic bytes of
+ *                     fx_stats (extra loads in the kernels: a counting pass)
  * fx_autotune sets the first six.  Errors: FX_EINVAL for an unknown name or a
  * value out of range (the context is unchanged). */
 fx_status fx_ctx_set(fx_ctx *ctx, const char *key, int64_t value);

@@ -199,6 +199,10 @@ struct FxQuery {
     double rate[FX_MAXN + 1]{};            // passing fraction of each level's last slice
     uint64_t alg_probe_seen = 0;           // probe bytes read back so far
     double alg_probe_credit = 0;           // of those, the share of the candidates taken
+    uint64_t ref_probe_seen = 0;           // the same for the reference bytes (counting pass)
+    double ref_probe_credit = 0;
+    uint64_t ref_row_seen = 0;
+    double ref_row_credit = 0;
     uint64_t probed_support = 0;           // candidates probed in the support phase
     int32_t steps = 0;
     int deep = -1;                         // deepest level with candidates left (-1: none)
@@ -506,6 +510,10 @@ fx_status FxEngine::finish(FxQuery &q, const FxSummary *sums)
     }
     stats_->probe_alg_bytes += (uint64_t)q.alg_probe_credit;
     stats_->scatter_alg_bytes += S.alg_scatter;
+    stats_->probe_ref_bytes += (uint64_t)q.ref_probe_credit;
+    stats_->probe_ref_row_bytes += (uint64_t)q.ref_row_credit;
+    stats_->scatter_ref_bytes += S.ref_scatter;
+    stats_->greedy_ref_bytes += S.ref_greedy;
     stats_->queries++;
     W_->pool.give(q.region, q.region_bytes);
     q.region = nullptr;
@@ -781,6 +789,7 @@ fx_status FxEngine::launch(int g)
         }
         const uint64_t span = std::min<uint64_t>(std::min<uint64_t>(q.T[l] - q.cur[l], want), budget);
         if (span == 0) continue;
+        if (P_.ref_bytes) flags |= FX_PROBE_REF;
         FxSeg &S = segs[nsegs];
         S.in = q.lev[l];
         S.out = q.lev[l + 1];
@@ -877,10 +886,15 @@ fx_status FxEngine::collect(int g, double &waited)
                            q.seg_span);
         q.cur[l] = q.seg_t0 + taken;
         stats_->reoffered += q.seg_span - taken;
+        stats_->probed += q.seg_span;
         if (q.phase == PH_SUPPORT) q.probed_support += q.seg_span;
         q.rate[l] = (double)S.passes / (double)q.seg_span;
         q.alg_probe_credit += (double)(S.alg_probe - q.alg_probe_seen) * (double)taken / (double)q.seg_span;
         q.alg_probe_seen = S.alg_probe;
+        q.ref_probe_credit += (double)(S.ref_probe - q.ref_probe_seen) * (double)taken / (double)q.seg_span;
+        q.ref_probe_seen = S.ref_probe;
+        q.ref_row_credit += (double)(S.ref_probe_row - q.ref_row_seen) * (double)taken / (double)q.seg_span;
+        q.ref_row_seen = S.ref_probe_row;
         q.steps++;
         q.seg_l = -1;
         const uint64_t N = S.total_out;

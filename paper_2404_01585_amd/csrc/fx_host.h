@@ -97,6 +97,7 @@ struct EngineParams {
     int32_t lanes = 2;                     // pipeline lanes (1 to FX_MAX_LANES)
     bool timing = false;
     bool no_digest = false;
+    bool ref_bytes = false;   // count the reference algorithmic bytes (extra loads: a counting pass)
     bool lone_growth = true;  // long VERDICT queries left nearly alone may grow their support stacks
     int32_t promote_after = 16;   // steps a query has run before its stack may grow
     int32_t lone_queries = 2;     // open queries at or below which VERDICT support stacks grow freely

@@ -82,7 +82,13 @@ struct FxSummary {
     unsigned long long ufiltered;   // candidates the used set U has removed so far
     unsigned long long sel_d0;      // sum of the hashes of the selected embeddings (mod 2^64)
     unsigned long long sel_d1;      // xor of their second hashes
-    unsigned long long pad[1];
+    // reference algorithmic bytes (counted only with FX_PROBE_REF): the bytes
+    // the matching must move by a per-unit model (see k_probe, k_scatter,
+    // k_greedy); ref_probe_row is the same model reading whole adjacency rows
+    unsigned long long ref_probe;
+    unsigned long long ref_scatter;
+    unsigned long long ref_greedy;
+    unsigned long long ref_probe_row;
 };
 
 // One level of a slice stack: partial embeddings with l matched vertices
@@ -112,6 +118,7 @@ enum : int32_t {
     FX_PROBE_HASH = 8,      // with FX_PROBE_COUNT: also hash every counted embedding
     FX_PROBE_IMAGES = 16,   // with FX_PROBE_COUNT: mark every counted embedding's images
     FX_PROBE_SYM = 32,      // apply the plan's symmetry-breaking constraints (support phase)
+    FX_PROBE_REF = 64,      // also count the reference algorithmic bytes (a counting pass: extra loads)
 };
 
 struct FxSeg {

@@ -277,6 +277,68 @@ __device__ __forceinline__ bool touches_used(const uint32_t *__restrict__ U, con
     return false;
 }
 
+// Reference algorithmic bytes (the counting pass only).  A per-unit model of
+// what the matching itself must move, apart from this implementation's own
+// extras (pass flags, run descriptors, used-set words, binary-search probes of
+// the run index): 4-byte ids, 1-byte labels, 8-byte row offsets.
+//   root candidate (label bucket)      4 (id) + 16 (its two row offsets)
+//   partial expanded at level l        4 l (its row) + 16 (anchor's offsets)
+//                                      + 6 per neighbour read (id, edge label,
+//                                      neighbour label)
+//   candidate tested against an earlier
+//   neighbour b other than the anchor  4 ceil(log2(r + 1)) (a binary search
+//                                      over r entries)
+//   row written at level l + 1         4 (l + 1)
+//   greedy                             4 n per complete embedding read and
+//                                      4 n per selected embedding written
+// With label-sorted rows the neighbours read are the anchor's run of the
+// vertex's (label, edge label) and r is the length of b's run (ref_probe);
+// with plain rows they are the anchor's whole row and r = deg(f(b))
+// (ref_probe_row, the same model for a layout without label-sorted rows).
+__device__ __forceinline__ uint32_t bit_length(uint64_t d) { return d ? 64u - (uint32_t)__clzll(d) : 0u; }
+
+__device__ __forceinline__ uint64_t degree(const FxGraphDev &g, int32_t u)
+{
+    return (uint64_t)(g.rowp[u + 1] - g.rowp[u]);
+}
+
+template <int W>
+__device__ __forceinline__ void ref_back_edges(const FxGraphDev &g, const FxPlan *__restrict__ plan, int32_t l,
+                                               const Cand<W> &x, unsigned long long &run_b, unsigned long long &row_b)
+{
+    const int32_t nb = plan->nback[l];
+    const uint32_t vl = plan->vl[l];
+    for (int kk = 0; kk < nb; kk++) {
+        const int32_t a = plan->back[l][kk];
+        if (a == x.anc) continue;
+        const int32_t u = pick(x.v, a);
+        int64_t lo;
+        int32_t len;
+        uint32_t ignored = 0;
+        run_of<scan_width<W>()>(g, u, run_key(vl, plan->bel[l][kk]), lo, len, ignored);
+        run_b += 4u * bit_length((uint64_t)len);
+        row_b += 4u * bit_length(degree(g, u));
+    }
+}
+
+// Injectivity and the symmetry-breaking order alone (the tests before any
+// adjacency probe).
+template <int W>
+__device__ __forceinline__ bool distinct_and_ordered(const FxPlan *__restrict__ plan, int32_t l, bool sym,
+                                                     const Cand<W> &x)
+{
+#pragma unroll
+    for (int k = 0; k < W; k++)
+        if (k < l && x.v[k] == x.c) return false;
+    if (sym) {
+        const uint32_t lt = plan->sym_lt[l];
+#pragma unroll
+        for (int k = 0; k < W; k++)
+            if (k < l && ((lt >> k) & 1u) && x.v[k] >= x.c) return false;
+    }
+    return true;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
     const uint32_t lane = __lane_id();
@@ -410,8 +472,10 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     const bool hash = (flags & FX_PROBE_HASH) != 0;
     const bool images = (flags & FX_PROBE_IMAGES) != 0;
     const bool sym = (flags & FX_PROBE_SYM) != 0;
+    const bool ref = (flags & FX_PROBE_REF) != 0;
     uint32_t passed = 0, uout = 0;
     unsigned long long cnt = 0;
+    unsigned long long rbytes = 0, dbytes = 0;  // reference algorithmic bytes (counting pass): run, row model
     uint64_t h1 = 0, h2 = 0;
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) {
@@ -425,6 +489,18 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
             // candidate entry + flag; the partial row and its run descriptor once
             bytes += (x.anc >= 0 ? 8u : 4u) + 1u;
             if (x.first || tl == tile0) bytes += 4u * (uint32_t)l + 21u;
+            if (ref) {
+                const unsigned long long own = x.first ? 4u * (uint32_t)l : 0u;  // the partial's row, once
+                rbytes += own;
+                dbytes += own;
+                if (x.anc < 0) {  // a label-bucket candidate and its offsets
+                    rbytes += 20u;
+                    dbytes += 20u;
+                } else if (x.first) {  // the anchor's run, or its whole row
+                    rbytes += 16u + 6u * (unsigned long long)S.in.len[p];
+                    dbytes += 16u + 6u * degree(g, pick(x.v, x.anc));
+                }
+            }
             bool ok = true;
             if (ufilter) {
                 if (pdead) {
@@ -436,7 +512,18 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
                 }
                 uout += ok ? 0u : 1u;
             }
+            if (ref && ok && distinct_and_ordered(S.plan, l, sym, x)) ref_back_edges(g, S.plan, l, x, rbytes, dbytes);
             if (ok) ok = feasible(g, S.plan, n, l, sym, x, bytes);
+            if (ref && ok && leaf) {  // the last vertex's expansion, counted in closed form here
+                const int32_t a = S.plan->back[l + 1][0];
+                const int32_t u = a == l ? x.c : pick(x.v, a);
+                int64_t lo;
+                int32_t len;
+                uint32_t ignored = 0;
+                run_of<scan_width<W>()>(g, u, run_key(S.plan->vl[l + 1], S.plan->bel[l + 1][0]), lo, len, ignored);
+                rbytes += 4u * (uint32_t)(l + 1) + 16u + 6u * (unsigned long long)len;
+                dbytes += 4u * (uint32_t)(l + 1) + 16u + 6u * degree(g, u);
+            }
             if (ok) {
                 if (count) {
                     cnt++;
@@ -484,6 +571,16 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
             if (uo) atomicAdd(&S.sum->ufiltered, (unsigned long long)uo);
             wcnt[threadIdx.x >> 6] = pc;
         }
+    }
+    if (ref) {  // uniform across the workgroup
+        unsigned long long r = rbytes, d = dbytes;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            r += __shfl_xor(r, o);
+            d += __shfl_xor(d, o);
+        }
+        if (__lane_id() == 0 && r) atomicAdd(&S.sum->ref_probe, r);
+        if (__lane_id() == 0 && d) atomicAdd(&S.sum->ref_probe_row, d);
     }
     __syncthreads();
     if (threadIdx.x == 0) bcnt[blockIdx.x] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
@@ -675,6 +772,14 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) b += __shfl_xor(b, o);
     if (__lane_id() == 0 && b) atomicAdd(&S.sum->alg_scatter, b);
+    if (S.flags & FX_PROBE_REF) {  // reference bytes: the rows written, 4 (l + 1) each
+        unsigned long long r = 0;
+#pragma unroll
+        for (int it = 0; it < ITEMS; it++) r += f[it] ? 4u * (uint32_t)w1 : 0u;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) r += __shfl_xor(r, o);
+        if (__lane_id() == 0 && r) atomicAdd(&S.sum->ref_scatter, r);
+    }
 }
 
 // Adds each workgroup's offset (scan of lsum within its segment) to the
@@ -799,6 +904,7 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
     const uint32_t B = FX_GREEDY_VN / (uint32_t)n;  // embeddings per chunk
     constexpr uint32_t kTailBelow = 64;              // undecided embeddings one wave finishes
     uint32_t rounds_total = 0;
+    unsigned long long selected_total = 0;           // (thread 0) selections of this launch
     for (uint64_t c0 = 0; c0 < N; c0 += B) {
         const uint32_t nb = (uint32_t)((N - c0) < B ? (N - c0) : B);
         // a table of at least twice the chunk's vertices (at least 64 slots):
@@ -920,6 +1026,7 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
         if (threadIdx.x == 0) {
             const unsigned long long c = nsel;
             sel_base = c ? atomicAdd(&S.sum->support, c) : 0ULL;
+            selected_total += c;
         }
         if (S.sel_rows) {  // selections are kept only when the caller asked for them
             __syncthreads();
@@ -936,7 +1043,11 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(&S.sum->rounds, (unsigned long long)rounds_total);
+    if (threadIdx.x == 0) {
+        atomicAdd(&S.sum->rounds, (unsigned long long)rounds_total);
+        if (S.flags & FX_PROBE_REF)  // reference bytes: every embedding read once, the selections written
+            atomicAdd(&S.sum->ref_greedy, 4ull * (unsigned long long)n * (N + selected_total));
+    }
 }
 
 // Admission / phase start of queries: level 0 is the single empty partial
@@ -1015,7 +1126,8 @@ hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int
 template <int ITEMS, int W>
 hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
                              int32_t nsegs, uint32_t nblocks, FxTile *tmap, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
-                             uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin, hipEvent_t probe_end,
+                             uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
+                             hipEvent_t probe_end,
                              hipEvent_t scatter_begin, hipEvent_t scatter_end, hipEvent_t greedy_begin,
                              hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
 {
@@ -1042,7 +1154,7 @@ hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *se
 template <int W>
 hipError_t launch_step_width(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
                              int32_t nsegs, uint32_t nblocks, int32_t items, FxTile *tmap, uint8_t *flag,
-                             uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
+                             uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff,  hipEvent_t probe_begin,
                              hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
                              hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
 {

@@ -98,7 +98,9 @@ class StatsC(ctypes.Structure):
                 ("syncs", ctypes.c_uint64), ("queries", ctypes.c_uint64), ("reoffered", ctypes.c_uint64),
                 ("promotions", ctypes.c_uint64), ("host_ms", ctypes.c_double), ("wait_ms", ctypes.c_double),
                 ("exits_reached", ctypes.c_uint64), ("exits_bound", ctypes.c_uint64),
-                ("lone_promotions", ctypes.c_uint64)]
+                ("lone_promotions", ctypes.c_uint64), ("probe_ref_bytes", ctypes.c_uint64),
+                ("scatter_ref_bytes", ctypes.c_uint64), ("greedy_ref_bytes", ctypes.c_uint64),
+                ("probed", ctypes.c_uint64), ("probe_ref_row_bytes", ctypes.c_uint64)]
 
     def to_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -25,6 +25,7 @@ device path and the oracle.
 
 from __future__ import annotations
 
+import functools
 import itertools
 from collections import deque
 from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
@@ -47,6 +48,13 @@ def _adj(n: int, edges: Sequence[Tuple[int, int]], elabel: Sequence[int]):
 def canonical_key(p: Pattern) -> Tuple[Key, List[int]]:
     """Smallest (labels, sorted edge list) encoding over invariant-respecting
     vertex orders, and the order (old ids in canonical position order)."""
+    key, perm = _canonical_key(tuple(p.vlabel), tuple(tuple(e) for e in p.edges), tuple(p.elabel))
+    return key, list(perm)
+
+
+@functools.lru_cache(maxsize=1 << 20)
+def _canonical_key(vlabel, edges, elabel):
+    p = Pattern(vlabel=list(vlabel), edges=[tuple(e) for e in edges], elabel=list(elabel))
     n = p.n
     adj = _adj(n, p.edges, p.elabel)
     inv = [(p.vlabel[v], len(adj[v]), tuple(sorted((p.vlabel[u], l) for u, l in adj[v].items()))) for v in range(n)]
@@ -67,7 +75,7 @@ def canonical_key(p: Pattern) -> Tuple[Key, List[int]]:
         key = (labels, es)
         if best is None or key < best:
             best, best_perm = key, perm
-    return best, best_perm
+    return best, tuple(best_perm)
 
 
 def from_key(key: Key) -> Pattern:
@@ -163,12 +171,15 @@ SupportFn = Callable[[List[Pattern], int, float], List[Dict]]
 
 
 def mine(g: Graph, sigma: int, lam: float, max_edges: int, evaluate: SupportFn,
-         max_vertices: int = 16, max_candidates: Optional[int] = None, tau_fn=None) -> Dict:
+         max_vertices: int = 16, max_candidates: Optional[int] = None, tau_fn=None,
+         types: Optional[List[Tuple[int, int, int]]] = None) -> Dict:
     """Runs the level-wise loop.  ``evaluate(patterns, sigma, lam)`` returns one
     result dict per pattern with at least 'frequent'.  Returns the candidate
-    lists and results of every level."""
+    lists and results of every level.  ``types``: the graph's edge types
+    (``edge_types(g)``), when the caller already has them."""
     nv = g.num_vertices
-    types = edge_types(g)
+    if types is None:
+        types = edge_types(g)
     level_cands: List[List[Pattern]] = []
     level_res: List[List[Dict]] = []
     cands = [from_key(canonical_key(Pattern([a, b], [(0, 1)], [e]))[0]) for a, b, e in types]
