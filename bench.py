@@ -111,7 +111,9 @@ def build_candidates(dg, g, spec, lam, types=None):
 
         res = generate.mine_by_vertices(g, spec["sigma"], lam, spec["vertices"], evaluate, fx.tau)
     else:
-        res = mining.mine(g, spec["sigma"], lam, spec["levels"], evaluate, tau_fn=fx.tau, types=types)
+        # the last level's candidates are the batch itself: generated, not evaluated here
+        res = mining.mine(g, spec["sigma"], lam, spec["levels"], evaluate, tau_fn=fx.tau, types=types,
+                          evaluate_last=False)
     cands = [p for lvl in res["levels"] for p in lvl]
     return cands, [len(l) for l in res["levels"]]
 
@@ -454,10 +456,24 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="calibration only: copy a buffer of this many bytes 5 times with torch and exit "
                          "(a plain copy kernel of known size for the PMC traffic factors)")
+    ap.add_argument("--gather-count", type=int, default=0,
+                    help="calibration only: gather this many random 8-byte words from a 4 GiB table 5 times "
+                         "with torch and exit (random reads of known count for the PMC traffic factors)")
     args = ap.parse_args()
 
     if args.serve:
         serve_sweep(args)
+        return
+
+    if args.gather_count > 0:
+        import torch
+        table = torch.zeros(1 << 29, dtype=torch.int64, device="cuda")  # 4 GiB
+        idx = torch.randint(0, 1 << 29, (args.gather_count,), generator=torch.Generator().manual_seed(1)).cuda()
+        out = torch.empty(args.gather_count, dtype=torch.int64, device="cuda")
+        for _ in range(5):
+            torch.index_select(table, 0, idx, out=out)
+        torch.cuda.synchronize()
+        log(f"[bench] gathered {args.gather_count} random words 5 times")
         return
 
     if args.copy_bytes > 0:

@@ -277,7 +277,11 @@ fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, co
  *               l + 1, 4 (l + 1) (scatter); per complete embedding read by the
  *               greedy and per selection written, 4 n.
  *   probe_ref_row_bytes   the same model for plain rows: the anchor's whole row
- *               read and r = its degree. */
+ *               read and r = its degree.
+ *   chains, chain_steps   device-scheduled chains run (one host
+ *               synchronisation each) and the steps they ran (see the
+ *               chain_* tunables of fx_ctx_set); steps, syncs and the launch
+ *               counts include them. */
 typedef struct {
     uint64_t probe_launches;
     double probe_ms;
@@ -302,6 +306,8 @@ typedef struct {
     uint64_t greedy_ref_bytes;
     uint64_t probed;
     uint64_t probe_ref_row_bytes;
+    uint64_t chains;
+    uint64_t chain_steps;
 } fx_stats;
 
 /* Copies the context's statistics into *out; reset != 0 zeroes them after. */
@@ -320,7 +326,13 @@ fx_status fx_ctx_stats(fx_ctx *ctx, fx_stats *out, int32_t reset);
  *                     their support-phase stacks
  *   lone_queries      ... once at most this many patterns are open [0, 2^31)
  *   lone_after        ... and the pattern has run this many steps [0, 2^31)
- *   kernel_timing     0/1: as FX_CTX_KERNEL_TIMING
+ *   chain_queries     once no pattern waits and at most this many are in
+ *                     flight, their steps are scheduled on the device: a chain
+ *                     of chain_steps steps, captured once in a HIP graph, runs
+ *                     with one host synchronisation [0 (never), 64]
+ *   chain_steps       steps per chain [1, 256]
+ *   kernel_timing     0/1: as FX_CTX_KERNEL_TIMING (per-kernel timing needs the
+ *                     host-scheduled steps: no chains while it is on)
  *   ref_bytes         0/1: also count the reference algorithmic bytes of
  *                     fx_stats (extra loads in the kernels: a counting pass)
  * fx_autotune sets the first six.  Errors: FX_EINVAL for an unknown name or a

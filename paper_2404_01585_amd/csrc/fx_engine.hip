@@ -158,8 +158,8 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
 
 namespace {
 
-constexpr uint64_t kCountSpan = 1ull << 22;  // least last-vertex candidates per counting step
-constexpr double kFill = 0.8;                // aim a slice at this fraction of the rows it may write
+constexpr uint64_t kCountSpan = FX_COUNT_SPAN;  // least last-vertex candidates per counting step
+constexpr double kFill = FX_FILL;                // aim a slice at this fraction of the rows it may write
 constexpr int64_t kPromoteCap = 1 << 23;     // largest slice capacity a stack is moved to
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -208,6 +208,8 @@ struct FxQuery {
     int deep = -1;                         // deepest level with candidates left (-1: none)
     int lane = 0;
     int exit = FX_EXIT_END;                // how the query ended (fx_result.exit)
+    uint64_t last_ufiltered = 0;           // candidates U has removed, as of the last step read back
+    bool chain_done = false;               // finished in a device-scheduled chain
     int64_t listed = 0;
     // the segment of the current step (-1: none)
     int seg_l = -1, seg_kind = 0;
@@ -326,6 +328,20 @@ EngineWork::~EngineWork()
             (void)hipStreamSynchronize(st);
             (void)hipStreamDestroy(st);
         }
+    drop_chain_graph();
+    if (chain_stream) {
+        (void)hipStreamSynchronize(chain_stream);
+        (void)hipStreamDestroy(chain_stream);
+    }
+}
+
+void EngineWork::drop_chain_graph()
+{
+    if (chain_exec) (void)hipGraphExecDestroy(chain_exec);
+    if (chain_graph) (void)hipGraphDestroy(chain_graph);
+    chain_exec = nullptr;
+    chain_graph = nullptr;
+    chain_key = ChainGraphKey{};
 }
 
 fx_status EngineWork::init_events()
@@ -338,6 +354,7 @@ fx_status EngineWork::init_events()
     if (!start_ev) FX_HIP(hipEventCreateWithFlags(&start_ev, hipEventDisableTiming));
     for (auto &st : own_stream)
         if (!st) FX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    if (!chain_stream) FX_HIP(hipStreamCreateWithFlags(&chain_stream, hipStreamNonBlocking));
     return FX_OK;
 }
 
@@ -447,10 +464,9 @@ void FxEngine::enqueue(std::unique_ptr<FxQuery> q)
     pending_.push_back(std::move(q));
 }
 
-fx_status FxEngine::finish(FxQuery &q, const FxSummary *sums)
+fx_status FxEngine::finish(FxQuery &q, const FxSummary &S)
 {
     FxRequest &r = *q.req;
-    const FxSummary &S = sums[q.slot];
     if (q.phase == PH_LIST) {
         *r.list_count = q.listed;  // rows written at the last level (a capped slice re-offers the rest)
     } else {
@@ -681,11 +697,49 @@ fx_status FxEngine::step()
         }
         buffers_ready_ = true;
     }
+    if (chain_ready()) return chain_step(waited);
     const int g = lane_;
     lane_ = (lane_ + 1) % P_.lanes;
     if (in_flight_[g]) FX_TRY(collect(g, waited));
     FX_TRY(admit(g));
     if (!active_[g].empty()) FX_TRY(launch(g));
+    return FX_OK;
+}
+
+// Moves the stacks of long-running queries that now have the device nearly
+// to themselves to a larger capacity (room for slices of their share of a
+// step).  In the support phase the slice size is also the granularity at
+// which selections prune the search through U: larger slices expand partials
+// that a selection would have removed (measured: twice the probe work on
+// cl1m).  A support-phase stack grows only while U has removed under 1/64 of
+// its candidates -- or, for a VERDICT query that has run lone_after steps,
+// once at most lone_queries queries are left: then the device is idle between
+// their small steps, and fewer, larger steps finish sooner despite the extra
+// expansion (cl1m: half the steps, 40% more patterns/s).  FULL queries keep
+// the rule: their batch tail also holds other queries' counting, and the
+// extra expansion cost 10% there; short queries keep it too (a single VERDICT
+// call grew from the start and ran 3x slower).
+fx_status FxEngine::grow_stacks(std::vector<FxQuery *> &qs, uint64_t n_open)
+{
+    const uint64_t share = P_.step_candidates / std::max<uint64_t>(n_open, 1);
+    const bool lone = P_.lone_growth && n_open <= (uint64_t)std::max<int32_t>(P_.lone_queries, 0);
+    for (FxQuery *qp : qs) {
+        FxQuery &q = *qp;
+        const bool free_growth = lone && q.req->kind == FX_Q_VERDICT && q.steps >= P_.lone_after;
+        const bool u_ok = q.phase != PH_SUPPORT || (q.probed_support > 0 && q.last_ufiltered * 64 <= q.probed_support);
+        if (!free_growth && !u_ok) continue;
+        if (q.steps < P_.promote_after || q.cap >= kPromoteCap || share < 4 * (uint64_t)q.cap) continue;
+        if (q.deep < 0) continue;
+        uint64_t left = 0;  // largest candidate range still open: no slice needs more rows
+        for (int l = 0; l < q.n; l++) left = std::max<uint64_t>(left, q.T[l] - q.cur[l]);
+        int64_t nc = q.cap;
+        while (nc < kPromoteCap && (uint64_t)nc * 2 <= share && (uint64_t)nc < left) nc *= 2;
+        if (nc > q.cap) {
+            const uint64_t before = stats_->promotions;
+            FX_TRY(promote(q, nc));
+            if (!u_ok && stats_->promotions > before) stats_->lone_promotions++;  // only the lone rule allowed it
+        }
+    }
     return FX_OK;
 }
 
@@ -702,7 +756,6 @@ fx_status FxEngine::launch(int g)
     uint32_t *blk0 = L.stage_h.as<uint32_t>();
     FxSeg *segs = (FxSeg *)((char *)L.stage_h.p + seg_off);
     FxSummary *sums_d = W_->sums_d.as<FxSummary>();
-    const FxSummary *sums_prev = L.sums_h.as<FxSummary>();
     int nsegs = 0;
     uint64_t budget = P_.step_candidates;
     uint32_t nblocks = 0;
@@ -721,37 +774,10 @@ fx_status FxEngine::launch(int g)
     // than its level holds rows when few of them pass (the row cap bounds
     // what is written, see k_scatter)
     const uint64_t share = P_.step_candidates / std::max<uint64_t>(n_open, 1);
-    // long-running queries that now have the device nearly to themselves get
-    // room for slices of their share.  In the support phase the slice size is
-    // also the granularity at which selections prune the search through U:
-    // larger slices expand partials that a selection would have removed
-    // (measured: twice the probe work on cl1m).  A support-phase stack grows
-    // only while U has removed under 1/64 of its candidates -- or, for a
-    // VERDICT query that has run lone_after steps, once at most lone_queries
-    // queries are left: then the device is idle between their small steps,
-    // and fewer, larger steps finish sooner despite the extra expansion (cl1m:
-    // half the steps, 40% more patterns/s).  FULL queries keep the rule: their
-    // batch tail also holds other queries' counting, and the extra expansion
-    // cost 10% there; short queries keep it too (a single VERDICT call grew
-    // from the start and ran 3x slower).
-    const bool lone = P_.lone_growth && n_open <= (uint64_t)std::max<int32_t>(P_.lone_queries, 0);
-    for (auto &qp : act) {
-        FxQuery &q = *qp;
-        const bool free_growth = lone && q.req->kind == FX_Q_VERDICT && q.steps >= P_.lone_after;
-        const bool u_ok = q.phase != PH_SUPPORT ||
-                          (q.probed_support > 0 && sums_prev[q.slot].ufiltered * 64 <= q.probed_support);
-        if (!free_growth && !u_ok) continue;
-        if (q.steps < P_.promote_after || q.cap >= kPromoteCap || share < 4 * (uint64_t)q.cap) continue;
-        if (q.deep < 0) continue;
-        uint64_t left = 0;  // largest candidate range still open: no slice needs more rows
-        for (int l = 0; l < q.n; l++) left = std::max<uint64_t>(left, q.T[l] - q.cur[l]);
-        int64_t nc = q.cap;
-        while (nc < kPromoteCap && (uint64_t)nc * 2 <= share && (uint64_t)nc < left) nc *= 2;
-        if (nc > q.cap) {
-            const uint64_t before = stats_->promotions;
-            FX_TRY(promote(q, nc));
-            if (!u_ok && stats_->promotions > before) stats_->lone_promotions++;  // only the lone rule allowed it
-        }
+    {
+        std::vector<FxQuery *> qs;
+        for (auto &qp : act) qs.push_back(qp.get());
+        FX_TRY(grow_stacks(qs, n_open));
     }
     for (size_t k = 0; k < A && budget > 0; k++) {
         FxQuery &q = *act[(rot_[g] + k) % A];
@@ -889,6 +915,7 @@ fx_status FxEngine::collect(int g, double &waited)
         stats_->probed += q.seg_span;
         if (q.phase == PH_SUPPORT) q.probed_support += q.seg_span;
         q.rate[l] = (double)S.passes / (double)q.seg_span;
+        q.last_ufiltered = S.ufiltered;
         q.alg_probe_credit += (double)(S.alg_probe - q.alg_probe_seen) * (double)taken / (double)q.seg_span;
         q.alg_probe_seen = S.alg_probe;
         q.ref_probe_credit += (double)(S.ref_probe - q.ref_probe_seen) * (double)taken / (double)q.seg_span;
@@ -954,13 +981,231 @@ fx_status FxEngine::collect(int g, double &waited)
             }
         }
         if (fin) {
-            FX_TRY(finish(q, sums_h));
+            FX_TRY(finish(q, sums_h[q.slot]));
             act[k] = std::move(act.back());
             act.pop_back();
         } else {
             k++;
         }
     }
+    return FX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device-scheduled chains
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kChainCtlBytes = 256;
+
+size_t chain_layout(int32_t max_q, size_t *cq_off, size_t *blk0_off, size_t *segs_off)
+{
+    *cq_off = kChainCtlBytes;
+    *blk0_off = align256(*cq_off + (size_t)max_q * sizeof(FxChainQuery));
+    *segs_off = align256(*blk0_off + ((size_t)max_q + 1) * 4);
+    return align256(*segs_off + (size_t)max_q * sizeof(FxSeg));
+}
+
+}  // namespace
+
+// Chains run once no query waits for admission, at most chain_queries are in
+// flight, and no query lists its embeddings (a listing copies rows out every
+// step).  Per-kernel timing needs the host-scheduled steps.
+bool FxEngine::chain_ready() const
+{
+    if (P_.chain_queries <= 0 || P_.chain_steps <= 0 || P_.timing || !pending_.empty()) return false;
+    size_t total = 0;
+    for (int g = 0; g < P_.lanes; g++) {
+        total += active_[g].size();
+        for (const auto &q : active_[g])
+            if (q->phase == PH_LIST) return false;
+    }
+    return total > 0 && total <= (size_t)P_.chain_queries;
+}
+
+// One chain: every lane's step in flight is collected, the open queries'
+// state goes to the device, the captured chain of chain_steps steps runs
+// (its scheduler kernel advances, retires and schedules the queries between
+// steps), and the state comes back: finished queries are retired here, the
+// others continue in the next chain or in host-scheduled steps.
+fx_status FxEngine::chain_step(double &waited)
+{
+    for (int g = 0; g < P_.lanes; g++)
+        if (in_flight_[g]) FX_TRY(collect(g, waited));
+    std::vector<FxQuery *> qs;
+    uint64_t n_open = 0;
+    int maxn = 1;
+    for (int g = 0; g < P_.lanes; g++)
+        for (auto &qp : active_[g]) {
+            qs.push_back(qp.get());
+            n_open += qp->deep >= 0;
+            maxn = std::max(maxn, qp->n);
+        }
+    if (qs.empty()) return FX_OK;
+    FX_TRY(grow_stacks(qs, n_open));
+    const int32_t max_q = P_.chain_queries;
+    size_t cq_off, blk0_off, segs_off;
+    const size_t bytes = chain_layout(max_q, &cq_off, &blk0_off, &segs_off);
+    FX_TRY(W_->chain_d.ensure(bytes));
+    FX_TRY(W_->chain_h.ensure(bytes));
+    char *hb = (char *)W_->chain_h.p;
+    char *db = (char *)W_->chain_d.p;
+    FxChainCtl *ctl_h = (FxChainCtl *)hb;
+    FxChainQuery *cq_h = (FxChainQuery *)(hb + cq_off);
+    memset(ctl_h, 0, sizeof(FxChainCtl));
+    ctl_h->nq = (int32_t)qs.size();
+    ctl_h->budget = P_.step_candidates;
+    FxSummary *sums_d = W_->sums_d.as<FxSummary>();
+    const uint64_t words = ((uint64_t)G_->nv + 31) / 32;
+    for (size_t i = 0; i < qs.size(); i++) {
+        FxQuery &q = *qs[i];
+        FxChainQuery &c = cq_h[i];
+        memset(&c, 0, sizeof(c));
+        for (int l = 0; l <= q.n; l++) c.lev[l] = q.lev[l];
+        c.plan = q.plan;
+        c.U = q.U;
+        c.sum = sums_d + q.slot;
+        c.sel_rows = q.sel_rows;
+        c.sel_rank = q.sel_rank;
+        c.img = q.img;
+        c.img_words = words;
+        c.cap = q.cap;
+        c.tau_eff = q.tau_eff;
+        c.upper_bound = q.hp.upper_bound;
+        c.count_cap = P_.count_cap;
+        c.bucket0 = (uint64_t)(G_->bptr[q.hp.plan.vl[0] + 1] - G_->bptr[q.hp.plan.vl[0]]);
+        c.last_span = q.last_span;
+        c.n = q.n;
+        c.verdict = q.req->kind == FX_Q_VERDICT;
+        c.mni = q.req->kind == FX_Q_MNI;
+        c.full = q.req->kind == FX_Q_FULL;
+        c.sym = q.hp.symmetric;
+        c.leaf_count = P_.no_digest && !c.mni && q.n >= 2 && q.hp.plan.nback[q.n - 1] == 1;
+        c.hash = !P_.no_digest;
+        c.ref_bytes = P_.ref_bytes;
+        c.phase = q.phase == PH_SUPPORT ? FX_CQ_SUPPORT : FX_CQ_COUNT;
+        c.deep = q.deep;
+        c.exit = q.exit;
+        c.steps = q.steps;
+        for (int l = 0; l <= FX_MAXN; l++) {
+            c.T[l] = q.T[l];
+            c.cur[l] = q.cur[l];
+            c.nparts[l] = q.nparts[l];
+            c.rate[l] = q.rate[l];
+        }
+        c.rank_base = q.rank_base;
+        c.probed_support = q.probed_support;
+        c.alg_probe_seen = q.alg_probe_seen;
+        c.alg_probe_credit = q.alg_probe_credit;
+        c.ref_probe_seen = q.ref_probe_seen;
+        c.ref_probe_credit = q.ref_probe_credit;
+        c.ref_row_seen = q.ref_row_seen;
+        c.ref_row_credit = q.ref_row_credit;
+        c.seg_l = -1;
+    }
+    // the chain runs on its own stream, after everything queued on the lanes
+    hipStream_t cs = W_->chain_stream;
+    for (int g = 0; g < P_.lanes; g++) {
+        FX_HIP(hipEventRecord(W_->lane[g].done, ls_[g]));
+        FX_HIP(hipStreamWaitEvent(cs, W_->lane[g].done, 0));
+    }
+    EngineLane &L = W_->lane[0];
+    ChainGraphKey key{};
+    key.graph = G_;
+    key.dev = G_->dev;
+    key.items = P_.items;
+    key.width = maxn <= 4 ? 4 : (maxn <= 8 ? 8 : FX_MAXN);
+    key.steps = P_.chain_steps;
+    key.max_q = max_q;
+    const void *bufs[8] = {hb, db, L.tmap.p, L.flag.p, L.bcnt.p, L.boff.p, L.lsum.p, L.loff.p};
+    memcpy(key.bufs, bufs, sizeof(bufs));
+    key.bytes = bytes;
+    if (!W_->chain_exec || !(W_->chain_key == key)) {
+        W_->drop_chain_graph();
+        FX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipMemcpyAsync(db, hb, bytes, hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess)
+            e = fx_launch_chain(cs, G_->dev, (FxChainQuery *)(db + cq_off), (FxChainCtl *)db, max_q, P_.chain_steps,
+                                (FxSeg *)(db + segs_off), (uint32_t *)(db + blk0_off), P_.items, key.width,
+                                L.tmap.as<FxTile>(), L.flag.as<uint8_t>(), L.bcnt.as<uint32_t>(),
+                                L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>());
+        if (e == hipSuccess) e = hipMemcpyAsync(hb, db, bytes, hipMemcpyDeviceToHost, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fx_fail(FX_EDEVICE, "capturing the device-scheduled chain failed: %s",
+                           hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        W_->chain_graph = graph;
+        FX_HIP(hipGraphInstantiate(&W_->chain_exec, graph, nullptr, nullptr, 0));
+        W_->chain_key = key;
+    }
+    FX_HIP(hipGraphLaunch(W_->chain_exec, cs));
+    {
+        const auto w0 = std::chrono::steady_clock::now();
+        FX_HIP(hipStreamSynchronize(cs));
+        waited += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+    }
+    // stack regions freed by promotions: the chain has run past them
+    for (int g = 0; g < FX_MAX_LANES; g++) {
+        for (auto &r : deferred_[g]) W_->pool.give(r.first, r.second);
+        deferred_[g].clear();
+    }
+    const uint32_t ran = ctl_h->steps;
+    stats_->chains++;
+    stats_->chain_steps += ran;
+    stats_->steps += ran;
+    stats_->syncs++;
+    stats_->probe_launches += ran;
+    stats_->scatter_launches += ran;
+    stats_->greedy_launches += ran;
+    bool any_done = false;
+    for (size_t i = 0; i < qs.size(); i++) {
+        FxQuery &q = *qs[i];
+        const FxChainQuery &c = cq_h[i];
+        if (c.error) return fx_fail(FX_EDEVICE, "device consistency check failed in a device-scheduled step");
+        for (int l = 0; l <= FX_MAXN; l++) {
+            q.T[l] = c.T[l];
+            q.cur[l] = c.cur[l];
+            q.nparts[l] = c.nparts[l];
+            q.rate[l] = c.rate[l];
+        }
+        q.phase = c.phase == FX_CQ_SUPPORT ? PH_SUPPORT : PH_COUNT;
+        q.deep = c.deep;
+        q.exit = c.exit;
+        q.steps = c.steps;
+        q.rank_base = c.rank_base;
+        q.probed_support = c.probed_support;
+        q.alg_probe_seen = c.alg_probe_seen;
+        q.alg_probe_credit = c.alg_probe_credit;
+        q.ref_probe_seen = c.ref_probe_seen;
+        q.ref_probe_credit = c.ref_probe_credit;
+        q.ref_row_seen = c.ref_row_seen;
+        q.ref_row_credit = c.ref_row_credit;
+        q.last_ufiltered = c.last.ufiltered;
+        q.seg_l = -1;
+        stats_->reoffered += c.reoffered;
+        stats_->probed += c.probed;
+        if (c.done) {
+            FX_TRY(finish(q, c.last));
+            q.chain_done = true;
+            any_done = true;
+        }
+    }
+    if (any_done)
+        for (int g = 0; g < FX_MAX_LANES; g++) {
+            auto &act = active_[g];
+            for (size_t k = 0; k < act.size();) {
+                if (act[k]->chain_done) {
+                    act[k] = std::move(act.back());
+                    act.pop_back();
+                } else {
+                    k++;
+                }
+            }
+        }
     return FX_OK;
 }
 

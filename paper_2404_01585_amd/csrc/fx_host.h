@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <cstring>
 #include <memory>
 #include <cstdarg>
 #include <cstdint>
@@ -99,6 +100,8 @@ struct EngineParams {
     bool no_digest = false;
     bool ref_bytes = false;   // count the reference algorithmic bytes (extra loads: a counting pass)
     bool lone_growth = true;  // long VERDICT queries left nearly alone may grow their support stacks
+    int32_t chain_queries = 8;    // at most this many queries left (none waiting): device-scheduled steps
+    int32_t chain_steps = 16;     // steps per chain (one host synchronisation each)
     int32_t promote_after = 16;   // steps a query has run before its stack may grow
     int32_t lone_queries = 2;     // open queries at or below which VERDICT support stacks grow freely
     int32_t lone_after = 1024;    // ... once the VERDICT query has run this many steps
@@ -117,6 +120,17 @@ struct EngineLane {
 // Device and pinned buffers of one engine (a context's, or a server's).  Lane
 // 0 runs on the engine's stream, every other lane on a stream of its own, so
 // the lanes' steps overlap on the device; each lane has its own scratch.
+// A chain of device-scheduled steps captured in a HIP graph, with what it was
+// captured for (the launch shape and every buffer its nodes point at).
+struct ChainGraphKey {
+    const void *graph;
+    FxGraphDev dev;
+    int32_t items, width, steps, max_q;
+    const void *bufs[8];
+    size_t bytes;
+    bool operator==(const ChainGraphKey &o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
 struct EngineWork {
     EngineWork();  // the pool allocates its chunks with hipMalloc
     RegionPool pool;
@@ -124,8 +138,18 @@ struct EngineWork {
     EngineLane lane[FX_MAX_LANES];
     hipStream_t own_stream[FX_MAX_LANES - 1] = {};  // lanes 1.. (non-blocking, default priority)
     hipEvent_t start_ev = nullptr;  // orders those lanes after earlier work on the engine's stream
+    // device-scheduled steps: control block, chained queries and their
+    // segment table (device), their pinned mirror, the stream the captured
+    // chain replays on, and the captured chain
+    DevBuf chain_d;
+    HostBuf chain_h;
+    hipStream_t chain_stream = nullptr;
+    ChainGraphKey chain_key{};
+    hipGraph_t chain_graph = nullptr;
+    hipGraphExec_t chain_exec = nullptr;
     ~EngineWork();
     fx_status init_events();
+    void drop_chain_graph();
 };
 
 struct fx_ctx {
@@ -225,7 +249,10 @@ private:
     void enqueue(std::unique_ptr<FxQuery> q);
     fx_status admit(int g);
     fx_status promote(FxQuery &q, int64_t new_cap);
-    fx_status finish(FxQuery &q, const FxSummary *sums);
+    fx_status finish(FxQuery &q, const FxSummary &S);
+    bool chain_ready() const;
+    fx_status chain_step(double &waited);
+    fx_status grow_stacks(std::vector<FxQuery *> &qs, uint64_t n_open);
     fx_status collect(int g, double &waited);
     fx_status launch(int g);
     void done(FxRequest *r);

@@ -37,6 +37,8 @@
 #define FX_LDSP 1024         // partial offsets a workgroup stages in LDS
 #define FX_GREEDY_H 4096     // LDS hash slots of the per-query greedy
 #define FX_GREEDY_VN 2048    // embedding-vertices per greedy chunk (<= H / 2)
+#define FX_FILL 0.8          // a slice aims at this fraction of the rows it may write
+#define FX_COUNT_SPAN (1ull << 22)  // least last-vertex candidates of a counting slice
 
 // Dense labels fit 16 bits (more than 65535 distinct labels is FX_ELIMIT).
 struct FxPlan {
@@ -163,6 +165,75 @@ struct FxInit {
     int32_t clear_u, clear_sum;
 };
 
+// ---------------------------------------------------------------------------
+// Device-scheduled steps.  When few queries are left, the engine hands them
+// to a chain of steps that runs without the host: each step starts with a
+// one-workgroup scheduler kernel that advances every query from its last
+// step's counters (as the host would), decides which queries are finished,
+// and writes the next segment table; the expansion and greedy kernels then
+// run over a fixed grid and loop over the tiles the scheduler announced.  A
+// chain of K steps is captured once in a HIP graph and replayed; the host
+// reads the queries' state back once per chain instead of once per step.
+// ---------------------------------------------------------------------------
+
+enum : int32_t { FX_CQ_SUPPORT = 0, FX_CQ_COUNT = 1 };  // phase of a chained query
+
+struct FxChainQuery {
+    // fixed while the query runs
+    FxLevelDev lev[FX_MAXN + 1];
+    const FxPlan *plan;
+    uint32_t *U;
+    FxSummary *sum;
+    int32_t *sel_rows;
+    int64_t *sel_rank;
+    uint32_t *img;
+    uint64_t img_words;
+    int64_t cap;            // rows per level of its stack
+    int64_t tau_eff;
+    int64_t upper_bound;    // disjointness bound on the support
+    int64_t count_cap;
+    uint64_t bucket0;       // candidates of level 0 (the label bucket of vertex 0)
+    uint32_t last_span;     // complete embeddings per greedy slice
+    int32_t n;
+    int32_t verdict;        // VERDICT mode: ends at tau or at the exactness bound
+    int32_t mni;            // minimum-image mode: no support phase, no count cap
+    int32_t full;           // FULL mode: the count phase follows the support phase
+    int32_t sym;            // symmetry-breaking constraints in the support phase
+    int32_t leaf_count;     // count phase: the leaf last vertex is counted in closed form
+    int32_t hash;           // count phase: hash every embedding
+    int32_t ref_bytes;      // count the reference algorithmic bytes
+    // advanced by the scheduler
+    int32_t phase;          // FX_CQ_*
+    int32_t deep;           // deepest level with candidates left, -1: none
+    int32_t done;           // finished (the host retires it)
+    int32_t exit;           // fx_result.exit
+    int32_t steps;
+    int32_t error;          // nonzero: a consistency check failed
+    uint64_t T[FX_MAXN + 1], cur[FX_MAXN + 1];
+    int64_t nparts[FX_MAXN + 1];
+    double rate[FX_MAXN + 1];
+    int64_t rank_base;
+    uint64_t probed_support, probed, reoffered;
+    uint64_t alg_probe_seen, ref_probe_seen, ref_row_seen;
+    double alg_probe_credit, ref_probe_credit, ref_row_credit;
+    // the segment in flight
+    int32_t seg_l, seg_kind;
+    uint64_t seg_t0;
+    uint32_t seg_span;
+    uint32_t pad0;
+    FxSummary last;         // the counters as of the last advance
+};
+
+struct FxChainCtl {
+    int32_t nq;             // chained queries
+    uint32_t nsegs;         // segments of the step in flight
+    uint32_t nblocks;       // expansion workgroups (tiles) of the step in flight
+    uint32_t rot;           // rotates which query the step budget serves first
+    uint32_t steps;         // steps that had at least one segment
+    uint32_t error;
+    uint64_t budget;        // candidates per step, all queries together
+};
+
 // Launchers (fx_kernels.hip).  All return the hipError_t of the launches.
 hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *inits, int32_t ninit);
 // Minimum-image support from n image bitmaps of `words` words each: counts[j]
@@ -180,3 +251,10 @@ hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs,
                           uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
                           hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
                           hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy);
+// Enqueues `steps` device-scheduled steps over the chained queries in cq
+// (ctl->nq of them, at most max_q), then a final advance, on stream s.  The
+// scratch buffers must hold ceil(ctl->budget / (FX_BS * items)) + max_q
+// tiles; segs and blk0s room for max_q segments.
+hipError_t fx_launch_chain(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
+                           int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, int32_t maxn, FxTile *tmap,
+                           uint8_t *flag, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff);

@@ -15,6 +15,7 @@
 // this is the lexicographically-first MIS, i.e. exactly the sequential greedy
 // of the matcher in Section 3.2.2.
 #include "fx_internal.h"
+#include "../../include/flexis.h"
 
 namespace {
 
@@ -354,12 +355,10 @@ __device__ __forceinline__ uint64_t lanemask_lt()
 // level's candidate offsets -- done here once instead of at the start of
 // every workgroup of the probe, the scatter and the offset fix-up.
 template <int ITEMS>
-__global__ __launch_bounds__(FX_BS) void k_tile_map(const FxSeg *__restrict__ segs, const uint32_t *__restrict__ blk0s,
-                                                    int32_t nsegs, uint32_t nblocks, FxTile *tmap)
+__device__ __forceinline__ void tile_map_one(const FxSeg *__restrict__ segs, const uint32_t *__restrict__ blk0s,
+                                             int32_t nsegs, uint32_t b, FxTile *tmap)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
-    const uint32_t b = blockIdx.x * FX_BS + threadIdx.x;
-    if (b >= nblocks) return;
     int32_t lo = 0, hi = nsegs;
     while (hi - lo > 1) {
         const int32_t mid = (lo + hi) >> 1;
@@ -376,6 +375,26 @@ __global__ __launch_bounds__(FX_BS) void k_tile_map(const FxSeg *__restrict__ se
     t.np = (int32_t)(p1 - p0 + 1);
     t.p0 = p0;
     tmap[b] = t;
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(FX_BS) void k_tile_map(const FxSeg *__restrict__ segs, const uint32_t *__restrict__ blk0s,
+                                                    int32_t nsegs, uint32_t nblocks, FxTile *tmap)
+{
+    const uint32_t b = blockIdx.x * FX_BS + threadIdx.x;
+    if (b < nblocks) tile_map_one<ITEMS>(segs, blk0s, nsegs, b, tmap);
+}
+
+// The same over a fixed grid, with the step's size from the scheduler.
+template <int ITEMS>
+__global__ __launch_bounds__(FX_BS) void k_tile_map_chain(const FxSeg *__restrict__ segs,
+                                                          const uint32_t *__restrict__ blk0s, const FxChainCtl *ctl,
+                                                          FxTile *tmap)
+{
+    const uint32_t nb = ctl->nblocks;
+    const int32_t ns = (int32_t)ctl->nsegs;
+    for (uint32_t b = blockIdx.x * FX_BS + threadIdx.x; b < nb; b += gridDim.x * FX_BS)
+        tile_map_one<ITEMS>(segs, blk0s, ns, b, tmap);
 }
 
 template <int W>
@@ -439,18 +458,25 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
 // Test every candidate of every segment (ITEMS per thread, strided by
 // the workgroup size so each item pass covers consecutive candidates).
 // Writes a pass flag per candidate and the number of passes per workgroup.
+struct ProbeLds {
+    int64_t s_off[FX_LDSP + 1];
+    uint8_t s_dead[FX_LDSP];
+    uint32_t wcnt[FX_BS / 64];
+};
+
 template <int ITEMS, int W>
-__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe(
-    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt)
+__device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__restrict__ segs,
+                                           const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt,
+                                           const uint32_t blk, ProbeLds &lds)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
-    __shared__ int64_t s_off[FX_LDSP + 1];
-    __shared__ uint8_t s_dead[FX_LDSP];
-    __shared__ uint32_t wcnt[FX_BS / 64];
-    const FxTile T = tmap[blockIdx.x];
+    int64_t *s_off = lds.s_off;
+    uint8_t *s_dead = lds.s_dead;
+    uint32_t *wcnt = lds.wcnt;
+    const FxTile T = tmap[blk];
     const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
     const int32_t l = S.l, n = S.n, flags = S.flags;
-    const uint32_t tile0 = (blockIdx.x - S.blk0) * TILE;
+    const uint32_t tile0 = (blk - S.blk0) * TILE;
     const TileMap m = map_tile(S.in.off, T, s_off);
     const bool ufilter = (flags & FX_PROBE_UFILTER) != 0;
     uint32_t bytes = 0;
@@ -538,7 +564,7 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
                 if (leaf) cnt += leaf_count(g, S.plan, l, x, bytes);
                 mat = S.kind != FX_SEG_COUNT;
             }
-            flag[(uint64_t)blockIdx.x * TILE + it * FX_BS + threadIdx.x] = mat ? 1 : 0;
+            flag[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x] = mat ? 1 : 0;
         }
         passed += mat ? 1u : 0u;
     }
@@ -583,7 +609,28 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
         if (__lane_id() == 0 && d) atomicAdd(&S.sum->ref_probe_row, d);
     }
     __syncthreads();
-    if (threadIdx.x == 0) bcnt[blockIdx.x] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (threadIdx.x == 0) bcnt[blk] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+}
+
+template <int ITEMS, int W>
+__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe(
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt)
+{
+    __shared__ ProbeLds lds;
+    probe_tile<ITEMS, W>(g, segs, tmap, flag, bcnt, blockIdx.x, lds);
+}
+
+template <int ITEMS, int W>
+__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe_chain(
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt,
+    const FxChainCtl *ctl)
+{
+    __shared__ ProbeLds lds;
+    const uint32_t nb = ctl->nblocks;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        probe_tile<ITEMS, W>(g, segs, tmap, flag, bcnt, b, lds);
+        __syncthreads();  // the tile's LDS is reused by the next
+    }
 }
 
 // Exclusive scan of per-workgroup values over the whole launch (one
@@ -592,7 +639,7 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
 // 16 totals give each wave its starting offset, then the wave scans its range
 // 64 values at a time (a shuffle scan per chunk plus a running carry).
 template <class T>
-__global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt, uint32_t nblocks, uint64_t *boff)
+__device__ __forceinline__ void scan_blocks(const T *__restrict__ bcnt, uint32_t nblocks, uint64_t *boff)
 {
     constexpr uint32_t W = 1024 / 64;
     __shared__ unsigned long long wtot[W];
@@ -628,6 +675,19 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt
     if (threadIdx.x == 0) boff[nblocks] = total;
 }
 
+template <class T>
+__global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt, uint32_t nblocks, uint64_t *boff)
+{
+    scan_blocks<T>(bcnt, nblocks, boff);
+}
+
+template <class T>
+__global__ __launch_bounds__(1024) void k_scan_blocks_chain(const T *__restrict__ bcnt, const FxChainCtl *ctl,
+                                                            uint64_t *boff)
+{
+    scan_blocks<T>(bcnt, ctl->nblocks, boff);
+}
+
 // Ordered write of the passing candidates of each segment into its level l+1
 // (position = passes before it in the segment, in candidate order), with the
 // candidate run of the next pattern vertex for inner levels.  For inner
@@ -638,50 +698,58 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt
 // and the summary records how many candidates that took (the rest are
 // probed again in a later step), so a slice may span many more candidates
 // than the level holds rows.
+template <int ITEMS>
+struct ScatterLds {
+    int64_t s_off[FX_LDSP + 1];
+    uint32_t wcnt[ITEMS][FX_BS / 64];
+    unsigned long long ltot[ITEMS][FX_BS / 64];
+};
+
 template <int ITEMS, int W>
-__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scatter(FxGraphDev g, const FxSeg *__restrict__ segs,
-                                                   const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
-                                                   const uint64_t *__restrict__ boff, uint64_t *lsum)
+__device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *__restrict__ segs,
+                                             const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
+                                             const uint64_t *__restrict__ boff, uint64_t *lsum, const uint32_t blk,
+                                             ScatterLds<ITEMS> &lds)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
-    __shared__ int64_t s_off[FX_LDSP + 1];
-    __shared__ uint32_t wcnt[ITEMS][FX_BS / 64];
-    __shared__ unsigned long long ltot[ITEMS][FX_BS / 64];
-    const FxTile T = tmap[blockIdx.x];
+    int64_t *s_off = lds.s_off;
+    auto &wcnt = lds.wcnt;
+    auto &ltot = lds.ltot;
+    const FxTile T = tmap[blk];
     const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
     const int32_t l = S.l, n = S.n;
     const uint64_t seg_base = boff[S.blk0];
     const uint64_t seg_pass = boff[S.blk0 + (S.span + TILE - 1) / TILE] - seg_base;
     const uint64_t cap = S.kind == FX_SEG_COUNT ? seg_pass : (uint64_t)S.out_cap;
     const bool overflow = seg_pass > cap;
-    if (blockIdx.x == S.blk0 && threadIdx.x == 0) {
+    if (blk == S.blk0 && threadIdx.x == 0) {
         S.sum->passes = seg_pass;
         S.sum->total_out = overflow ? cap : seg_pass;
         if (!overflow) S.sum->consumed = S.span;
     }
-    if (S.kind != FX_SEG_INNER && threadIdx.x == 0) lsum[blockIdx.x] = 0;
+    if (S.kind != FX_SEG_INNER && threadIdx.x == 0) lsum[blk] = 0;
     if (S.kind == FX_SEG_COUNT) return;  // nothing is written for a counting segment
     // a tile without passing candidates, or whose passes all fall past the row
     // cap, writes nothing (its run-length total is 0); uniform per workgroup
-    if (boff[blockIdx.x + 1] == boff[blockIdx.x] || boff[blockIdx.x] - seg_base >= cap) {
-        if (threadIdx.x == 0) lsum[blockIdx.x] = 0;
+    if (boff[blk + 1] == boff[blk] || boff[blk] - seg_base >= cap) {
+        if (threadIdx.x == 0) lsum[blk] = 0;
         return;
     }
-    const uint32_t tile0 = (blockIdx.x - S.blk0) * TILE;
+    const uint32_t tile0 = (blk - S.blk0) * TILE;
     const uint32_t wave = threadIdx.x >> 6;
     uint64_t bal[ITEMS];
     bool f[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
-        f[it] = tl < S.span && flag[(uint64_t)blockIdx.x * TILE + it * FX_BS + threadIdx.x];
+        f[it] = tl < S.span && flag[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x];
         bal[it] = __ballot(f[it]);
         if (__lane_id() == 0) wcnt[it][wave] = (uint32_t)__popcll(bal[it]);
     }
     const TileMap m = map_tile(S.in.off, T, s_off);
     const int32_t w1 = l + 1;
     uint32_t bytes = 0;
-    uint64_t pos = boff[blockIdx.x] - seg_base;
+    uint64_t pos = boff[blk] - seg_base;
     uint32_t p_out[ITEMS];  // row of the candidate in the segment's output (< out_cap when written)
     int32_t lens[ITEMS];
 #pragma unroll
@@ -766,7 +834,7 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
             if (f[it]) S.out.off[p_out[it]] = (int64_t)(mine + (uint64_t)(inc - lens[it]));
             for (uint32_t w = 0; w < FX_BS / 64; w++) before += ltot[it][w];
         }
-        if (threadIdx.x == 0) lsum[blockIdx.x] = before;
+        if (threadIdx.x == 0) lsum[blk] = before;
     }
     unsigned long long b = bytes;
 #pragma unroll
@@ -782,29 +850,69 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     }
 }
 
+template <int ITEMS, int W>
+__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scatter(
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
+    const uint64_t *__restrict__ boff, uint64_t *lsum)
+{
+    __shared__ ScatterLds<ITEMS> lds;
+    scatter_tile<ITEMS, W>(g, segs, tmap, flag, boff, lsum, blockIdx.x, lds);
+}
+
+template <int ITEMS, int W>
+__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scatter_chain(
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
+    const uint64_t *__restrict__ boff, uint64_t *lsum, const FxChainCtl *ctl)
+{
+    __shared__ ScatterLds<ITEMS> lds;
+    const uint32_t nb = ctl->nblocks;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        scatter_tile<ITEMS, W>(g, segs, tmap, flag, boff, lsum, b, lds);
+        __syncthreads();  // the tile's LDS is reused by the next
+    }
+}
+
 // Adds each workgroup's offset (scan of lsum within its segment) to the
 // run-length prefixes k_scatter wrote, and closes each inner level with
 // off[N] and the level's candidate total.
 template <int ITEMS>
-__global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap,
-                                                   const uint64_t *__restrict__ boff, const uint64_t *__restrict__ loff)
+__device__ __forceinline__ void fix_off_tile(const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap,
+                                             const uint64_t *__restrict__ boff, const uint64_t *__restrict__ loff,
+                                             const uint32_t blk)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
-    const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(tmap[blockIdx.x].seg)];
+    const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(tmap[blk].seg)];
     if (S.kind != FX_SEG_INNER) return;
     const uint64_t seg_base = boff[S.blk0];
     const uint64_t cap = S.out_cap;
-    const uint64_t r0 = min(boff[blockIdx.x] - seg_base, cap), r1 = min(boff[blockIdx.x + 1] - seg_base, cap);
-    const uint64_t add = loff[blockIdx.x] - loff[S.blk0];
+    const uint64_t r0 = min(boff[blk] - seg_base, cap), r1 = min(boff[blk + 1] - seg_base, cap);
+    const uint64_t add = loff[blk] - loff[S.blk0];
     if (add)
         for (uint64_t r = r0 + threadIdx.x; r < r1; r += FX_BS) S.out.off[r] += (int64_t)add;
-    if (blockIdx.x == S.blk0 && threadIdx.x == 0) {
+    if (blk == S.blk0 && threadIdx.x == 0) {
         const uint32_t nblk = (S.span + TILE - 1) / TILE;
         const uint64_t N = min(boff[S.blk0 + nblk] - seg_base, cap);
         const uint64_t total = loff[S.blk0 + nblk] - loff[S.blk0];
         S.out.off[N] = (int64_t)total;
         S.sum->t_next = total;
     }
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(FX_BS) void k_fix_off(const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap,
+                                                   const uint64_t *__restrict__ boff, const uint64_t *__restrict__ loff)
+{
+    fix_off_tile<ITEMS>(segs, tmap, boff, loff, blockIdx.x);
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(FX_BS) void k_fix_off_chain(const FxSeg *__restrict__ segs,
+                                                         const FxTile *__restrict__ tmap,
+                                                         const uint64_t *__restrict__ boff,
+                                                         const uint64_t *__restrict__ loff, const FxChainCtl *ctl)
+{
+    const uint32_t nb = ctl->nblocks;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) fix_off_tile<ITEMS>(segs, tmap, boff, loff, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -884,7 +992,8 @@ __device__ void greedy_tail(uint8_t *state, const uint16_t *slot, uint32_t *hval
     }
 }
 
-__global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs)
+template <bool CHAIN>
+__global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs, const FxChainCtl *ctl)
 {
     static_assert(FX_GREEDY_H == 4096 && 2 * FX_GREEDY_VN <= FX_GREEDY_H, "a chunk's vertices fill at most half");
     // 32-bit slot keys: a chunk's ranks and rounds (at most one per embedding)
@@ -896,6 +1005,7 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
     __shared__ uint8_t state[FX_GREEDY_VN];  // 0 undecided, 1 selected, 2 out, 3 selected by the tail
     __shared__ uint32_t undecided, nsel;
     __shared__ unsigned long long sel_base;
+    if (CHAIN && blockIdx.x >= ctl->nsegs) return;  // a fixed grid: one workgroup per possible segment
     const FxSeg &S = segs[blockIdx.x];
     if (S.kind != FX_SEG_GREEDY) return;
     const int32_t n = S.n;
@@ -1050,6 +1160,192 @@ __global__ __launch_bounds__(FX_BS) void k_greedy(const FxSeg *__restrict__ segs
     }
 }
 
+// ---------------------------------------------------------------------------
+// Device scheduler of a chain of steps (one thread).  It does for the chained
+// queries what the engine's host side does between two steps: advance every
+// query from the counters of its last segment, retire the finished ones
+// (VERDICT at tau or at the exactness bound, the count cap, an exhausted
+// search; a FULL query moves from its support phase to its count phase), and
+// choose every open query's next segment: the deepest level with candidates
+// left, a span aimed at the rows the segment may write from the level's last
+// passing rate, within the query's share of the step's candidates.
+// ---------------------------------------------------------------------------
+
+__device__ int32_t chain_deepest(const FxChainQuery &q)
+{
+    for (int32_t l = q.n - 1; l >= 0; l--)
+        if (q.cur[l] < q.T[l]) return l;
+    return -1;
+}
+
+__device__ void chain_restart(FxChainQuery &q)
+{
+    for (int l = 0; l <= q.n; l++) q.T[l] = q.cur[l] = 0, q.nparts[l] = 0;
+    q.T[0] = q.bucket0;
+    q.nparts[0] = 1;
+    q.deep = chain_deepest(q);
+}
+
+__device__ void chain_advance(FxChainQuery &q)
+{
+    q.last = *q.sum;
+    if (q.seg_l < 0) return;
+    const FxSummary &S = q.last;
+    const int32_t l = q.seg_l;
+    const uint64_t taken = S.consumed;
+    q.seg_l = -1;
+    if (S.error || taken == 0 || taken > q.seg_span) {
+        q.error = 1;
+        q.done = 1;
+        return;
+    }
+    const double share = (double)taken / (double)q.seg_span;
+    q.cur[l] = q.seg_t0 + taken;
+    q.reoffered += q.seg_span - taken;
+    q.probed += q.seg_span;
+    if (q.phase == FX_CQ_SUPPORT) q.probed_support += q.seg_span;
+    q.rate[l] = (double)S.passes / (double)q.seg_span;
+    q.alg_probe_credit += (double)(S.alg_probe - q.alg_probe_seen) * share;
+    q.alg_probe_seen = S.alg_probe;
+    q.ref_probe_credit += (double)(S.ref_probe - q.ref_probe_seen) * share;
+    q.ref_probe_seen = S.ref_probe;
+    q.ref_row_credit += (double)(S.ref_probe_row - q.ref_row_seen) * share;
+    q.ref_row_seen = S.ref_probe_row;
+    q.steps++;
+    if (q.seg_kind == FX_SEG_INNER) {
+        q.nparts[l + 1] = (int64_t)S.total_out;
+        q.T[l + 1] = S.t_next;
+        q.cur[l + 1] = 0;
+    } else if (q.seg_kind == FX_SEG_GREEDY) {
+        q.rank_base += (int64_t)S.total_out;
+    }
+    q.deep = chain_deepest(q);
+}
+
+__device__ void chain_check(FxChainQuery &q)
+{
+    if (q.done) return;
+    const FxSummary &S = q.last;
+    bool fin = false;
+    if (q.phase == FX_CQ_SUPPORT && q.verdict) {
+        const int64_t sup = (int64_t)S.support;
+        if (sup >= q.tau_eff) {
+            fin = true;
+            q.exit = FX_EXIT_REACHED;
+        } else if (q.deep >= 0) {
+            uint64_t roots = q.T[0] - q.cur[0];
+            if (q.deep >= 1) roots += (uint64_t)q.nparts[1];
+            const int64_t room = q.upper_bound - sup > 0 ? q.upper_bound - sup : 0;
+            const int64_t possible = roots < (uint64_t)room ? (int64_t)roots : room;
+            if (sup + possible < q.tau_eff) {
+                fin = true;
+                q.exit = FX_EXIT_BOUND;
+            }
+        }
+    }
+    if (q.phase == FX_CQ_COUNT && !q.mni && (int64_t)S.count >= q.count_cap) fin = true;
+    if (!fin && q.deep < 0) {
+        if (q.phase == FX_CQ_SUPPORT && q.full) {
+            q.phase = FX_CQ_COUNT;
+            chain_restart(q);
+        } else {
+            fin = true;
+        }
+    }
+    if (fin) q.done = 1;
+}
+
+__global__ void k_sched(FxChainQuery *qs, FxChainCtl *ctl, FxSeg *segs, uint32_t *blk0s, uint32_t tile, int32_t final)
+{
+    if (threadIdx.x != 0) return;
+    const int32_t nq = ctl->nq;
+    uint64_t n_open = 0;
+    for (int32_t k = 0; k < nq; k++) {
+        FxChainQuery &q = qs[k];
+        chain_advance(q);
+        chain_check(q);
+        n_open += (!q.done && q.deep >= 0) ? 1 : 0;
+    }
+    uint32_t nsegs = 0, nblocks = 0;
+    if (!final) {
+        uint64_t budget = ctl->budget;
+        const uint64_t share = ctl->budget / (n_open > 0 ? n_open : 1);
+        for (int32_t k = 0; k < nq && budget > 0; k++) {
+            FxChainQuery &q = qs[(ctl->rot + (uint32_t)k) % (uint32_t)nq];
+            if (q.done || q.deep < 0) continue;
+            const int32_t l = q.deep;
+            const bool last = l == q.n - 1;
+            int32_t kind, flags = 0;
+            uint64_t out_cap = (uint64_t)q.cap;
+            if (q.phase == FX_CQ_SUPPORT) {
+                flags = FX_PROBE_UFILTER | (q.sym ? FX_PROBE_SYM : 0);
+                kind = last ? FX_SEG_GREEDY : FX_SEG_INNER;
+                if (last) out_cap = q.last_span < (uint64_t)q.cap ? q.last_span : (uint64_t)q.cap;
+            } else {
+                const bool end = q.leaf_count ? (l == q.n - 2) : last;
+                flags = end ? (q.leaf_count ? FX_PROBE_LEAF
+                                            : (FX_PROBE_COUNT | (q.hash ? FX_PROBE_HASH : 0) |
+                                               (q.mni ? FX_PROBE_IMAGES : 0)))
+                            : 0;
+                kind = end ? FX_SEG_COUNT : FX_SEG_INNER;
+            }
+            uint64_t want;
+            if (kind == FX_SEG_COUNT) {
+                want = FX_COUNT_SPAN > share ? FX_COUNT_SPAN : share;
+            } else {
+                const double r = q.rate[l] > 1e-9 ? q.rate[l] : 1e-9;
+                if (r >= 1.0) {
+                    want = out_cap;
+                } else {
+                    const double w = FX_FILL * (double)out_cap / r;
+                    want = (uint64_t)(w < 2147483648.0 ? w : 2147483648.0);
+                }
+                if (want < out_cap) want = out_cap;
+                const uint64_t hi = out_cap > share ? out_cap : share;
+                if (want > hi) want = hi;
+            }
+            uint64_t span = q.T[l] - q.cur[l];
+            if (span > want) span = want;
+            if (span > budget) span = budget;
+            if (span == 0) continue;
+            if (q.ref_bytes) flags |= FX_PROBE_REF;
+            FxSeg &S = segs[nsegs];
+            S.in = q.lev[l];
+            S.out = q.lev[l + 1];
+            S.plan = q.plan;
+            S.U = q.U;
+            S.sum = q.sum;
+            S.sel_rows = q.sel_rows;
+            S.sel_rank = q.sel_rank;
+            S.img = q.img;
+            S.img_words = q.img_words;
+            S.nparts = q.nparts[l];
+            S.t0 = q.cur[l];
+            S.rank_base = q.rank_base;
+            S.span = (uint32_t)span;
+            S.out_cap = (uint32_t)(out_cap < 0xffffffffull ? out_cap : 0xffffffffull);
+            S.blk0 = nblocks;
+            S.n = q.n;
+            S.l = l;
+            S.flags = flags;
+            S.kind = kind;
+            blk0s[nsegs] = nblocks;
+            nblocks += (uint32_t)((span + tile - 1) / tile);
+            budget -= span;
+            q.seg_l = l;
+            q.seg_kind = kind;
+            q.seg_t0 = q.cur[l];
+            q.seg_span = (uint32_t)span;
+            nsegs++;
+        }
+        ctl->rot++;
+        if (nsegs) ctl->steps++;
+    }
+    blk0s[nsegs] = nblocks;
+    ctl->nsegs = nsegs;
+    ctl->nblocks = nblocks;
+}
+
 // Admission / phase start of queries: level 0 is the single empty partial
 // whose candidate run is the label bucket of pattern vertex 0.
 __global__ void k_init(FxGraphDev g, const FxInit *__restrict__ inits)
@@ -1146,9 +1442,49 @@ hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *se
         hipLaunchKernelGGL(k_fix_off<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, segs, tmap, boff, loff);
     }
     if (greedy_begin && (e = hipEventRecord(greedy_begin, s)) != hipSuccess) return e;
-    if (any_greedy) hipLaunchKernelGGL(k_greedy, dim3(nsegs), dim3(FX_BS), 0, s, segs);
+    if (any_greedy) hipLaunchKernelGGL(k_greedy<false>, dim3(nsegs), dim3(FX_BS), 0, s, segs, nullptr);
     if (greedy_end && (e = hipEventRecord(greedy_end, s)) != hipSuccess) return e;
     return hipGetLastError();
+}
+
+template <int ITEMS, int W>
+hipError_t launch_chain_items(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
+                              int32_t steps, FxSeg *segs, uint32_t *blk0s, FxTile *tmap, uint8_t *flag, uint32_t *bcnt,
+                              uint64_t *boff, uint64_t *lsum, uint64_t *loff)
+{
+    constexpr uint32_t TILE = FX_BS * ITEMS;
+    // enough workgroups to fill the chip at the expansion kernels' occupancy
+    // (8 waves per SIMD, 4 waves per workgroup: 8 per CU on 256 CUs); each
+    // loops over the tiles the scheduler announced
+    constexpr uint32_t kGrid = 2048, kMapGrid = 64;
+    for (int32_t k = 0; k < steps; k++) {
+        hipLaunchKernelGGL(k_sched, dim3(1), dim3(64), 0, s, cq, ctl, segs, blk0s, TILE, 0);
+        hipLaunchKernelGGL(k_tile_map_chain<ITEMS>, dim3(kMapGrid), dim3(FX_BS), 0, s, segs, blk0s, ctl, tmap);
+        hipLaunchKernelGGL((k_probe_chain<ITEMS, W>), dim3(kGrid), dim3(FX_BS), 0, s, g, segs, tmap, flag, bcnt, ctl);
+        hipLaunchKernelGGL(k_scan_blocks_chain<uint32_t>, dim3(1), dim3(1024), 0, s, bcnt, ctl, boff);
+        hipLaunchKernelGGL((k_scatter_chain<ITEMS, W>), dim3(kGrid), dim3(FX_BS), 0, s, g, segs, tmap, flag, boff,
+                           lsum, ctl);
+        hipLaunchKernelGGL(k_scan_blocks_chain<uint64_t>, dim3(1), dim3(1024), 0, s, lsum, ctl, loff);
+        hipLaunchKernelGGL(k_fix_off_chain<ITEMS>, dim3(kGrid), dim3(FX_BS), 0, s, segs, tmap, boff, loff, ctl);
+        hipLaunchKernelGGL(k_greedy<true>, dim3(max_q), dim3(FX_BS), 0, s, segs, ctl);
+    }
+    hipLaunchKernelGGL(k_sched, dim3(1), dim3(64), 0, s, cq, ctl, segs, blk0s, TILE, 1);
+    return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_chain_width(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
+                              int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, FxTile *tmap, uint8_t *flag,
+                              uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff)
+{
+    switch (items) {
+    case 2:
+        return launch_chain_items<2, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, flag, bcnt, boff, lsum, loff);
+    case 8:
+        return launch_chain_items<8, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, flag, bcnt, boff, lsum, loff);
+    default:
+        return launch_chain_items<4, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, flag, bcnt, boff, lsum, loff);
+    }
 }
 
 template <int W>
@@ -1192,4 +1528,19 @@ hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs,
     return launch_step_width<FX_MAXN>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, flag, bcnt, boff, lsum, loff,
                                       probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
                                       any_inner, any_greedy);
+}
+
+hipError_t fx_launch_chain(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
+                           int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, int32_t maxn, FxTile *tmap,
+                           uint8_t *flag, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff)
+{
+    if (maxn < 1 || maxn > FX_MAXN || max_q < 1 || steps < 1) return hipErrorInvalidValue;
+    if (maxn <= 4)
+        return launch_chain_width<4>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, flag, bcnt, boff, lsum,
+                                     loff);
+    if (maxn <= 8)
+        return launch_chain_width<8>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, flag, bcnt, boff, lsum,
+                                     loff);
+    return launch_chain_width<FX_MAXN>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, flag, bcnt, boff, lsum,
+                                       loff);
 }

@@ -51,6 +51,7 @@ EngineParams fx_noalloc_params(const EngineParams &base)
     p.timing = false;
     p.lone_growth = false;
     p.promote_after = INT32_MAX;  // the stack never moves to a larger region
+    p.chain_queries = 0;          // no device-scheduled chains (their graph and buffers are allocated)
     return p;
 }
 

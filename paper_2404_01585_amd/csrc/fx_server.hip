@@ -120,6 +120,9 @@ extern "C" fx_status fx_server_create(fx_graph *g, const fx_server_opts *opts, f
     // server rather than the tail of a batch: measured on the cl100k sweep,
     // growing there cost 16% of the served capacity
     S->params.lone_growth = false;
+    // a query that arrives while a device-scheduled chain runs would wait for
+    // the whole chain: the server schedules every step on the host
+    S->params.chain_queries = 0;
     if (o.max_active > 0) S->params.max_active = o.max_active;
     if (o.slice_rows > 0) S->params.slice_rows = std::min<int64_t>(std::max<int64_t>(o.slice_rows, 64), (int64_t)1 << 26);
     if (o.step_candidates > 0) S->params.step_candidates = (uint64_t)std::max<int64_t>(o.step_candidates, FX_MAX_TILE);

@@ -100,7 +100,8 @@ class StatsC(ctypes.Structure):
                 ("exits_reached", ctypes.c_uint64), ("exits_bound", ctypes.c_uint64),
                 ("lone_promotions", ctypes.c_uint64), ("probe_ref_bytes", ctypes.c_uint64),
                 ("scatter_ref_bytes", ctypes.c_uint64), ("greedy_ref_bytes", ctypes.c_uint64),
-                ("probed", ctypes.c_uint64), ("probe_ref_row_bytes", ctypes.c_uint64)]
+                ("probed", ctypes.c_uint64), ("probe_ref_row_bytes", ctypes.c_uint64),
+                ("chains", ctypes.c_uint64), ("chain_steps", ctypes.c_uint64)]
 
     def to_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -172,11 +172,13 @@ SupportFn = Callable[[List[Pattern], int, float], List[Dict]]
 
 def mine(g: Graph, sigma: int, lam: float, max_edges: int, evaluate: SupportFn,
          max_vertices: int = 16, max_candidates: Optional[int] = None, tau_fn=None,
-         types: Optional[List[Tuple[int, int, int]]] = None) -> Dict:
+         types: Optional[List[Tuple[int, int, int]]] = None, evaluate_last: bool = True) -> Dict:
     """Runs the level-wise loop.  ``evaluate(patterns, sigma, lam)`` returns one
     result dict per pattern with at least 'frequent'.  Returns the candidate
     lists and results of every level.  ``types``: the graph's edge types
-    (``edge_types(g)``), when the caller already has them."""
+    (``edge_types(g)``), when the caller already has them.  With
+    ``evaluate_last`` false the candidates of level ``max_edges`` are generated
+    but not evaluated (their results list is empty)."""
     nv = g.num_vertices
     if types is None:
         types = edge_types(g)
@@ -190,6 +192,10 @@ def mine(g: Graph, sigma: int, lam: float, max_edges: int, evaluate: SupportFn,
             break
         if max_candidates is not None:
             cands = cands[:max_candidates]
+        if level == max_edges and not evaluate_last:
+            level_cands.append(cands)
+            level_res.append([])
+            break
         res = evaluate(cands, sigma, lam)
         level_cands.append(cands)
         level_res.append(res)

@@ -632,3 +632,52 @@ def test_lone_growth_fires(torch_cuda, er1k):
         _say("stats", st)
         assert st["lone_promotions"] > 0
     c.close()
+
+
+@pytest.mark.parametrize("chain_steps", [1, 3, 16])
+def test_device_scheduled_chains(torch_cuda, er1k, chain_steps):
+    """Queries whose steps are scheduled on the device (a captured chain of
+    steps replayed with host work between the replays) give the oracle's
+    results, alone and in a batch, in every mode; small slices make every
+    query run many steps across many chains."""
+    g = er1k
+    pats = sample_patterns(g, 24, seed=808, kmin=2, kmax=6)
+    c = fx.Context(device=0, slice_rows=64, run_index_bytes=-1)
+    c.set("chain_queries", 64)
+    c.set("chain_steps", chain_steps)
+    with c.load_graph(g) as dg:
+        c.stats(reset=True)
+        for i, p in enumerate(pats[:8]):
+            _say("chain alone", chain_steps, i, "n", p.n)
+            full_match(dg, g, p, 20, 1.0)
+            verdict_match(dg, g, p, 20, 0.5)
+        st = c.stats(reset=True)
+        _say("stats alone", st)
+        assert st["chains"] > 0 and st["chain_steps"] > 0
+        for lam in (1.0, 0.3):
+            _say("chain batch FULL", chain_steps, lam)
+            got = dg.support_batch(pats, [20] * len(pats), [lam] * len(pats), fx.MODE_FULL)
+            for p, r in zip(pats, got):
+                want = O.query(g, p, 20, lam, O.FULL)
+                for k in FULL_KEYS:
+                    assert r[k] == want[k], (p, k, r[k], want[k])
+            got = dg.support_batch(pats, [20] * len(pats), [lam] * len(pats), fx.MODE_VERDICT)
+            for p, r in zip(pats, got):
+                want = O.query(g, p, 20, lam, O.VERDICT)
+                for k in ("tau", "support", "frequent", "embedding_count"):
+                    assert r[k] == want[k], (p, k, r[k], want[k])
+        got = dg.support_batch(pats, [20] * len(pats), [1.0] * len(pats), fx.MODE_MNI)
+        for p, r in zip(pats, got):
+            assert r["support"] == O.mni(g, p)
+        st = c.stats()
+        _say("stats batch", st)
+        assert st["chains"] > 0
+        # the same batch with every step scheduled on the host
+        c.set("chain_queries", 0)
+        ref = dg.support_batch(pats, [20] * len(pats), [1.0] * len(pats), fx.MODE_FULL)
+        c.set("chain_queries", 64)
+        again = dg.support_batch(pats, [20] * len(pats), [1.0] * len(pats), fx.MODE_FULL)
+        for a, b in zip(ref, again):
+            for k in FULL_KEYS + ("exit",):
+                assert a[k] == b[k], k
+    c.close()
