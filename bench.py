@@ -84,6 +84,7 @@ GRAPH_DESC = {"cl100k": "Chung-Lu 100K vertices / 500K edges (gamma 2.1), 20 Zip
               "rmat22": "R-MAT scale 22 (4,194,304 vertices, 40M edges), 50 Zipf(1.1) vertex labels, 4 edge labels",
               "cl1m": "Chung-Lu 1M vertices / 8M edges (gamma 2.3), 30 Zipf(1.0) vertex labels, 1 edge label"}
 SHAPE_KEYS = ("slice_rows", "step_candidates", "items_per_thread", "last_span_init", "lanes", "max_active")
+ENGINE_KEYS = ("chain_queries", "chain_steps")  # device-scheduled steps (library defaults unless given)
 
 
 def log(*a):
@@ -359,8 +360,9 @@ def roofline_pass(ctx, dg, batches, mode, repeats: int, count_ref: bool, traffic
     events around every launch; then, when count_ref, again with the same
     launches and the reference algorithmic bytes counted on the device (extra
     loads, so never in the timed pass)."""
-    lanes0 = ctx.get("lanes")
+    lanes0, chain0 = ctx.get("lanes"), ctx.get("chain_queries")
     ctx.set("lanes", 1)
+    ctx.set("chain_queries", 0)  # both passes host-scheduled, so their launches are the same
     marker()
     ctx.set("kernel_timing", 1)
     ctx.stats(reset=True)
@@ -381,6 +383,7 @@ def roofline_pass(ctx, dg, batches, mode, repeats: int, count_ref: bool, traffic
         ctx.set("ref_bytes", 0)
         log("[bench] roofline counting pass done")
     ctx.set("lanes", lanes0)
+    ctx.set("chain_queries", chain0)
     per = {}
     for key, name in KERNELS:
         n = st[f"{key}_launches"]
@@ -408,9 +411,9 @@ def roofline_pass(ctx, dg, batches, mode, repeats: int, count_ref: bool, traffic
     return dict(bound="hbm", achieved=p.get("achieved"), peak=HBM_PEAK_GBS, unit="GB/s", frac=p.get("frac"),
                 traffic=traffic, kernel="k_probe", avg_launch_us=p["avg_launch_us"],
                 alg_bytes_per_launch=p.get("ref_bytes_per_launch"), launches=p["launches"], per_kernel=per,
-                timing="one-lane pass after the timed region (the same batches, HIP events around every launch on "
-                       "the lane's stream); algorithmic bytes = reference bytes counted on the device in a second "
-                       "pass with the same launches")
+                timing="one-lane pass after the timed region (the same batches, host-scheduled steps, HIP events "
+                       "around every launch on the lane's stream); algorithmic bytes = reference bytes counted on "
+                       "the device in a second pass with the same launches")
 
 
 def main():
@@ -430,6 +433,9 @@ def main():
     for k in SHAPE_KEYS:
         ap.add_argument("--" + k.replace("_", "-"), type=int, default=None,
                         help=f"launch shape: {k} (default: the workload's tuned value)")
+    for k in ENGINE_KEYS:
+        ap.add_argument("--" + k.replace("_", "-"), type=int, default=None,
+                        help=f"engine tunable {k} (default: the library's)")
     ap.add_argument("--digest", action="store_true",
                     help="also hash every embedding (FULL-mode digest); counts are exact either way")
     ap.add_argument("--plain-seconds", type=float, default=5.0,
@@ -543,7 +549,10 @@ def main():
         log(f"[bench] autotune {tuned} ({time.perf_counter() - t:.1f} s)")
     else:
         apply_shape(ctx, shape)
-    shape = {k: ctx.get(k) for k in SHAPE_KEYS}
+    for k in ENGINE_KEYS:
+        if getattr(args, k) is not None:
+            ctx.set(k, getattr(args, k))
+    shape = {k: ctx.get(k) for k in SHAPE_KEYS + ENGINE_KEYS}
     log(f"[bench] launch shape {shape}")
 
     for w in range(args.warmup):
@@ -657,6 +666,9 @@ def main():
         "host_ms_per_step": round(st["host_ms"] / max(args.steps, 1), 3),
         "device_wait_ms_per_step": round(st["wait_ms"] / max(args.steps, 1), 3),
         "device_steps_per_step": st["steps"] / max(args.steps, 1),
+        "chained_steps_per_step": st["chain_steps"] / max(args.steps, 1),
+        "chains_per_step": st["chains"] / max(args.steps, 1),
+        "probed_candidates_per_step": st["probed"] / max(args.steps, 1),
         "plain_form": plain,
         "serving": serving,
         "roofline": roofline,

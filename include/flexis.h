@@ -326,10 +326,11 @@ fx_status fx_ctx_stats(fx_ctx *ctx, fx_stats *out, int32_t reset);
  *                     their support-phase stacks
  *   lone_queries      ... once at most this many patterns are open [0, 2^31)
  *   lone_after        ... and the pattern has run this many steps [0, 2^31)
- *   chain_queries     once no pattern waits and at most this many are in
- *                     flight, their steps are scheduled on the device: a chain
- *                     of chain_steps steps, captured once in a HIP graph, runs
- *                     with one host synchronisation [0 (never), 64]
+ *   chain_queries     once no pattern of a batch waits and at most this many
+ *                     are in flight, their steps are scheduled on the device: a
+ *                     chain of up to chain_steps steps, captured once in a HIP
+ *                     graph, runs with one host synchronisation (single-pattern
+ *                     calls keep host-scheduled steps) [0 (never), 64]
  *   chain_steps       steps per chain [1, 256]
  *   kernel_timing     0/1: as FX_CTX_KERNEL_TIMING (per-kernel timing needs the
  *                     host-scheduled steps: no chains while it is on)

@@ -250,7 +250,7 @@ extern "C" fx_status fx_support(fx_graph *g, const fx_pattern *p, int64_t sigma,
     r.out = &res;
     r.selected = selected;
     r.selected_cap = selected_cap;
-    FX_TRY(fx_engine_run(g, reqs, 1));
+    FX_TRY(fx_engine_run(g, reqs, 1, false));
     if (r.status != FX_OK) return r.status;
     *out = res;
     return FX_OK;
@@ -269,7 +269,7 @@ extern "C" fx_status fx_enumerate(fx_graph *g, const fx_pattern *p, int32_t *row
     r.list_rows = rows;
     r.list_cap = cap;
     r.list_count = &cnt;
-    FX_TRY(fx_engine_run(g, reqs, 1));
+    FX_TRY(fx_engine_run(g, reqs, 1, false));
     if (r.status != FX_OK) return r.status;
     *count_out = cnt;
     return FX_OK;

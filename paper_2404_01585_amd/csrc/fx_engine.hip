@@ -328,20 +328,32 @@ EngineWork::~EngineWork()
             (void)hipStreamSynchronize(st);
             (void)hipStreamDestroy(st);
         }
-    drop_chain_graph();
+    for (auto &c : chain) {
+        if (c.exec) (void)hipGraphExecDestroy(c.exec);
+        if (c.graph) (void)hipGraphDestroy(c.graph);
+    }
     if (chain_stream) {
         (void)hipStreamSynchronize(chain_stream);
         (void)hipStreamDestroy(chain_stream);
     }
 }
 
-void EngineWork::drop_chain_graph()
+EngineWork::ChainGraph &EngineWork::chain_graph(const ChainGraphKey &key)
 {
-    if (chain_exec) (void)hipGraphExecDestroy(chain_exec);
-    if (chain_graph) (void)hipGraphDestroy(chain_graph);
-    chain_exec = nullptr;
-    chain_graph = nullptr;
-    chain_key = ChainGraphKey{};
+    ChainGraph *lru = &chain[0];
+    for (auto &c : chain) {
+        if (c.exec && c.key == key) {
+            c.used = ++chain_clock;
+            return c;
+        }
+        if (c.used < lru->used) lru = &c;
+    }
+    if (lru->exec) (void)hipGraphExecDestroy(lru->exec);
+    if (lru->graph) (void)hipGraphDestroy(lru->graph);
+    *lru = ChainGraph{};
+    lru->key = key;
+    lru->used = ++chain_clock;
+    return *lru;
 }
 
 fx_status EngineWork::init_events()
@@ -674,7 +686,7 @@ fx_status FxEngine::step()
         FX_TRY(W_->sums_d.ensure((size_t)A * sizeof(FxSummary)));
         for (int g = 0; g < P_.lanes; g++) {
             EngineLane &L = W_->lane[g];
-            FX_TRY(L.flag.ensure(max_blocks * tile));
+            FX_TRY(L.cand.ensure(max_blocks * tile * 4));
             FX_TRY(L.bcnt.ensure(max_blocks * 4));
             FX_TRY(L.boff.ensure((max_blocks + 1) * 8));
             FX_TRY(L.lsum.ensure(max_blocks * 8));
@@ -856,7 +868,7 @@ fx_status FxEngine::launch(int g)
                           st));
     hipEvent_t *ev = P_.timing ? L.evk : nullptr;
     FX_HIP(fx_launch_step(st, G_->dev, (const FxSeg *)((char *)L.stage_d.p + seg_off), L.stage_d.as<uint32_t>(),
-                          nsegs, nblocks, P_.items, maxn, L.tmap.as<FxTile>(), L.flag.as<uint8_t>(), L.bcnt.as<uint32_t>(),
+                          nsegs, nblocks, P_.items, maxn, L.tmap.as<FxTile>(), L.cand.as<int32_t>(), L.bcnt.as<uint32_t>(),
                           L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>(), ev ? ev[0] : nullptr,
                           ev ? ev[1] : nullptr, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
                           ev ? ev[5] : nullptr, any_inner, any_greedy));
@@ -1116,19 +1128,23 @@ fx_status FxEngine::chain_step(double &waited)
     key.dev = G_->dev;
     key.items = P_.items;
     key.width = maxn <= 4 ? 4 : (maxn <= 8 ? 8 : FX_MAXN);
-    key.steps = P_.chain_steps;
+    // chains start short and double while queries stay open: a query that
+    // ends after a few steps does not sit through a long chain's empty steps
+    key.steps = chain_k_ = std::min<int32_t>(chain_k_ ? 2 * chain_k_ : 2, std::max<int32_t>(P_.chain_steps, 1));
     key.max_q = max_q;
-    const void *bufs[8] = {hb, db, L.tmap.p, L.flag.p, L.bcnt.p, L.boff.p, L.lsum.p, L.loff.p};
+    const void *bufs[8] = {hb, db, L.tmap.p, L.cand.p, L.bcnt.p, L.boff.p, L.lsum.p, L.loff.p};
     memcpy(key.bufs, bufs, sizeof(bufs));
     key.bytes = bytes;
-    if (!W_->chain_exec || !(W_->chain_key == key)) {
-        W_->drop_chain_graph();
+    EngineWork::ChainGraph &cg = W_->chain_graph(key);
+    if (!cg.exec) {
+        if (cg.graph) (void)hipGraphDestroy(cg.graph);
+        cg.graph = nullptr;
         FX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipMemcpyAsync(db, hb, bytes, hipMemcpyHostToDevice, cs);
         if (e == hipSuccess)
-            e = fx_launch_chain(cs, G_->dev, (FxChainQuery *)(db + cq_off), (FxChainCtl *)db, max_q, P_.chain_steps,
+            e = fx_launch_chain(cs, G_->dev, (FxChainQuery *)(db + cq_off), (FxChainCtl *)db, max_q, key.steps,
                                 (FxSeg *)(db + segs_off), (uint32_t *)(db + blk0_off), P_.items, key.width,
-                                L.tmap.as<FxTile>(), L.flag.as<uint8_t>(), L.bcnt.as<uint32_t>(),
+                                L.tmap.as<FxTile>(), L.cand.as<int32_t>(), L.bcnt.as<uint32_t>(),
                                 L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>());
         if (e == hipSuccess) e = hipMemcpyAsync(hb, db, bytes, hipMemcpyDeviceToHost, cs);
         hipGraph_t graph = nullptr;
@@ -1138,11 +1154,14 @@ fx_status FxEngine::chain_step(double &waited)
             return fx_fail(FX_EDEVICE, "capturing the device-scheduled chain failed: %s",
                            hipGetErrorString(e != hipSuccess ? e : e2));
         }
-        W_->chain_graph = graph;
-        FX_HIP(hipGraphInstantiate(&W_->chain_exec, graph, nullptr, nullptr, 0));
-        W_->chain_key = key;
+        cg.graph = graph;
+        const hipError_t e3 = hipGraphInstantiate(&cg.exec, graph, nullptr, nullptr, 0);
+        if (e3 != hipSuccess) {
+            cg.exec = nullptr;
+            return fx_fail(FX_EDEVICE, "instantiating the device-scheduled chain failed: %s", hipGetErrorString(e3));
+        }
     }
-    FX_HIP(hipGraphLaunch(W_->chain_exec, cs));
+    FX_HIP(hipGraphLaunch(cg.exec, cs));
     {
         const auto w0 = std::chrono::steady_clock::now();
         FX_HIP(hipStreamSynchronize(cs));
@@ -1218,10 +1237,11 @@ fx_status fx_engine_run_on(fx_graph *G, EngineWork *W, const EngineParams &p, st
     return FX_OK;
 }
 
-fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active)
+fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active, bool chains)
 {
     fx_ctx *c = G->ctx;
     EngineParams p = c->params;
+    if (!chains) p.chain_queries = 0;
     p.max_active = std::max<int32_t>(1, std::min<int32_t>(max_active, (int32_t)std::max<size_t>(reqs.size(), 1)));
     return fx_engine_run_on(G, &c->work, p, reqs);
 }

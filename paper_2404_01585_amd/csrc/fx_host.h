@@ -111,7 +111,7 @@ struct EngineParams {
 // lane's step, and the summaries read back after it.
 struct EngineLane {
     DevBuf stage_d, inits_d;           // stage: workgroup starts, then the segment table
-    DevBuf flag, bcnt, boff, lsum, loff, tmap;  // per-step scratch of the expansion kernels
+    DevBuf cand, bcnt, boff, lsum, loff, tmap;  // per-step scratch of the expansion kernels
     HostBuf stage_h, inits_h, sums_h;
     hipEvent_t done = nullptr;  // recorded after the lane's summary copy
     hipEvent_t evk[6] = {};     // kernel timing
@@ -144,12 +144,20 @@ struct EngineWork {
     DevBuf chain_d;
     HostBuf chain_h;
     hipStream_t chain_stream = nullptr;
-    ChainGraphKey chain_key{};
-    hipGraph_t chain_graph = nullptr;
-    hipGraphExec_t chain_exec = nullptr;
+    struct ChainGraph {
+        ChainGraphKey key{};
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        uint64_t used = 0;
+    };
+    static constexpr int kChainGraphs = 6;  // captured chains kept (chain lengths and shapes)
+    ChainGraph chain[kChainGraphs];
+    uint64_t chain_clock = 0;
     ~EngineWork();
     fx_status init_events();
-    void drop_chain_graph();
+    // the captured chain for `key`, or a free (least recently used) entry
+    // for it after destroying what it held
+    ChainGraph &chain_graph(const ChainGraphKey &key);
 };
 
 struct fx_ctx {
@@ -271,6 +279,7 @@ private:
     int any_greedy_[FX_MAX_LANES] = {};
     uint64_t nopen_[FX_MAX_LANES] = {};  // queries with candidates left, per lane, at its last launch
     int lane_ = 0;  // the lane the next step() serves
+    int32_t chain_k_ = 0;  // steps of the last device-scheduled chain
     std::chrono::steady_clock::time_point t0_;
     bool buffers_ready_ = false;
 };
@@ -278,6 +287,8 @@ private:
 // Runs every request to completion, many at a time (at most max_active in
 // flight).  Requests that fail validation get their status set; any device
 // error aborts the run.
-fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active);
+// chains: device-scheduled chains allowed (batches; a single query's few steps
+// run faster host-scheduled: measured 2,291 against 1,810 one-call queries/s).
+fx_status fx_engine_run(fx_graph *G, std::vector<FxRequest> &reqs, int32_t max_active, bool chains = true);
 // The same over given buffers and parameters.
 fx_status fx_engine_run_on(fx_graph *G, EngineWork *W, const EngineParams &p, std::vector<FxRequest> &reqs);

@@ -246,7 +246,7 @@ hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int
 // maxn is the largest pattern size among the segments (it picks the register
 // width of a partial row).
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                          int32_t nsegs, uint32_t nblocks, int32_t items, int32_t maxn, FxTile *tmap, uint8_t *flag,
+                          int32_t nsegs, uint32_t nblocks, int32_t items, int32_t maxn, FxTile *tmap, int32_t *cand,
                           uint32_t *bcnt,
                           uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
                           hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
@@ -257,4 +257,4 @@ hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs,
 // tiles; segs and blk0s room for max_q segments.
 hipError_t fx_launch_chain(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
                            int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, int32_t maxn, FxTile *tmap,
-                           uint8_t *flag, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff);
+                           int32_t *cand, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff);

@@ -457,7 +457,9 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
 
 // Test every candidate of every segment (ITEMS per thread, strided by
 // the workgroup size so each item pass covers consecutive candidates).
-// Writes a pass flag per candidate and the number of passes per workgroup.
+// Writes, per candidate, its vertex id when it passes (-1 when not), so the
+// scatter never reads the candidate's adjacency entry again, and the number
+// of passes per workgroup.
 struct ProbeLds {
     int64_t s_off[FX_LDSP + 1];
     uint8_t s_dead[FX_LDSP];
@@ -466,7 +468,7 @@ struct ProbeLds {
 
 template <int ITEMS, int W>
 __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__restrict__ segs,
-                                           const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt,
+                                           const FxTile *__restrict__ tmap, int32_t *cand, uint32_t *bcnt,
                                            const uint32_t blk, ProbeLds &lds)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
@@ -512,8 +514,8 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
             Cand<W> x;
             const int64_t p = tile_part(m, S.in.off, s_off, t);
             load_cand(g, S.in, l, p, t, x);
-            // candidate entry + flag; the partial row and its run descriptor once
-            bytes += (x.anc >= 0 ? 8u : 4u) + 1u;
+            // candidate entry + the pass word; the partial row and its run descriptor once
+            bytes += (x.anc >= 0 ? 8u : 4u) + 4u;
             if (x.first || tl == tile0) bytes += 4u * (uint32_t)l + 21u;
             if (ref) {
                 const unsigned long long own = x.first ? 4u * (uint32_t)l : 0u;  // the partial's row, once
@@ -564,7 +566,7 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
                 if (leaf) cnt += leaf_count(g, S.plan, l, x, bytes);
                 mat = S.kind != FX_SEG_COUNT;
             }
-            flag[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x] = mat ? 1 : 0;
+            cand[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x] = mat ? x.c : -1;
         }
         passed += mat ? 1u : 0u;
     }
@@ -614,21 +616,21 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
 
 template <int ITEMS, int W>
 __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe(
-    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt)
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, int32_t *cand, uint32_t *bcnt)
 {
     __shared__ ProbeLds lds;
-    probe_tile<ITEMS, W>(g, segs, tmap, flag, bcnt, blockIdx.x, lds);
+    probe_tile<ITEMS, W>(g, segs, tmap, cand, bcnt, blockIdx.x, lds);
 }
 
 template <int ITEMS, int W>
 __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe_chain(
-    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, uint8_t *flag, uint32_t *bcnt,
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, int32_t *cand, uint32_t *bcnt,
     const FxChainCtl *ctl)
 {
     __shared__ ProbeLds lds;
     const uint32_t nb = ctl->nblocks;
     for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        probe_tile<ITEMS, W>(g, segs, tmap, flag, bcnt, b, lds);
+        probe_tile<ITEMS, W>(g, segs, tmap, cand, bcnt, b, lds);
         __syncthreads();  // the tile's LDS is reused by the next
     }
 }
@@ -707,7 +709,7 @@ struct ScatterLds {
 
 template <int ITEMS, int W>
 __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *__restrict__ segs,
-                                             const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
+                                             const FxTile *__restrict__ tmap, const int32_t *__restrict__ cand,
                                              const uint64_t *__restrict__ boff, uint64_t *lsum, const uint32_t blk,
                                              ScatterLds<ITEMS> &lds)
 {
@@ -739,10 +741,12 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
     const uint32_t wave = threadIdx.x >> 6;
     uint64_t bal[ITEMS];
     bool f[ITEMS];
+    int32_t cv[ITEMS];  // the passing candidates' vertex ids (from the probe)
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
-        f[it] = tl < S.span && flag[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x];
+        cv[it] = tl < S.span ? cand[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x] : -1;
+        f[it] = cv[it] >= 0;
         bal[it] = __ballot(f[it]);
         if (__lane_id() == 0) wcnt[it][wave] = (uint32_t)__popcll(bal[it]);
     }
@@ -760,12 +764,16 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
         for (uint32_t w = 0; w < wave; w++) p_out[it] += wcnt[it][w];
         if (f[it] && overflow && p_out[it] == cap - 1) S.sum->consumed = tl + 1;  // the last row that fits
         f[it] = f[it] && p_out[it] < cap;
-        // flag read per candidate; row and run descriptor written per survivor
-        bytes += (tl < S.span ? 1u : 0u) + (f[it] ? 4u * (uint32_t)w1 : 0u) + ((f[it] && w1 < n) ? 21u : 0u);
+        // pass word read per candidate; the partial's row read, the new row and
+        // its run descriptor written per survivor
+        bytes += (tl < S.span ? 4u : 0u) + (f[it] ? 4u * (uint32_t)(l + w1) : 0u) + ((f[it] && w1 < n) ? 21u : 0u);
         if (f[it]) {
             const uint64_t t = S.t0 + tl;
             Cand<W> x;
-            load_cand(g, S.in, l, tile_part(m, S.in.off, s_off, t), t, x);
+            const int32_t *row = S.in.rows + tile_part(m, S.in.off, s_off, t) * l;
+#pragma unroll
+            for (int k = 0; k < W; k++) x.v[k] = (k < l) ? row[k] : -1;
+            x.c = cv[it];
             int32_t *dst = S.out.rows + (uint64_t)p_out[it] * (uint32_t)w1;
 #pragma unroll
             for (int k = 0; k < W; k++)
@@ -852,22 +860,22 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
 
 template <int ITEMS, int W>
 __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scatter(
-    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, const int32_t *__restrict__ cand,
     const uint64_t *__restrict__ boff, uint64_t *lsum)
 {
     __shared__ ScatterLds<ITEMS> lds;
-    scatter_tile<ITEMS, W>(g, segs, tmap, flag, boff, lsum, blockIdx.x, lds);
+    scatter_tile<ITEMS, W>(g, segs, tmap, cand, boff, lsum, blockIdx.x, lds);
 }
 
 template <int ITEMS, int W>
 __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scatter_chain(
-    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, const uint8_t *__restrict__ flag,
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, const int32_t *__restrict__ cand,
     const uint64_t *__restrict__ boff, uint64_t *lsum, const FxChainCtl *ctl)
 {
     __shared__ ScatterLds<ITEMS> lds;
     const uint32_t nb = ctl->nblocks;
     for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        scatter_tile<ITEMS, W>(g, segs, tmap, flag, boff, lsum, b, lds);
+        scatter_tile<ITEMS, W>(g, segs, tmap, cand, boff, lsum, b, lds);
         __syncthreads();  // the tile's LDS is reused by the next
     }
 }
@@ -1421,7 +1429,7 @@ hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int
 
 template <int ITEMS, int W>
 hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                             int32_t nsegs, uint32_t nblocks, FxTile *tmap, uint8_t *flag, uint32_t *bcnt, uint64_t *boff,
+                             int32_t nsegs, uint32_t nblocks, FxTile *tmap, int32_t *cand, uint32_t *bcnt, uint64_t *boff,
                              uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
                              hipEvent_t probe_end,
                              hipEvent_t scatter_begin, hipEvent_t scatter_end, hipEvent_t greedy_begin,
@@ -1431,11 +1439,11 @@ hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *se
     hipLaunchKernelGGL(k_tile_map<ITEMS>, dim3((nblocks + FX_BS - 1) / FX_BS), dim3(FX_BS), 0, s, segs, blk0s, nsegs,
                        nblocks, tmap);
     if (probe_begin && (e = hipEventRecord(probe_begin, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_probe<ITEMS, W>), dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, flag, bcnt);
+    hipLaunchKernelGGL((k_probe<ITEMS, W>), dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, cand, bcnt);
     if (probe_end && (e = hipEventRecord(probe_end, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_blocks<uint32_t>, dim3(1), dim3(1024), 0, s, bcnt, nblocks, boff);
     if (scatter_begin && (e = hipEventRecord(scatter_begin, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scatter<ITEMS, W>), dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, flag, boff, lsum);
+    hipLaunchKernelGGL((k_scatter<ITEMS, W>), dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, cand, boff, lsum);
     if (scatter_end && (e = hipEventRecord(scatter_end, s)) != hipSuccess) return e;
     if (any_inner) {
         hipLaunchKernelGGL(k_scan_blocks<uint64_t>, dim3(1), dim3(1024), 0, s, lsum, nblocks, loff);
@@ -1449,7 +1457,7 @@ hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *se
 
 template <int ITEMS, int W>
 hipError_t launch_chain_items(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
-                              int32_t steps, FxSeg *segs, uint32_t *blk0s, FxTile *tmap, uint8_t *flag, uint32_t *bcnt,
+                              int32_t steps, FxSeg *segs, uint32_t *blk0s, FxTile *tmap, int32_t *cand, uint32_t *bcnt,
                               uint64_t *boff, uint64_t *lsum, uint64_t *loff)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
@@ -1460,9 +1468,9 @@ hipError_t launch_chain_items(hipStream_t s, const FxGraphDev &g, FxChainQuery *
     for (int32_t k = 0; k < steps; k++) {
         hipLaunchKernelGGL(k_sched, dim3(1), dim3(64), 0, s, cq, ctl, segs, blk0s, TILE, 0);
         hipLaunchKernelGGL(k_tile_map_chain<ITEMS>, dim3(kMapGrid), dim3(FX_BS), 0, s, segs, blk0s, ctl, tmap);
-        hipLaunchKernelGGL((k_probe_chain<ITEMS, W>), dim3(kGrid), dim3(FX_BS), 0, s, g, segs, tmap, flag, bcnt, ctl);
+        hipLaunchKernelGGL((k_probe_chain<ITEMS, W>), dim3(kGrid), dim3(FX_BS), 0, s, g, segs, tmap, cand, bcnt, ctl);
         hipLaunchKernelGGL(k_scan_blocks_chain<uint32_t>, dim3(1), dim3(1024), 0, s, bcnt, ctl, boff);
-        hipLaunchKernelGGL((k_scatter_chain<ITEMS, W>), dim3(kGrid), dim3(FX_BS), 0, s, g, segs, tmap, flag, boff,
+        hipLaunchKernelGGL((k_scatter_chain<ITEMS, W>), dim3(kGrid), dim3(FX_BS), 0, s, g, segs, tmap, cand, boff,
                            lsum, ctl);
         hipLaunchKernelGGL(k_scan_blocks_chain<uint64_t>, dim3(1), dim3(1024), 0, s, lsum, ctl, loff);
         hipLaunchKernelGGL(k_fix_off_chain<ITEMS>, dim3(kGrid), dim3(FX_BS), 0, s, segs, tmap, boff, loff, ctl);
@@ -1474,73 +1482,73 @@ hipError_t launch_chain_items(hipStream_t s, const FxGraphDev &g, FxChainQuery *
 
 template <int W>
 hipError_t launch_chain_width(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
-                              int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, FxTile *tmap, uint8_t *flag,
+                              int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, FxTile *tmap, int32_t *cand,
                               uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff)
 {
     switch (items) {
     case 2:
-        return launch_chain_items<2, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, flag, bcnt, boff, lsum, loff);
+        return launch_chain_items<2, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, cand, bcnt, boff, lsum, loff);
     case 8:
-        return launch_chain_items<8, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, flag, bcnt, boff, lsum, loff);
+        return launch_chain_items<8, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, cand, bcnt, boff, lsum, loff);
     default:
-        return launch_chain_items<4, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, flag, bcnt, boff, lsum, loff);
+        return launch_chain_items<4, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, cand, bcnt, boff, lsum, loff);
     }
 }
 
 template <int W>
 hipError_t launch_step_width(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                             int32_t nsegs, uint32_t nblocks, int32_t items, FxTile *tmap, uint8_t *flag,
+                             int32_t nsegs, uint32_t nblocks, int32_t items, FxTile *tmap, int32_t *cand,
                              uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff,  hipEvent_t probe_begin,
                              hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
                              hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
 {
     switch (items) {
     case 2:
-        return launch_step_items<2, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff,
+        return launch_step_items<2, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, cand, bcnt, boff, lsum, loff,
                                        probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
                                        any_inner, any_greedy);
     case 8:
-        return launch_step_items<8, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff,
+        return launch_step_items<8, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, cand, bcnt, boff, lsum, loff,
                                        probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
                                        any_inner, any_greedy);
     default:
-        return launch_step_items<4, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, flag, bcnt, boff, lsum, loff,
+        return launch_step_items<4, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, cand, bcnt, boff, lsum, loff,
                                        probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
                                        any_inner, any_greedy);
     }
 }
 
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
-                          int32_t nsegs, uint32_t nblocks, int32_t items, int32_t maxn, FxTile *tmap, uint8_t *flag,
+                          int32_t nsegs, uint32_t nblocks, int32_t items, int32_t maxn, FxTile *tmap, int32_t *cand,
                           uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
                           hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
                           hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
 {
     if (maxn < 1 || maxn > FX_MAXN) return hipErrorInvalidValue;
     if (maxn <= 4)
-        return launch_step_width<4>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, flag, bcnt, boff, lsum, loff,
+        return launch_step_width<4>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, cand, bcnt, boff, lsum, loff,
                                     probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
                                     any_inner, any_greedy);
     if (maxn <= 8)
-        return launch_step_width<8>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, flag, bcnt, boff, lsum, loff,
+        return launch_step_width<8>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, cand, bcnt, boff, lsum, loff,
                                     probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
                                     any_inner, any_greedy);
-    return launch_step_width<FX_MAXN>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, flag, bcnt, boff, lsum, loff,
+    return launch_step_width<FX_MAXN>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, cand, bcnt, boff, lsum, loff,
                                       probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
                                       any_inner, any_greedy);
 }
 
 hipError_t fx_launch_chain(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
                            int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, int32_t maxn, FxTile *tmap,
-                           uint8_t *flag, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff)
+                           int32_t *cand, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff)
 {
     if (maxn < 1 || maxn > FX_MAXN || max_q < 1 || steps < 1) return hipErrorInvalidValue;
     if (maxn <= 4)
-        return launch_chain_width<4>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, flag, bcnt, boff, lsum,
+        return launch_chain_width<4>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, cand, bcnt, boff, lsum,
                                      loff);
     if (maxn <= 8)
-        return launch_chain_width<8>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, flag, bcnt, boff, lsum,
+        return launch_chain_width<8>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, cand, bcnt, boff, lsum,
                                      loff);
-    return launch_chain_width<FX_MAXN>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, flag, bcnt, boff, lsum,
+    return launch_chain_width<FX_MAXN>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, cand, bcnt, boff, lsum,
                                        loff);
 }

@@ -75,7 +75,7 @@ fx_status fx_noalloc_setup(fx_ctx *c)
     // gives at the fixed step budget (one query: one segment)
     const uint64_t min_tile = (uint64_t)FX_BS * 2;
     const uint64_t max_blocks = (kStepCandidates + min_tile - 1) / min_tile + 1;
-    const size_t flag_bytes = (size_t)(kStepCandidates + (uint64_t)FX_MAX_TILE * 2);
+    const size_t cand_bytes = (size_t)(kStepCandidates + (uint64_t)FX_MAX_TILE * 2) * 4;
     char *p = (char *)base;
     auto carve = [&](DevBuf &b, size_t bytes) {
         b.borrow(p, bytes);
@@ -83,7 +83,7 @@ fx_status fx_noalloc_setup(fx_ctx *c)
     };
     EngineLane &L = W->lane[0];
     carve(W->sums_d, sizeof(FxSummary));
-    carve(L.flag, flag_bytes);
+    carve(L.cand, cand_bytes);
     carve(L.bcnt, max_blocks * 4);
     carve(L.boff, (max_blocks + 1) * 8);
     carve(L.lsum, max_blocks * 8);

@@ -638,8 +638,8 @@ def test_lone_growth_fires(torch_cuda, er1k):
 def test_device_scheduled_chains(torch_cuda, er1k, chain_steps):
     """Queries whose steps are scheduled on the device (a captured chain of
     steps replayed with host work between the replays) give the oracle's
-    results, alone and in a batch, in every mode; small slices make every
-    query run many steps across many chains."""
+    results, alone (a batch of one) and in a batch, in every mode; small
+    slices make every query run many steps across many chains."""
     g = er1k
     pats = sample_patterns(g, 24, seed=808, kmin=2, kmax=6)
     c = fx.Context(device=0, slice_rows=64, run_index_bytes=-1)
@@ -649,8 +649,14 @@ def test_device_scheduled_chains(torch_cuda, er1k, chain_steps):
         c.stats(reset=True)
         for i, p in enumerate(pats[:8]):
             _say("chain alone", chain_steps, i, "n", p.n)
-            full_match(dg, g, p, 20, 1.0)
-            verdict_match(dg, g, p, 20, 0.5)
+            r = dg.support_batch([p], [20], [1.0], fx.MODE_FULL)[0]
+            want = O.query(g, p, 20, 1.0, O.FULL)
+            for k in FULL_KEYS:
+                assert r[k] == want[k], (k, r[k], want[k])
+            r = dg.support_batch([p], [20], [0.5], fx.MODE_VERDICT)[0]
+            want = O.query(g, p, 20, 0.5, O.VERDICT)
+            for k in ("tau", "support", "frequent"):
+                assert r[k] == want[k], (k, r[k], want[k])
         st = c.stats(reset=True)
         _say("stats alone", st)
         assert st["chains"] > 0 and st["chain_steps"] > 0
