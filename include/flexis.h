@@ -336,6 +336,12 @@ fx_status fx_ctx_stats(fx_ctx *ctx, fx_stats *out, int32_t reset);
  *                     host-scheduled steps: no chains while it is on)
  *   ref_bytes         0/1: also count the reference algorithmic bytes of
  *                     fx_stats (extra loads in the kernels: a counting pass)
+ *   check_steps       0/1: check every step on the host -- its segment table
+ *                     before the launch (candidate ranges inside their levels,
+ *                     level rows and row caps inside the stacks, workgroups
+ *                     inside the step's buffers) and the tile map the device
+ *                     built after it; a violation fails the call with
+ *                     FX_EDEVICE instead of launching (host-scheduled steps)
  * fx_autotune sets the first six.  Errors: FX_EINVAL for an unknown name or a
  * value out of range (the context is unchanged). */
 fx_status fx_ctx_set(fx_ctx *ctx, const char *key, int64_t value);

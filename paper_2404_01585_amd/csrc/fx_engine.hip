@@ -762,6 +762,7 @@ fx_status FxEngine::launch(int g)
 {
     EngineLane &L = W_->lane[g];
     auto &act = active_[g];
+    step_view_[g].clear();
     // the stage buffer holds the workgroup starts, then the segment table,
     // so one copy uploads both
     const size_t seg_off = stage_off(act.size());
@@ -851,6 +852,21 @@ fx_status FxEngine::launch(int g)
         blk0[nsegs] = nblocks;
         nblocks += (uint32_t)((span + (uint64_t)FX_BS * P_.items - 1) / ((uint64_t)FX_BS * P_.items));
         budget -= span;
+        if (P_.check_steps) {
+            FxStepSeg v{};
+            v.n = S.n;
+            v.l = S.l;
+            v.kind = S.kind;
+            v.leaf = (S.flags & FX_PROBE_LEAF) != 0;
+            v.t0 = S.t0;
+            v.span = S.span;
+            v.level_total = q.T[l];
+            v.nparts = S.nparts;
+            v.cap = q.cap;
+            v.out_cap = S.out_cap;
+            v.blk0 = S.blk0;
+            step_view_[g].push_back(v);
+        }
         q.seg_l = l;
         q.seg_kind = kind;
         q.seg_t0 = q.cur[l];
@@ -863,6 +879,14 @@ fx_status FxEngine::launch(int g)
     rot_[g]++;
     if (nsegs == 0) return fx_fail(FX_EDEVICE, "engine stalled with %zu active queries", A);
     blk0[nsegs] = nblocks;
+    if (P_.check_steps) {  // every range the kernels will index, against the buffers sized for it
+        const std::vector<FxStepSeg> &view = step_view_[g];
+        const uint64_t tile = (uint64_t)FX_BS * P_.items;
+        const uint64_t max_blocks = L.bcnt.bytes / 4;
+        const std::string err = fx_check_segments(view, nblocks, (uint32_t)tile, max_blocks, P_.step_candidates);
+        if (!err.empty()) return fx_fail(FX_EDEVICE, "step check failed before the launch: %s", err.c_str());
+        step_blocks_[g] = nblocks;
+    }
     hipStream_t st = ls_[g];
     FX_HIP(hipMemcpyAsync(L.stage_d.p, L.stage_h.p, seg_off + (size_t)nsegs * sizeof(FxSeg), hipMemcpyHostToDevice,
                           st));
@@ -893,6 +917,16 @@ fx_status FxEngine::collect(int g, double &waited)
         waited += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
     }
     in_flight_[g] = false;
+    if (P_.check_steps) {  // the tile map the device built for this step
+        std::vector<FxStepTile> tiles(step_blocks_[g]);
+        static_assert(sizeof(FxStepTile) == sizeof(FxTile), "tile views mirror FxTile");
+        if (!tiles.empty()) {
+            FX_HIP(hipMemcpyAsync(tiles.data(), L.tmap.p, tiles.size() * sizeof(FxTile), hipMemcpyDeviceToHost, ls_[g]));
+            FX_HIP(hipStreamSynchronize(ls_[g]));
+        }
+        const std::string err = fx_check_tiles(step_view_[g], tiles, (uint32_t)(FX_BS * P_.items));
+        if (!err.empty()) return fx_fail(FX_EDEVICE, "step check failed after the step: %s", err.c_str());
+    }
     for (auto &r : deferred_[g]) W_->pool.give(r.first, r.second);
     deferred_[g].clear();
     const FxSummary *sums_h = L.sums_h.as<FxSummary>();
@@ -1026,7 +1060,8 @@ size_t chain_layout(int32_t max_q, size_t *cq_off, size_t *blk0_off, size_t *seg
 // step).  Per-kernel timing needs the host-scheduled steps.
 bool FxEngine::chain_ready() const
 {
-    if (P_.chain_queries <= 0 || P_.chain_steps <= 0 || P_.timing || !pending_.empty()) return false;
+    if (P_.chain_queries <= 0 || P_.chain_steps <= 0 || P_.timing || P_.check_steps || !pending_.empty())
+        return false;
     size_t total = 0;
     for (int g = 0; g < P_.lanes; g++) {
         total += active_[g].size();

@@ -18,6 +18,7 @@
 
 #include "../../include/flexis.h"
 #include "fx_internal.h"
+#include "fx_check.h"
 #include "fx_pool.h"
 
 fx_status fx_fail(fx_status code, const char *fmt, ...);
@@ -99,6 +100,7 @@ struct EngineParams {
     bool timing = false;
     bool no_digest = false;
     bool ref_bytes = false;   // count the reference algorithmic bytes (extra loads: a counting pass)
+    bool check_steps = false; // check every step's segment table and tile map on the host (fx_check.h)
     bool lone_growth = true;  // long VERDICT queries left nearly alone may grow their support stacks
     int32_t chain_queries = 8;    // at most this many queries left (none waiting): device-scheduled steps
     int32_t chain_steps = 16;     // steps per chain (one host synchronisation each)
@@ -280,6 +282,8 @@ private:
     uint64_t nopen_[FX_MAX_LANES] = {};  // queries with candidates left, per lane, at its last launch
     int lane_ = 0;  // the lane the next step() serves
     int32_t chain_k_ = 0;  // steps of the last device-scheduled chain
+    std::vector<FxStepSeg> step_view_[FX_MAX_LANES];  // the lane's step in flight, for check_steps
+    uint32_t step_blocks_[FX_MAX_LANES] = {};
     std::chrono::steady_clock::time_point t0_;
     bool buffers_ready_ = false;
 };

@@ -687,3 +687,25 @@ def test_device_scheduled_chains(torch_cuda, er1k, chain_steps):
             for k in FULL_KEYS + ("exit",):
                 assert a[k] == b[k], k
     c.close()
+
+
+def test_step_checks_on_real_steps(torch_cuda, er1k):
+    """With check_steps on, every host-scheduled step's segment table and the
+    tile map the device built are checked against the buffers sized for them
+    (small slices: ragged tails, capped slices, promotions); no check fires
+    and the results stay the oracle's."""
+    g = er1k
+    pats = sample_patterns(g, 20, seed=909, kmin=2, kmax=7)
+    c = fx.Context(device=0, slice_rows=64, run_index_bytes=-1)
+    c.set("check_steps", 1)
+    with c.load_graph(g) as dg:
+        for mode, om in ((fx.MODE_FULL, O.FULL), (fx.MODE_VERDICT, O.VERDICT)):
+            _say("step checks mode", mode)
+            got = dg.support_batch(pats, [20] * len(pats), [0.5] * len(pats), mode)
+            for p, r in zip(pats, got):
+                want = O.query(g, p, 20, 0.5, om)
+                for k in ("tau", "support", "frequent", "embedding_count"):
+                    assert r[k] == want[k], (p, k, r[k], want[k])
+        for p in pats[:4]:
+            list_match(dg, g, p)
+    c.close()

@@ -34,3 +34,17 @@ def test_host_workers(tmp_path, sanitizer):
     out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "ok"
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="no host C++ compiler")
+def test_step_checks(tmp_path):
+    """The host-side checks of a step's segment table and tile map (the
+    check_steps tunable) accept a well-formed step and catch every way one
+    could index outside its buffers."""
+    exe = str(tmp_path / "check_test")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                           "-I", os.path.join(ROOT, "paper_2404_01585_amd", "csrc"),
+                           os.path.join(HERE, "host_check_test.cpp"), "-o", exe])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "ok"
