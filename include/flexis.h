@@ -51,13 +51,21 @@ enum {
 enum {
     FX_MODE_FULL = 0,    /* exact support, verdict, embedding count and digest */
     FX_MODE_VERDICT = 1, /* verdict only; the search stops as soon as it is decided */
-    FX_MODE_MNI = 2      /* the minimum-image support of Section 2.4.4 instead of the
+    FX_MODE_MNI = 2,     /* the minimum-image support of Section 2.4.4 instead of the
                             greedy: support = min over pattern vertices v of the
                             number of distinct data vertices v is mapped to by the
                             embeddings; tau = sigma (lambda is not used: it belongs
                             to the greedy metric); frequent = support >= max(sigma, 1);
                             embedding count and digest as in FULL (every embedding is
                             enumerated, the count cap only caps the reported count) */
+    FX_MODE_MIS = 3      /* the exact maximum independent set of Section 2.4.2 (the
+                            paper's gold-standard metric, NP-hard: small instances
+                            only) instead of the greedy: support = the largest number
+                            of pairwise vertex-disjoint embeddings; tau = sigma;
+                            frequent = support >= max(sigma, 1); embedding_count =
+                            |M| (exact); digest 0; rounds = search nodes.  FX_ELIMIT
+                            beyond 4096 embeddings, 256 distinct vertex sets or 2^24
+                            search nodes.  fx_support and fx_support_batch only. */
 };
 
 #define FX_MAX_PATTERN_VERTICES 16

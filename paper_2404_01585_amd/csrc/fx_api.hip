@@ -232,13 +232,23 @@ extern "C" fx_status fx_ctx_stats(fx_ctx *c, fx_stats *out, int32_t reset)
 // Queries
 // ---------------------------------------------------------------------------
 
+int32_t fx_query_kind(int32_t mode)
+{
+    switch (mode) {
+    case FX_MODE_FULL: return FX_Q_FULL;
+    case FX_MODE_MNI: return FX_Q_MNI;
+    case FX_MODE_MIS: return FX_Q_MIS;
+    default: return FX_Q_VERDICT;
+    }
+}
+
 extern "C" fx_status fx_support(fx_graph *g, const fx_pattern *p, int64_t sigma, double lambda, int32_t mode,
                                 fx_result *out, int32_t *selected, int64_t selected_cap)
 {
     if (!g || !out) return fx_fail(FX_EINVAL, "NULL argument");
     if (sigma < 1) return fx_fail(FX_EINVAL, "sigma must be >= 1");
     if (!(lambda >= 0.0 && lambda <= 1.0)) return fx_fail(FX_EINVAL, "lambda must lie in [0, 1]");
-    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI)
+    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI && mode != FX_MODE_MIS)
         return fx_fail(FX_EINVAL, "unknown mode %d", mode);
     if (selected_cap < 0 || (selected_cap > 0 && !selected)) return fx_fail(FX_EINVAL, "bad selected buffer");
     FX_HIP(hipSetDevice(g->ctx->device));
@@ -248,7 +258,7 @@ extern "C" fx_status fx_support(fx_graph *g, const fx_pattern *p, int64_t sigma,
     r.pattern = p;
     r.sigma = sigma;
     r.lambda = lambda;
-    r.kind = mode == FX_MODE_FULL ? FX_Q_FULL : (mode == FX_MODE_MNI ? FX_Q_MNI : FX_Q_VERDICT);
+    r.kind = fx_query_kind(mode);
     r.out = &res;
     r.selected = selected;
     r.selected_cap = selected_cap;
@@ -281,7 +291,7 @@ extern "C" fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_patter
                                       const double *lambda, int32_t mode, fx_result *out)
 {
     if (!g || npat < 0 || (npat > 0 && (!pats || !sigma || !lambda || !out))) return fx_fail(FX_EINVAL, "bad batch");
-    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI)
+    if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI && mode != FX_MODE_MIS)
         return fx_fail(FX_EINVAL, "unknown mode %d", mode);
     // sigma and lambda here; the patterns are checked when their plans are
     // built, for the whole batch before any device work
@@ -296,7 +306,7 @@ extern "C" fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_patter
         reqs[i].pattern = &pats[i];
         reqs[i].sigma = sigma[i];
         reqs[i].lambda = lambda[i];
-        reqs[i].kind = mode == FX_MODE_FULL ? FX_Q_FULL : (mode == FX_MODE_MNI ? FX_Q_MNI : FX_Q_VERDICT);
+        reqs[i].kind = fx_query_kind(mode);
         reqs[i].out = &res[i];
     }
     FX_TRY(fx_engine_run(g, reqs, g->ctx->params.max_active));

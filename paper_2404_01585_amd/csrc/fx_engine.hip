@@ -209,6 +209,9 @@ struct FxQuery {
     int lane = 0;
     int exit = FX_EXIT_END;                // how the query ended (fx_result.exit)
     uint64_t last_ufiltered = 0;           // candidates U has removed, as of the last step read back
+    int32_t *mis_rows = nullptr;           // exact-MIS mode: every embedding, collected on the device
+    uint64_t *mis_hash = nullptr;
+    FxMisOut *mis_out = nullptr;
     bool chain_done = false;               // finished in a device-scheduled chain
     int64_t listed = 0;
     // the segment of the current step (-1: none)
@@ -234,6 +237,8 @@ size_t region_size(const FxQuery &q, int64_t nv)
         const size_t k = (size_t)nv / n + 1;
         b += align256(k * n * 4) + align256(k * 8);
     }
+    if (q.req->kind == FX_Q_MIS)
+        b += align256((size_t)FX_MIS_MAX_EMB * n * 4) + align256((size_t)FX_MIS_MAX_EMB * 8) + align256(sizeof(FxMisOut));
     return b;
 }
 
@@ -273,6 +278,14 @@ void carve(FxQuery &q, int64_t nv)
         const size_t k = (size_t)nv / n + 1;
         q.sel_rows = (int32_t *)take(k * n * 4);
         q.sel_rank = (int64_t *)take(k * 8);
+    }
+    q.mis_rows = nullptr;
+    q.mis_hash = nullptr;
+    q.mis_out = nullptr;
+    if (q.req->kind == FX_Q_MIS) {
+        q.mis_rows = (int32_t *)take((size_t)FX_MIS_MAX_EMB * n * 4);
+        q.mis_hash = (uint64_t *)take((size_t)FX_MIS_MAX_EMB * 8);
+        q.mis_out = (FxMisOut *)take(sizeof(FxMisOut));
     }
 }
 
@@ -419,7 +432,8 @@ std::unique_ptr<FxQuery> FxEngine::prepare(FxRequest *r) const
     if (r->kind != FX_Q_LIST) {
         r->status = fx_tau_checked(r->sigma, r->lambda, q->n, &q->tau);
         if (r->status != FX_OK) return q;
-        if (r->kind == FX_Q_MNI) q->tau = r->sigma;  // the minimum-image threshold is sigma itself
+        // the minimum-image and maximum-independent-set thresholds are sigma itself
+        if (r->kind == FX_Q_MNI || r->kind == FX_Q_MIS) q->tau = r->sigma;
         q->tau_eff = std::max<int64_t>(q->tau, 1);
     }
     return q;
@@ -469,7 +483,7 @@ void FxEngine::enqueue(std::unique_ptr<FxQuery> q)
         *r->out = res;
         return done(r);
     }
-    q->phase = r->kind == FX_Q_LIST ? PH_LIST : (r->kind == FX_Q_MNI ? PH_COUNT : PH_SUPPORT);
+    q->phase = (r->kind == FX_Q_LIST || r->kind == FX_Q_MIS) ? PH_LIST : (r->kind == FX_Q_MNI ? PH_COUNT : PH_SUPPORT);
     q->cap = P_.slice_rows;
     q->last_span = (uint32_t)std::min<int64_t>(P_.last_span_init, q->cap);
     for (auto &r : q->rate) r = 1.0;
@@ -479,7 +493,33 @@ void FxEngine::enqueue(std::unique_ptr<FxQuery> q)
 fx_status FxEngine::finish(FxQuery &q, const FxSummary &S)
 {
     FxRequest &r = *q.req;
-    if (q.phase == PH_LIST) {
+    if (q.phase == PH_LIST && r.kind == FX_Q_MIS) {
+        fx_result res{};
+        res.tau = q.tau;
+        res.steps = q.steps;
+        res.status = FX_OK;
+        res.exit = FX_EXIT_END;
+        res.embedding_count = q.listed;
+        res.device_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0_).count();
+        if (q.listed > FX_MIS_MAX_EMB) {
+            r.status = fx_fail(FX_ELIMIT, "exact MIS: more than %d embeddings", FX_MIS_MAX_EMB);
+        } else {
+            FxMisOut mo{};
+            hipStream_t st = ls_[q.lane];
+            FX_HIP(fx_launch_mis(st, q.mis_rows, (int32_t)q.listed, q.n, q.mis_hash, q.mis_out));
+            FX_HIP(hipMemcpyAsync(&mo, q.mis_out, sizeof(mo), hipMemcpyDeviceToHost, st));
+            FX_HIP(hipStreamSynchronize(st));
+            if (mo.status == 1)
+                r.status = fx_fail(FX_ELIMIT, "exact MIS: %d distinct vertex sets, at most %d", mo.sets,
+                                   FX_MIS_MAX_SETS);
+            else if (mo.status != 0)
+                r.status = fx_fail(FX_ELIMIT, "exact MIS: the search needs more than %u nodes", FX_MIS_MAX_NODES);
+            res.support = mo.mis;
+            res.rounds = (int32_t)std::min<uint64_t>(mo.nodes, INT32_MAX);
+        }
+        res.frequent = res.support >= q.tau_eff;
+        *r.out = res;
+    } else if (q.phase == PH_LIST) {
         *r.list_count = q.listed;  // rows written at the last level (a capped slice re-offers the rest)
     } else {
         fx_result res{};
@@ -619,6 +659,7 @@ fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
     old.plan = q.plan;
     old.sel_rows = q.sel_rows;
     old.sel_rank = q.sel_rank;
+    old.mis_rows = q.mis_rows;
     q.cap = new_cap;
     const size_t bytes = region_size(q, nv);
     void *region = nullptr;
@@ -654,6 +695,8 @@ fx_status FxEngine::promote(FxQuery &q, int64_t new_cap)
         FX_TRY(cp(q.sel_rows, old.sel_rows, k * q.n * 4));
         FX_TRY(cp(q.sel_rank, old.sel_rank, k * 8));
     }
+    if (q.mis_rows && q.listed > 0)  // the embeddings collected so far (exact-MIS mode)
+        FX_TRY(cp(q.mis_rows, old.mis_rows, (size_t)std::min<int64_t>(q.listed, FX_MIS_MAX_EMB) * q.n * 4));
     // the copies read the old region on this lane's stream: it goes back to
     // the pool once the lane's next step has been waited for (the other lanes
     // run on other streams and could reuse it too early)
@@ -977,6 +1020,12 @@ fx_status FxEngine::collect(int g, double &waited)
             q.cur[l + 1] = 0;
         } else if (q.seg_kind == FX_SEG_GREEDY) {
             q.rank_base += (int64_t)N;
+        } else if (q.seg_kind == FX_SEG_LIST && q.req->kind == FX_Q_MIS) {
+            // collected on the device; past the limit the query ends with an error
+            if (q.listed + (int64_t)N <= FX_MIS_MAX_EMB && N > 0)
+                FX_HIP(hipMemcpyAsync(q.mis_rows + q.listed * q.n, q.lev[q.n].rows, (size_t)N * q.n * 4,
+                                      hipMemcpyDeviceToDevice, ls_[g]));
+            q.listed += (int64_t)N;
         } else if (q.seg_kind == FX_SEG_LIST) {
             FxRequest &r = *q.req;
             const int64_t take = std::min<int64_t>((int64_t)N, std::max<int64_t>(0, r.list_cap - q.listed));
@@ -1018,6 +1067,7 @@ fx_status FxEngine::collect(int g, double &waited)
         }
         // (the minimum-image support needs every embedding: the cap only caps its count)
         if (q.phase == PH_COUNT && q.req->kind != FX_Q_MNI && (int64_t)S.count >= P_.count_cap) fin = true;
+        if (q.req->kind == FX_Q_MIS && q.listed > FX_MIS_MAX_EMB) fin = true;  // reported as FX_ELIMIT
         if (!fin && q.deep < 0) {
             if (q.phase == PH_SUPPORT && q.req->kind == FX_Q_FULL) {
                 q.phase = PH_COUNT;  // level 0 is unchanged; restart the cursors

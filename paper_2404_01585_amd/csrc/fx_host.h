@@ -205,11 +205,12 @@ struct HostPlan {
 };
 
 fx_status fx_check_pattern(const fx_pattern *p);
+int32_t fx_query_kind(int32_t mode);  // FX_MODE_* -> FX_Q_*
 fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp);
 fx_status fx_tau_checked(int64_t sigma, double lambda, int32_t n, int64_t *tau_out);
 
 // One request to the engine.
-enum FxQueryKind { FX_Q_FULL = 0, FX_Q_VERDICT = 1, FX_Q_LIST = 2, FX_Q_MNI = 3 };
+enum FxQueryKind { FX_Q_FULL = 0, FX_Q_VERDICT = 1, FX_Q_LIST = 2, FX_Q_MNI = 3, FX_Q_MIS = 4 };
 
 struct FxRequest {
     const fx_pattern *pattern = nullptr;

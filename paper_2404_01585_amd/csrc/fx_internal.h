@@ -234,7 +234,25 @@ struct FxChainCtl {
     uint64_t budget;        // candidates per step, all queries together
 };
 
+// Exact maximum independent set of a pattern's embeddings (Section 2.4.2),
+// for small instances: at most FX_MIS_MAX_EMB embeddings, at most
+// FX_MIS_MAX_SETS distinct vertex sets, at most FX_MIS_MAX_NODES search nodes.
+#define FX_MIS_MAX_EMB 4096
+#define FX_MIS_MAX_SETS 256
+#define FX_MIS_MAX_NODES (1u << 24)
+
+struct FxMisOut {
+    int64_t mis;        // size of a maximum independent set
+    int32_t sets;       // distinct vertex sets
+    int32_t status;     // 0 ok, 1 too many distinct sets, 2 the search budget ran out
+    uint64_t nodes;     // branch-and-bound nodes visited
+};
+
 // Launchers (fx_kernels.hip).  All return the hipError_t of the launches.
+// The exact maximum independent set of `count` embeddings of n vertices
+// (rows, device, sorted in place), into *out.
+hipError_t fx_launch_mis(hipStream_t s, int32_t *rows, int32_t count, int32_t n, uint64_t *hash_scratch,
+                         FxMisOut *out);
 hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *inits, int32_t ninit);
 // Minimum-image support from n image bitmaps of `words` words each: counts[j]
 // = set bits of bitmap j, then *out = min_j counts[j].

@@ -1354,6 +1354,223 @@ __global__ void k_sched(FxChainQuery *qs, FxChainCtl *ctl, FxSeg *segs, uint32_t
     ctl->nblocks = nblocks;
 }
 
+// ---------------------------------------------------------------------------
+// Exact maximum independent set (Section 2.4.2) for small instances: one
+// workgroup.  Embeddings with the same vertex set are interchangeable for
+// independence, so each row's ids are sorted, rows are reduced to distinct
+// sets (first occurrence kept), the overlap relation of the sets becomes LDS
+// bitsets, and one lane searches for a largest independent set by branch and
+// bound: take the open set that overlaps most open sets, search with it
+// (dropping everything it overlaps) and without it, and prune a branch that
+// cannot beat the best found.  Bounds: independent sets never share a vertex,
+// so among the open sets at most one per distinct smallest vertex, and one
+// per distinct largest vertex, can be chosen -- and at most (the vertices the
+// open sets cover) / n of them (when the sets cover at most 256 vertices).
+// ---------------------------------------------------------------------------
+
+constexpr int kMisWords = FX_MIS_MAX_SETS / 64;
+
+__global__ __launch_bounds__(256) void k_mis(int32_t *rows, int32_t count, int32_t n, uint64_t *hash_scratch,
+                                             FxMisOut *out)
+{
+    __shared__ int32_t set_first[FX_MIS_MAX_SETS];     // row of each distinct set
+    __shared__ uint8_t grp_lo[FX_MIS_MAX_SETS];        // class of the set's smallest vertex
+    __shared__ uint8_t grp_hi[FX_MIS_MAX_SETS];        // class of the set's largest vertex
+    __shared__ uint64_t vmask[FX_MIS_MAX_SETS][kMisWords];  // the set's vertices, as local ids
+    __shared__ int32_t local_ids[FX_MIS_MAX_SETS];     // data vertex of each local id
+    __shared__ int32_t nlocal;
+    __shared__ uint64_t adj[FX_MIS_MAX_SETS][kMisWords];  // overlap bitsets
+    __shared__ uint64_t stack_p[FX_MIS_MAX_SETS + 2][kMisWords];
+    __shared__ int32_t stack_size[FX_MIS_MAX_SETS + 2];
+    __shared__ int32_t nsets;
+    // 1. sort every row's vertex ids; hash the sorted row
+    for (int32_t r = threadIdx.x; r < count; r += blockDim.x) {
+        int32_t *row = rows + (int64_t)r * n;
+        for (int32_t a = 1; a < n; a++) {  // insertion sort, n <= 16
+            const int32_t v = row[a];
+            int32_t b = a - 1;
+            while (b >= 0 && row[b] > v) {
+                row[b + 1] = row[b];
+                b--;
+            }
+            row[b + 1] = v;
+        }
+        uint64_t h = kSeed1;
+        for (int32_t a = 0; a < n; a++) h = mix64(h ^ (uint64_t)(uint32_t)row[a]);
+        hash_scratch[r] = h;
+    }
+    __syncthreads();
+    // 2. distinct sets: row r is kept when no earlier row holds the same set
+    //    (taken in row order by one wave so the kept rows stay ordered; the
+    //    running count is a wave-uniform register)
+    if (threadIdx.x < 64) {
+        int32_t kept = 0;
+        for (int32_t base = 0; base < count; base += 64) {
+            const int32_t r = base + (int32_t)threadIdx.x;
+            bool first = r < count;
+            if (first) {
+                const uint64_t h = hash_scratch[r];
+                const int32_t *row = rows + (int64_t)r * n;
+                for (int32_t q = 0; q < r && first; q++) {
+                    if (hash_scratch[q] != h) continue;
+                    const int32_t *other = rows + (int64_t)q * n;
+                    bool same = true;
+                    for (int32_t a = 0; a < n; a++) same = same && other[a] == row[a];
+                    first = !same;
+                }
+            }
+            const uint64_t m = __ballot(first);
+            const int32_t k = kept + __popcll(m & lanemask_lt());
+            if (first && k < FX_MIS_MAX_SETS) set_first[k] = r;
+            kept += __popcll(m);
+        }
+        if (threadIdx.x == 0) nsets = kept;
+    }
+    __syncthreads();
+    const int32_t K = nsets < FX_MIS_MAX_SETS ? nsets : FX_MIS_MAX_SETS;
+    if (nsets > FX_MIS_MAX_SETS) {
+        if (threadIdx.x == 0) {
+            out->mis = -1;
+            out->sets = nsets;
+            out->status = 1;
+            out->nodes = 0;
+        }
+        return;
+    }
+    // 3. overlap bitsets of the distinct sets (sorted rows: a merge)
+    for (int32_t i = threadIdx.x; i < FX_MIS_MAX_SETS; i += blockDim.x)
+        for (int w = 0; w < kMisWords; w++) adj[i][w] = 0;
+    __syncthreads();
+    for (int32_t pq = threadIdx.x; pq < K * K; pq += blockDim.x) {
+        const int32_t i = pq / K, j = pq % K;
+        if (i == j) continue;
+        const int32_t *a = rows + (int64_t)set_first[i] * n;
+        const int32_t *b = rows + (int64_t)set_first[j] * n;
+        int32_t x = 0, y = 0;
+        bool meet = false;
+        while (x < n && y < n && !meet) {
+            if (a[x] == b[y]) meet = true;
+            else if (a[x] < b[y]) x++;
+            else y++;
+        }
+        if (meet) atomicOr((unsigned long long *)&adj[i][j >> 6], 1ull << (j & 63));
+    }
+    // classes of equal smallest (largest) vertex, numbered by their first set
+    for (int32_t i = threadIdx.x; i < K; i += blockDim.x) {
+        const int32_t *a = rows + (int64_t)set_first[i] * n;
+        int32_t lo = i, hi = i;
+        for (int32_t j = 0; j < i; j++) {
+            const int32_t *b = rows + (int64_t)set_first[j] * n;
+            if (lo == i && b[0] == a[0]) lo = j;
+            if (hi == i && b[n - 1] == a[n - 1]) hi = j;
+        }
+        grp_lo[i] = (uint8_t)lo;
+        grp_hi[i] = (uint8_t)hi;
+    }
+    // local ids of the vertices the sets cover (at most 256, else no cover bound)
+    if (threadIdx.x == 0) {
+        int32_t nl = 0;
+        for (int32_t i = 0; i < K && nl >= 0; i++) {
+            const int32_t *a = rows + (int64_t)set_first[i] * n;
+            for (int w = 0; w < kMisWords; w++) vmask[i][w] = 0;
+            for (int32_t x = 0; x < n && nl >= 0; x++) {
+                int32_t id = -1;
+                for (int32_t q = 0; q < nl; q++)
+                    if (local_ids[q] == a[x]) id = q;
+                if (id < 0) {
+                    if (nl == FX_MIS_MAX_SETS) {
+                        nl = -1;
+                        break;
+                    }
+                    local_ids[nl] = a[x];
+                    id = nl++;
+                }
+                vmask[i][id >> 6] |= 1ull << (id & 63);
+            }
+        }
+        nlocal = nl;
+    }
+    __syncthreads();
+    // 4. branch and bound (one lane)
+    if (threadIdx.x != 0) return;
+    const bool cover_bound = nlocal >= 0;
+    int32_t best = 0;
+    uint64_t nodes = 0;
+    int32_t top = 0;
+    for (int w = 0; w < kMisWords; w++) {
+        const int32_t lo = w * 64;
+        stack_p[0][w] = K >= lo + 64 ? ~0ull : (K > lo ? ((1ull << (K - lo)) - 1) : 0ull);
+    }
+    stack_size[0] = 0;
+    top = 1;
+    int32_t status = 0;
+    while (top > 0) {
+        top--;
+        uint64_t P[kMisWords];
+        int32_t open = 0;
+        for (int w = 0; w < kMisWords; w++) {
+            P[w] = stack_p[top][w];
+            open += __popcll(P[w]);
+        }
+        const int32_t size = stack_size[top];
+        if (++nodes > FX_MIS_MAX_NODES) {
+            status = 2;
+            break;
+        }
+        if (size + open <= best) continue;
+        if (open == 0) {
+            best = size;  // size > best here
+            continue;
+        }
+        // the bounds, and the open set with the most open neighbours
+        uint64_t cl[kMisWords] = {}, ch[kMisWords] = {}, cv[kMisWords] = {};
+        int32_t v = -1, vdeg = -1;
+        for (int w = 0; w < kMisWords; w++) {
+            uint64_t m = P[w];
+            while (m) {
+                const int32_t i = w * 64 + __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                cl[grp_lo[i] >> 6] |= 1ull << (grp_lo[i] & 63);
+                ch[grp_hi[i] >> 6] |= 1ull << (grp_hi[i] & 63);
+                if (cover_bound)
+                    for (int u = 0; u < kMisWords; u++) cv[u] |= vmask[i][u];
+                int32_t d = 0;
+                for (int u = 0; u < kMisWords; u++) d += __popcll(adj[i][u] & P[u]);
+                if (d > vdeg) {
+                    vdeg = d;
+                    v = i;
+                }
+            }
+        }
+        int32_t blo = 0, bhi = 0, bcv = 0;
+        for (int w = 0; w < kMisWords; w++) {
+            blo += __popcll(cl[w]);
+            bhi += __popcll(ch[w]);
+            bcv += __popcll(cv[w]);
+        }
+        int32_t bound = blo < bhi ? blo : bhi;
+        if (cover_bound && bcv / n < bound) bound = bcv / n;
+        if (size + bound <= best) continue;
+        if (vdeg == 0) {  // no open set overlaps another: take them all
+            best = size + open > best ? size + open : best;
+            continue;
+        }
+        // without v (searched second), then with v (searched first)
+        for (int w = 0; w < kMisWords; w++) stack_p[top][w] = P[w];
+        stack_p[top][v >> 6] &= ~(1ull << (v & 63));
+        stack_size[top] = size;
+        top++;
+        for (int w = 0; w < kMisWords; w++) stack_p[top][w] = P[w] & ~adj[v][w];
+        stack_p[top][v >> 6] &= ~(1ull << (v & 63));
+        stack_size[top] = size + 1;
+        top++;
+    }
+    out->mis = status ? -1 : best;
+    out->sets = K;
+    out->status = status;
+    out->nodes = nodes;
+}
+
 // Admission / phase start of queries: level 0 is the single empty partial
 // whose candidate run is the label bucket of pattern vertex 0.
 __global__ void k_init(FxGraphDev g, const FxInit *__restrict__ inits)
@@ -1551,4 +1768,12 @@ hipError_t fx_launch_chain(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq,
                                      loff);
     return launch_chain_width<FX_MAXN>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, cand, bcnt, boff, lsum,
                                        loff);
+}
+
+hipError_t fx_launch_mis(hipStream_t s, int32_t *rows, int32_t count, int32_t n, uint64_t *hash_scratch,
+                         FxMisOut *out)
+{
+    if (n < 1 || n > FX_MAXN || count < 0 || count > FX_MIS_MAX_EMB) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mis, dim3(1), dim3(256), 0, s, rows, count, n, hash_scratch, out);
+    return hipGetLastError();
 }

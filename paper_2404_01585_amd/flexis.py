@@ -31,6 +31,7 @@ FX_ELIMIT = -8
 MODE_FULL = 0
 MODE_VERDICT = 1
 MODE_MNI = 2  # minimum-image support (Section 2.4.4) instead of the greedy
+MODE_MIS = 3  # exact maximum independent set (Section 2.4.2), small instances
 
 _STATUS_NAMES = {0: "FX_OK", -1: "FX_EINVAL", -2: "FX_EGRAPH", -3: "FX_EPATTERN", -4: "FX_ENOMEM",
                  -5: "FX_EDEVICE", -6: "FX_EBUSY", -7: "FX_ETIMEOUT", -8: "FX_ELIMIT"}

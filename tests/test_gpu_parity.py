@@ -709,3 +709,86 @@ def test_step_checks_on_real_steps(torch_cuda, er1k):
         for p in pats[:4]:
             list_match(dg, g, p)
     c.close()
+
+
+def test_exact_mis_mode(ctx, ctx_small):
+    """Exact maximum independent set (Section 2.4.2) as a support mode: the
+    paper's printed values (the running example's P1: 2; the tightness example
+    of Theorem 1: 4), brute force over all independent sets on tiny graphs,
+    and Theorem 1's bounds around the greedy support (m <= M <= m n)."""
+    fx1 = load_fixture("running_example.txt")
+    fx2 = load_fixture("tight_bound.txt")
+    with ctx.load_graph(fx1["D"]) as dg:
+        r = dg.support(fx1["P1"], 2, 1.0, fx.MODE_MIS)
+        assert r["support"] == 2 and r["embedding_count"] == 6 and r["tau"] == 2 and r["frequent"] == 1
+        assert dg.support(fx1["P1"], 3, 1.0, fx.MODE_MIS)["frequent"] == 0
+    with ctx.load_graph(fx2["Dm"]) as dg:
+        r = dg.support(fx2["Pm"], 1, 1.0, fx.MODE_MIS)
+        assert r["support"] == 4 and r["embedding_count"] == 48
+        greedy = dg.support(fx2["Pm"], 1, 1.0, fx.MODE_FULL)["support"]
+        assert greedy == 1  # the bound m <= M <= m n is tight here: M = n m
+    n_checked = 0
+    for idx, g, p in _tiny_cases(60, seed=606):
+        c = ctx if idx % 2 else ctx_small
+        with c.load_graph(g) as dg:
+            embs = O.brute_embeddings(g, p) if g.num_vertices <= 16 and p.n <= 4 else None
+            full = O.query(g, p, 2, 1.0, O.FULL)
+            if full["embedding_count"] > 4096:  # beyond the exact mode's size limit
+                with pytest.raises(fx.FxError) as e:
+                    dg.support(p, 2, 1.0, fx.MODE_MIS)
+                assert e.value.status == fx.FX_ELIMIT
+                continue
+            _, rows = O.enumerate_embeddings(g, p, cap=4096)
+            if len({frozenset(int(v) for v in row) for row in rows}) > 256:  # beyond the distinct-set limit
+                with pytest.raises(fx.FxError) as e:
+                    dg.support(p, 2, 1.0, fx.MODE_MIS)
+                assert e.value.status == fx.FX_ELIMIT
+                continue
+            r = dg.support(p, 2, 1.0, fx.MODE_MIS)
+            _say("mis tiny", idx, "nv", g.num_vertices, "n", p.n, "mis", r["support"])
+            assert r["embedding_count"] == full["embedding_count"]
+            m = full["support"]
+            assert m <= r["support"] <= m * p.n  # Theorem 1
+            if embs is not None:
+                assert r["support"] == O.brute_mis(embs)
+                n_checked += 1
+    assert n_checked >= 10
+    # a batch gives the same values; too large an instance is refused
+    g = csr_from_edges(12, list(range(11)), list(range(1, 12)), [0] * 11, [0] * 12)
+    pats = [Pattern([0, 0], [(0, 1)], [0]), Pattern([0, 0, 0], [(0, 1), (1, 2)], [0, 0])]
+    with ctx.load_graph(g) as dg:
+        got = dg.support_batch(pats, [1, 1], [1.0, 1.0], fx.MODE_MIS)
+        assert [r["support"] for r in got] == [6, 4]  # a 12-vertex path: 6 disjoint edges, 4 disjoint 3-paths
+    def complete(k):
+        e = [(a, b) for a in range(k) for b in range(a + 1, k)]
+        return csr_from_edges(k, [a for a, _ in e], [b for _, b in e], [0] * len(e), [0] * k)
+
+    with ctx.load_graph(complete(20)) as dg:  # 20 * 19 * 18 embeddings of a 3-path: more than 4096
+        with pytest.raises(fx.FxError) as e:
+            dg.support(Pattern([0, 0, 0], [(0, 1), (1, 2)], [0, 0]), 1, 1.0, fx.MODE_MIS)
+        assert e.value.status == fx.FX_ELIMIT
+    with ctx.load_graph(complete(30)) as dg:  # 435 distinct edges: more than 256 vertex sets
+        with pytest.raises(fx.FxError) as e:
+            dg.support(Pattern([0, 0], [(0, 1)], [0]), 1, 1.0, fx.MODE_MIS)
+        assert e.value.status == fx.FX_ELIMIT
+        assert dg.support(Pattern([0, 0], [(0, 1)], [0]), 1, 1.0, fx.MODE_FULL)["support"] == 15
+
+
+def test_exact_mis_across_stack_growth(torch_cuda):
+    """Exact MIS of a query whose stack grows while it enumerates (the
+    embeddings collected so far move with it): 3-vertex paths in a 30-vertex
+    path among 300 isolated vertices (many roots, few embeddings); a path of
+    k vertices holds floor(k / 3) disjoint 3-paths."""
+    nv = 330
+    g = csr_from_edges(nv, list(range(29)), list(range(1, 30)), [0] * 29, [0] * nv)
+    p = Pattern([0, 0, 0], [(0, 1), (1, 2)], [0, 0])
+    c = fx.Context(device=0, slice_rows=64, run_index_bytes=-1)
+    c.set("promote_after", 1)
+    with c.load_graph(g) as dg:
+        c.stats(reset=True)
+        r = dg.support(p, 1, 1.0, fx.MODE_MIS)
+        st = c.stats()
+        _say("mis growth", r, st["promotions"])
+        assert r["support"] == 10 and r["embedding_count"] == 2 * 28
+        assert st["promotions"] > 0
+    c.close()
