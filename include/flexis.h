@@ -133,8 +133,17 @@ fx_status fx_ctx_destroy(fx_ctx *ctx);
  *   on_device         0: the arrays are host memory; 1: device memory.  Either
  *                     way the library validates and builds its own copy, so the
  *                     arrays may be freed after the call.
+ *   directed          0: undirected, as above.  1: a directed graph (Section 2.2
+ *                     states the problem for labeled, directed graphs): row u
+ *                     lists the heads v of the edges u -> v, strictly ascending,
+ *                     no self-loops; (u,v) and (v,u) may both be present with
+ *                     their own labels; no symmetry is required.  Patterns of a
+ *                     directed graph are directed: fx_pattern edge (a, b) is
+ *                     a -> b, and an embedding maps it onto a data edge
+ *                     f(a) -> f(b) with the same label.
  * Errors: FX_EGRAPH for any violation above, FX_ELIMIT for more than 65535
- * distinct vertex or edge labels or more than 2^31-1 vertices. */
+ * distinct vertex labels, more than 65535 (32767 directed) distinct edge
+ * labels or more than 2^31-1 vertices. */
 typedef struct {
     int64_t num_vertices;
     int64_t num_adj;
@@ -144,6 +153,7 @@ typedef struct {
     const int32_t *vlabel;
     const int32_t *elabel;
     int32_t on_device;
+    int32_t directed;
 } fx_graph_desc;
 
 fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *desc, fx_graph **out);
@@ -152,7 +162,9 @@ fx_status fx_graph_destroy(fx_graph *g);
 /* Pattern: a connected simple labeled graph with 1 <= n <= 16 vertices,
  * numbered 0..n-1 as submitted (the numbering fixes the greedy order, see
  * fx_support).  edges holds m pairs (a, b), elabel m labels or NULL for all
- * zero.  The pattern is copied at call time.
+ * zero.  For a directed data graph the pair (a, b) is the edge a -> b, (a, b)
+ * and (b, a) may both be present, and connected means weakly connected.  The
+ * pattern is copied at call time.
  * Errors: FX_EPATTERN (disconnected, loops, repeated edges, bad endpoints),
  * FX_ELIMIT (n > 16). */
 typedef struct {

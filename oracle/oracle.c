@@ -20,6 +20,10 @@
  *     flag, which selects embeddings greedily in lexicographic order.
  *   - the threshold tau (Section 3.1.1, the equation for tau).
  *   - MNI (Section 2.4.4), used only as an invariant (mIS <= MNI).
+ *   - directed graphs (Section 2.2 states the problem for labeled, directed
+ *     graphs): with og_graph.directed set, row u lists the heads of the edges
+ *     u -> v, a pattern edge (a, b) is a -> b, and an embedding maps it onto
+ *     a data edge f(a) -> f(b) with the same label.
  *
  * Everything is exact integer arithmetic except tau's lambda, which is
  * quantised to parts per million before the integer floor (a reading of the
@@ -52,6 +56,7 @@ typedef struct {
     const int32_t *col;     /* ascending per row */
     const int32_t *vlabel;  /* [nv] */
     const int32_t *elabel;  /* [row_ptr[nv]] */
+    int32_t directed;       /* 0: symmetric rows; 1: row u holds the heads of u's edges */
 } og_graph;
 
 typedef struct {
@@ -94,6 +99,14 @@ static int32_t og_edge_label(const og_graph *g, int32_t u, int32_t v)
     return -1;
 }
 
+/* Label of the pattern edge a -> b (directed), or -1.                  */
+static int32_t og_pattern_arc(const og_pattern *p, int a, int b)
+{
+    for (int k = 0; k < p->m; k++)
+        if (p->edges[2 * k] == a && p->edges[2 * k + 1] == b) return p->elabel ? p->elabel[k] : 0;
+    return -1;
+}
+
 /* Label of pattern edge {a, b}, or -1.                                 */
 static int32_t og_pattern_edge(const og_pattern *p, int a, int b)
 {
@@ -122,7 +135,9 @@ struct og_dfs {
     int n;
     int32_t f[OG_MAXN];
     int32_t back_lab[OG_MAXN][OG_MAXN]; /* label of pattern edge (a, i), a < i, or -1 */
-    int first_back[OG_MAXN];            /* smallest earlier neighbour of i, or -1 */
+    int32_t arc_lab[OG_MAXN][OG_MAXN];  /* directed: label of the pattern edge a -> b, or -1 */
+    int first_back[OG_MAXN];            /* smallest earlier neighbour of i, or -1 (directed: the
+                                           smallest earlier a with an edge a -> i) */
     const uint8_t *skip;                /* optional: data vertices that may not be used */
     og_visit_fn visit;
     void *user;
@@ -135,6 +150,13 @@ static int og_feasible(og_dfs *s, int i, int32_t w)
     if (s->skip && s->skip[w]) return 0;
     for (int a = 0; a < i; a++)
         if (s->f[a] == w) return 0; /* injective */
+    if (s->g->directed) {
+        for (int a = 0; a < i; a++) {
+            if (s->arc_lab[a][i] >= 0 && og_edge_label(s->g, s->f[a], w) != s->arc_lab[a][i]) return 0;
+            if (s->arc_lab[i][a] >= 0 && og_edge_label(s->g, w, s->f[a]) != s->arc_lab[i][a]) return 0;
+        }
+        return 1;
+    }
     for (int a = 0; a < i; a++) {
         int32_t want = s->back_lab[a][i];
         if (want < 0) continue;
@@ -180,16 +202,23 @@ static void og_dfs_init(og_dfs *s, const og_graph *g, const og_pattern *p)
         s->first_back[i] = -1;
         for (int a = 0; a < p->n; a++) s->back_lab[a][i] = -1;
     }
+    for (int a = 0; a < p->n; a++)
+        for (int b = 0; b < p->n; b++) s->arc_lab[a][b] = g->directed ? og_pattern_arc(p, a, b) : -1;
     for (int i = 0; i < p->n; i++)
         for (int a = 0; a < i; a++) {
             s->back_lab[a][i] = og_pattern_edge(p, a, i);
-            if (s->back_lab[a][i] >= 0 && s->first_back[i] < 0) s->first_back[i] = a;
+            /* candidates of i come from the row of f(a): in a directed graph
+             * that row holds f(a)'s out-neighbours, so only an edge a -> i */
+            const int from = g->directed ? s->arc_lab[a][i] >= 0 : s->back_lab[a][i] >= 0;
+            if (from && s->first_back[i] < 0) s->first_back[i] = a;
         }
 }
 
 /* Rejects malformed patterns: n outside [1, 16], bad endpoints, loops,
- * repeated edges, or a disconnected pattern.  Returns 0 when valid. */
-int og_check_pattern(const og_pattern *p)
+ * repeated edges, or a disconnected pattern.  Returns 0 when valid.  With
+ * `directed`, (a, b) and (b, a) are different edges and connected means
+ * weakly connected. */
+static int og_check_pattern_d(const og_pattern *p, int directed)
 {
     if (p->n < 1 || p->n > OG_MAXN || p->m < 0) return -1;
     for (int k = 0; k < p->m; k++) {
@@ -197,7 +226,7 @@ int og_check_pattern(const og_pattern *p)
         if (a < 0 || b < 0 || a >= p->n || b >= p->n || a == b) return -1;
         for (int j = 0; j < k; j++) {
             int x = p->edges[2 * j], y = p->edges[2 * j + 1];
-            if ((x == a && y == b) || (x == b && y == a)) return -1;
+            if ((x == a && y == b) || (!directed && x == b && y == a)) return -1;
         }
     }
     /* connectivity by repeated relaxation */
@@ -212,6 +241,10 @@ int og_check_pattern(const og_pattern *p)
         if (!reach[i]) return -1;
     return 0;
 }
+
+int og_check_pattern(const og_pattern *p) { return og_check_pattern_d(p, 0); }
+
+static int og_check(const og_graph *g, const og_pattern *p) { return og_check_pattern_d(p, g->directed); }
 
 /* ------------------------------------------------------------------ */
 /* Literal form: list M, sort it, then the greedy (Section 2.4.3).     */
@@ -248,7 +281,7 @@ static int og_cmp_rows(const void *x, const void *y)
  * When |M| > cap the rows written are the lexicographically first cap. */
 int64_t og_enumerate(const og_graph *g, const og_pattern *p, int32_t *out, int64_t cap)
 {
-    if (og_check_pattern(p)) return -1;
+    if (og_check(g, p)) return -1;
     og_dfs s;
     og_dfs_init(&s, g, p);
     og_list L = {out, 0, cap, 1};
@@ -331,7 +364,7 @@ static int og_visit_stream(og_dfs *s)
 int64_t og_support_stream(const og_graph *g, const og_pattern *p, int64_t stop_at,
                           int32_t *sel_out, int64_t sel_cap)
 {
-    if (og_check_pattern(p)) return -1;
+    if (og_check(g, p)) return -1;
     og_dfs s;
     og_dfs_init(&s, g, p);
     og_stream S;
@@ -409,7 +442,7 @@ void og_rows_digest(const int32_t *rows, int64_t count, int32_t n, uint64_t *dig
 int og_count(const og_graph *g, const og_pattern *p, int64_t cap, int64_t *count_out,
              int32_t *saturated_out, uint64_t *digest_out)
 {
-    if (og_check_pattern(p)) return -1;
+    if (og_check(g, p)) return -1;
     og_dfs s;
     og_dfs_init(&s, g, p);
     og_counter C = {0, cap, 0, 0};
@@ -442,7 +475,7 @@ static int og_visit_mni(og_dfs *s)
 
 int64_t og_mni(const og_graph *g, const og_pattern *p)
 {
-    if (og_check_pattern(p)) return -1;
+    if (og_check(g, p)) return -1;
     og_dfs s;
     og_dfs_init(&s, g, p);
     og_mni_state M;

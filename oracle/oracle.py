@@ -41,7 +41,7 @@ def build(force: bool = False) -> str:
 
 class _OgGraph(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
-                ("vlabel", ctypes.c_void_p), ("elabel", ctypes.c_void_p)]
+                ("vlabel", ctypes.c_void_p), ("elabel", ctypes.c_void_p), ("directed", ctypes.c_int32)]
 
 
 class _OgPattern(ctypes.Structure):
@@ -89,20 +89,23 @@ def _ptr(a: np.ndarray) -> int:
 
 
 class OracleGraph:
-    """Holds the arrays alive for the C structs."""
+    """Holds the arrays alive for the C structs.  directed: row u lists the
+    heads of the edges u -> v (Section 2.2's directed graphs)."""
 
-    def __init__(self, row_ptr, col, vlabel, elabel=None):
+    def __init__(self, row_ptr, col, vlabel, elabel=None, directed=False):
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
         self.vlabel = np.ascontiguousarray(vlabel, dtype=np.int32)
         self.elabel = (np.zeros(self.col.shape[0], dtype=np.int32) if elabel is None
                        else np.ascontiguousarray(elabel, dtype=np.int32))
         self.nv = self.row_ptr.shape[0] - 1
-        self.c = _OgGraph(self.nv, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.vlabel), _ptr(self.elabel))
+        self.directed = bool(directed)
+        self.c = _OgGraph(self.nv, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.vlabel), _ptr(self.elabel),
+                          1 if directed else 0)
 
     @classmethod
     def of(cls, g) -> "OracleGraph":
-        return cls(g.row_ptr, g.col, g.vlabel, g.elabel)
+        return cls(g.row_ptr, g.col, g.vlabel, g.elabel, getattr(g, "directed", False))
 
 
 class OraclePattern:
@@ -258,7 +261,9 @@ def _adj_dict(g) -> Dict[Tuple[int, int], int]:
 
 
 def brute_embeddings(g, p) -> List[Tuple[int, ...]]:
-    """Every injective tuple satisfying Section 2.1.4, in lexicographic order."""
+    """Every injective tuple satisfying Section 2.1.4, in lexicographic order
+    (for a directed graph the rows hold out-edges only, so a pattern edge
+    (a, b) needs the data edge f(a) -> f(b))."""
     G, P = _as_graph(g), _as_pattern(p)
     adj = _adj_dict(G)
     edges = [(int(P.edges[2 * k]), int(P.edges[2 * k + 1]), int(P.elabel[k])) for k in range(P.m)]

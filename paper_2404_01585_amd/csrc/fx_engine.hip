@@ -31,21 +31,24 @@
 // Pattern plan
 // ---------------------------------------------------------------------------
 
-fx_status fx_check_pattern(const fx_pattern *p)
+fx_status fx_check_pattern(const fx_pattern *p, bool directed)
 {
     if (!p) return fx_fail(FX_EINVAL, "pattern is NULL");
     if (p->n > FX_MAXN) return fx_fail(FX_ELIMIT, "pattern has %d vertices; at most %d", p->n, FX_MAXN);
     if (p->n < 1 || p->m < 0) return fx_fail(FX_EPATTERN, "pattern needs n >= 1 and m >= 0");
     if (!p->vlabel || (p->m > 0 && !p->edges)) return fx_fail(FX_EINVAL, "pattern arrays are NULL");
     const int n = p->n;
-    bool adj[FX_MAXN][FX_MAXN] = {};
+    bool adj[FX_MAXN][FX_MAXN] = {};  // undirected: either order; directed: a -> b
+    bool any[FX_MAXN][FX_MAXN] = {};  // connected in either direction
     for (int k = 0; k < p->m; k++) {
         int a = p->edges[2 * k], b = p->edges[2 * k + 1];
         if (a < 0 || b < 0 || a >= n || b >= n) return fx_fail(FX_EPATTERN, "edge %d has an endpoint out of range", k);
         if (a == b) return fx_fail(FX_EPATTERN, "edge %d is a loop", k);
         if (adj[a][b]) return fx_fail(FX_EPATTERN, "edge %d repeats an edge", k);
         if (p->elabel && p->elabel[k] < 0) return fx_fail(FX_EPATTERN, "edge %d has a negative label", k);
-        adj[a][b] = adj[b][a] = true;
+        adj[a][b] = true;
+        if (!directed) adj[b][a] = true;
+        any[a][b] = any[b][a] = true;
     }
     for (int i = 0; i < n; i++)
         if (p->vlabel[i] < 0) return fx_fail(FX_EPATTERN, "vertex %d has a negative label", i);
@@ -56,7 +59,7 @@ fx_status fx_check_pattern(const fx_pattern *p)
     while (top) {
         int x = stack[--top];
         for (int y = 0; y < n; y++)
-            if (adj[x][y] && !seen[y]) {
+            if (any[x][y] && !seen[y]) {
                 seen[y] = true;
                 cnt++;
                 stack[top++] = y;
@@ -68,14 +71,18 @@ fx_status fx_check_pattern(const fx_pattern *p)
 
 fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
 {
-    FX_TRY(fx_check_pattern(p));
+    FX_TRY(fx_check_pattern(p, G->directed));
     const int n = p->n;
     FxPlan &P = hp.plan;
     memset(&P, 0, sizeof(P));
     P.n = n;
-    int32_t el[FX_MAXN][FX_MAXN];
+    // ed[a][b]: dense label of the pattern edge a -> b (undirected: both
+    // orders), or -1.  code(a, b): the edge code an edge between a and b has
+    // in the row of f(a) -- its dense label, or for a directed graph 2 label
+    // (outgoing from a) or 2 label + 1 (incoming into a).
+    int32_t ed[FX_MAXN][FX_MAXN];
     for (int a = 0; a < n; a++)
-        for (int b = 0; b < n; b++) el[a][b] = -1;
+        for (int b = 0; b < n; b++) ed[a][b] = -1;
     for (int i = 0; i < n; i++) {
         auto it = G->vl_map.find(p->vlabel[i]);
         if (it == G->vl_map.end()) hp.empty = true;
@@ -85,30 +92,47 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
         int a = p->edges[2 * k], b = p->edges[2 * k + 1];
         int32_t lab = p->elabel ? p->elabel[k] : 0;
         auto it = G->el_map.find(lab);
-        if (it == G->el_map.end()) {
-            hp.empty = true;
-            el[a][b] = el[b][a] = 0;
-        } else {
-            el[a][b] = el[b][a] = (int32_t)it->second;
-        }
+        int32_t d = 0;
+        if (it == G->el_map.end()) hp.empty = true;
+        else d = (int32_t)it->second;
+        ed[a][b] = d;
+        if (!G->directed) ed[b][a] = d;
     }
+    // the (neighbour, edge code) pairs of vertex a towards vertex b
+    auto codes = [&](int a, int b, int32_t *out) {
+        int c = 0;
+        if (!G->directed) {
+            if (ed[a][b] >= 0) out[c++] = ed[a][b];
+        } else {
+            if (ed[a][b] >= 0) out[c++] = 2 * ed[a][b];      // a -> b: outgoing in a's row
+            if (ed[b][a] >= 0) out[c++] = 2 * ed[b][a] + 1;  // b -> a: incoming in a's row
+        }
+        return c;
+    };
     for (int i = 0; i < n; i++) {
         P.nback[i] = 0;
-        for (int b = 0; b < i; b++)
-            if (el[b][i] >= 0) {
+        for (int b = 0; b < i; b++) {
+            int32_t cs[2];
+            const int c = codes(b, i, cs);
+            if (P.nback[i] + c > FX_MAXN)
+                return fx_fail(FX_ELIMIT, "vertex %d has more than %d edges to earlier vertices", i, FX_MAXN);
+            for (int k = 0; k < c; k++) {  // a reciprocal pair gives two constraints
                 P.back[i][P.nback[i]] = (int8_t)b;
-                P.bel[i][P.nback[i]] = (uint16_t)el[b][i];
+                P.bel[i][P.nback[i]] = (uint16_t)cs[k];
                 P.nback[i]++;
             }
+        }
         // neighbour-label filter over later neighbours: worthwhile for the
         // root and for vertices that need two or more later neighbours
-        std::pair<uint32_t, int> need_buf[FX_MAXN];
+        std::pair<uint32_t, int> need_buf[2 * FX_MAXN];
         int nneed = 0;
         int later = 0;
-        for (int j = i + 1; j < n; j++)
-            if (el[i][j] >= 0) {
+        for (int j = i + 1; j < n; j++) {
+            int32_t cs[2];
+            const int c = codes(i, j, cs);
+            for (int k = 0; k < c; k++) {
                 later++;
-                const uint32_t key = ((uint32_t)P.vl[j] << 16) | (uint32_t)el[i][j];
+                const uint32_t key = ((uint32_t)P.vl[j] << 16) | (uint32_t)cs[k];
                 bool found = false;
                 for (int q = 0; q < nneed; q++)
                     if (need_buf[q].first == key) {
@@ -117,6 +141,7 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
                     }
                 if (!found) need_buf[nneed++] = {key, 1};
             }
+        }
         P.nnlf[i] = 0;
         if (i < n - 1 && (i == 0 || later >= 2)) {
             std::stable_sort(need_buf, need_buf + nneed, [](auto &x, auto &y) { return x.second > y.second; });
@@ -127,6 +152,22 @@ fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp)
                 P.nnlf[i]++;
             }
         }
+    }
+    // symmetry breaking: automorphisms must keep every pair's edges, with
+    // their directions; each ordered pair gets the class of (a -> b, b -> a)
+    int32_t el[FX_MAXN][FX_MAXN];
+    {
+        std::vector<std::pair<int32_t, int32_t>> cls;
+        for (int a = 0; a < n; a++)
+            for (int b = 0; b < n; b++) {
+                el[a][b] = -1;
+                if (ed[a][b] < 0 && ed[b][a] < 0) continue;
+                const std::pair<int32_t, int32_t> key{ed[a][b], ed[b][a]};
+                size_t c = 0;
+                while (c < cls.size() && cls[c] != key) c++;
+                if (c == cls.size()) cls.push_back(key);
+                el[a][b] = (int32_t)c;
+            }
     }
     fx_symmetry_constraints(n, p->vlabel, el, P.sym_lt);
     for (int i = 0; i < n; i++) hp.symmetric = hp.symmetric || P.sym_lt[i] != 0;

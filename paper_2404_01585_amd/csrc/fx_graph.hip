@@ -115,6 +115,77 @@ fx_status validate_and_pack(const fx_graph_desc *d, const int64_t *rp, const int
     return FX_OK;
 }
 
+// A directed graph: the caller's rows list out-neighbours.  The packed
+// adjacency holds every edge u -> v twice: in u's row with code 2e (out) and
+// in v's row with code 2e + 1 (in), e the dense label; rp_sym receives the
+// rows of that symmetric form (twice the entries).
+fx_status validate_and_pack_directed(const fx_graph_desc *d, const int64_t *rp, const int32_t *col,
+                                     const int32_t *vlab, const int32_t *elab, fx_graph *G,
+                                     std::vector<uint64_t> &adj, std::vector<int32_t> &bucket,
+                                     std::vector<int64_t> &rp_sym)
+{
+    const int64_t nv = d->num_vertices, na = d->num_adj;
+    if (rp[0] != 0 || rp[nv] != na) return fx_fail(FX_EGRAPH, "row_ptr[0] must be 0 and row_ptr[nv] = num_adj");
+    for (int64_t v = 0; v < nv; v++)
+        if (rp[v + 1] < rp[v]) return fx_fail(FX_EGRAPH, "row_ptr decreases at vertex %lld", (long long)v);
+    for (int64_t v = 0; v < nv; v++)
+        if (vlab[v] < 0) return fx_fail(FX_EGRAPH, "negative vertex label at %lld", (long long)v);
+    for (int64_t v = 0; v < nv; v++)
+        for (int64_t k = rp[v]; k < rp[v + 1]; k++) {
+            const int32_t w = col[k];
+            if (w < 0 || w >= nv || w == v || (k > rp[v] && col[k - 1] >= w) || (elab && elab[k] < 0))
+                return fx_fail(FX_EGRAPH,
+                               "row %lld: head out of range, self-loop, duplicate, unsorted or negative label",
+                               (long long)v);
+        }
+    std::vector<int32_t> vals(vlab, vlab + nv);
+    std::sort(vals.begin(), vals.end());
+    vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+    if (vals.size() > 65535) return fx_fail(FX_ELIMIT, "more than 65535 distinct vertex labels");
+    G->vl_values = vals;
+    for (size_t i = 0; i < vals.size(); i++) G->vl_map[vals[i]] = (uint32_t)i;
+    std::vector<int32_t> evals;
+    if (elab) {
+        evals.assign(elab, elab + na);
+        std::sort(evals.begin(), evals.end());
+        evals.erase(std::unique(evals.begin(), evals.end()), evals.end());
+    }
+    if (evals.empty()) evals.push_back(0);
+    if (evals.size() > 32767) return fx_fail(FX_ELIMIT, "more than 32767 distinct edge labels in a directed graph");
+    G->el_values = evals;
+    for (size_t i = 0; i < evals.size(); i++) G->el_map[evals[i]] = (uint32_t)i;
+    std::vector<uint16_t> dvl(nv);
+    for (int64_t v = 0; v < nv; v++) dvl[v] = (uint16_t)G->vl_map[vlab[v]];
+    rp_sym.assign(nv + 1, 0);
+    for (int64_t u = 0; u < nv; u++) {
+        rp_sym[u + 1] += rp[u + 1] - rp[u];
+        for (int64_t k = rp[u]; k < rp[u + 1]; k++) rp_sym[col[k] + 1]++;
+    }
+    for (int64_t v = 0; v < nv; v++) rp_sym[v + 1] += rp_sym[v];
+    adj.resize(2 * na);
+    std::vector<int64_t> fill(rp_sym.begin(), rp_sym.end() - 1);
+    for (int64_t u = 0; u < nv; u++)
+        for (int64_t k = rp[u]; k < rp[u + 1]; k++) {
+            const uint32_t w = (uint32_t)col[k];
+            const uint64_t e = elab ? (uint64_t)(std::lower_bound(evals.begin(), evals.end(), elab[k]) - evals.begin())
+                                    : 0u;
+            adj[fill[u]++] = ((uint64_t)dvl[w] << 48) | ((2 * e) << 32) | w;           // u -> w, out of u
+            adj[fill[w]++] = ((uint64_t)dvl[u] << 48) | ((2 * e + 1) << 32) | (uint32_t)u;  // into w
+        }
+    parallel_for_chunks(nv, [&](int64_t a, int64_t b) {
+        for (int64_t v = a; v < b; v++) std::sort(adj.begin() + rp_sym[v], adj.begin() + rp_sym[v + 1]);
+    });
+    const size_t L = vals.size();
+    G->bptr.assign(L + 1, 0);
+    for (int64_t v = 0; v < nv; v++) G->bptr[dvl[v] + 1]++;
+    for (size_t l = 0; l < L; l++) G->bptr[l + 1] += G->bptr[l];
+    bucket.resize(nv);
+    std::vector<int64_t> bf(G->bptr.begin(), G->bptr.end() - 1);
+    for (int64_t v = 0; v < nv; v++) bucket[bf[dvl[v]]++] = (int32_t)v;
+    G->directed = true;
+    return FX_OK;
+}
+
 }  // namespace
 
 extern "C" fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *d, fx_graph **out)
@@ -160,13 +231,22 @@ extern "C" fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *d, fx_graph
     G->nadj = na;
     std::vector<uint64_t> adj;
     std::vector<int32_t> bucket;
-    fx_status st = validate_and_pack(d, rp.data(), col, vlab, elab, G, adj, bucket);
+    fx_status st;
+    if (d->directed) {
+        std::vector<int64_t> rp_sym;
+        st = validate_and_pack_directed(d, rp.data(), col, vlab, elab, G, adj, bucket, rp_sym);
+        rp.swap(rp_sym);  // the device rows are the symmetric form
+        G->nadj = 2 * na;
+    } else {
+        st = validate_and_pack(d, rp.data(), col, vlab, elab, G, adj, bucket);
+    }
     if (st != FX_OK) {
         delete G;
         return st;
     }
+    const int64_t nadj = G->nadj;
     st = G->rowp.ensure((nv + 1) * 8);
-    if (st == FX_OK) st = G->adj.ensure(std::max<int64_t>(na, 1) * 8);
+    if (st == FX_OK) st = G->adj.ensure(std::max<int64_t>(nadj, 1) * 8);
     if (st == FX_OK) st = G->bucket.ensure(nv * 4);
     if (st == FX_OK) st = G->bptr_d.ensure(G->bptr.size() * 8);
     if (st != FX_OK) {
@@ -174,7 +254,7 @@ extern "C" fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *d, fx_graph
         return st;
     }
     hipError_t e = hipMemcpy(G->rowp.p, rp.data(), (nv + 1) * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess && na) e = hipMemcpy(G->adj.p, adj.data(), na * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nadj) e = hipMemcpy(G->adj.p, adj.data(), nadj * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(G->bucket.p, bucket.data(), nv * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(G->bptr_d.p, G->bptr.data(), G->bptr.size() * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -182,13 +262,13 @@ extern "C" fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *d, fx_graph
         return fx_fail(FX_EDEVICE, "graph upload failed: %s", hipGetErrorString(e));
     }
     G->dev.nv = nv;
-    G->dev.nadj = na;
+    G->dev.nadj = nadj;
     G->dev.rowp = G->rowp.as<int64_t>();
     G->dev.adj = G->adj.as<uint64_t>();
     G->dev.bucket = G->bucket.as<int32_t>();
     G->dev.bptr = G->bptr_d.as<int64_t>();
     G->dev.nvl = (int32_t)G->vl_values.size();
-    G->dev.nel = (int32_t)G->el_values.size();
+    G->dev.nel = (int32_t)G->el_values.size() * (G->directed ? 2 : 1);  // edge codes
     G->dev.nkeys = G->dev.nvl * G->dev.nel;
     G->dev.runoff = nullptr;
     // label-run index: one offset per (vertex, key) plus the degree

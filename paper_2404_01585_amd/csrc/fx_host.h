@@ -194,6 +194,10 @@ struct fx_graph {
     std::vector<int64_t> bptr;                  // host copy of the label buckets' offsets
     DevBuf rowp, adj, bucket, bptr_d, runoff;
     FxGraphDev dev{};
+    // directed graphs: each edge u -> v with dense label e is held twice, in
+    // u's row with edge code 2e (outgoing) and in v's row with code 2e + 1
+    // (incoming), so an edge of either direction is a (label, code) run
+    bool directed = false;
 };
 
 // Matching plan of one pattern.
@@ -204,7 +208,7 @@ struct HostPlan {
     int64_t upper_bound = 0;  // support <= min(nv / n, min_l |V_l| / cnt_l)
 };
 
-fx_status fx_check_pattern(const fx_pattern *p);
+fx_status fx_check_pattern(const fx_pattern *p, bool directed = false);
 int32_t fx_query_kind(int32_t mode);  // FX_MODE_* -> FX_Q_*
 fx_status fx_build_plan(const fx_graph *G, const fx_pattern *p, HostPlan &hp);
 fx_status fx_tau_checked(int64_t sigma, double lambda, int32_t n, int64_t *tau_out);

@@ -46,8 +46,9 @@ struct FxPlan {
     uint16_t vl[FX_MAXN];                 // dense vertex label of pattern vertex i
     int8_t nback[FX_MAXN];                // number of earlier neighbours of i
     int8_t nnlf[FX_MAXN];                 // neighbour-label filter entries for i
-    int8_t back[FX_MAXN][FX_MAXN];        // earlier neighbours of i
-    uint16_t bel[FX_MAXN][FX_MAXN];       // dense edge label of (back[i][k], i)
+    int8_t back[FX_MAXN][FX_MAXN];        // earlier neighbours of i (one entry per edge: a
+                                          // reciprocal pair of a directed pattern gives two)
+    uint16_t bel[FX_MAXN][FX_MAXN];       // edge code of that edge in the row of back[i][k]
     uint32_t nlf_key[FX_MAXN][FX_NLF];    // (label << 16 | elabel) of later neighbours
     uint8_t nlf_need[FX_MAXN][FX_NLF];    // how many such neighbours i needs
     uint16_t sym_lt[FX_MAXN];             // bit j: f(j) < f(i) (support phase only)
@@ -99,7 +100,7 @@ struct FxLevelDev {
     int32_t *rows;   // [cap * l]
     int64_t *lo;     // start of the candidate run (index into adj, or into bucket if anc < 0)
     int32_t *len;    // length of the run
-    int8_t *anc;     // pattern vertex whose neighbour run is used, -1 for a label bucket
+    int8_t *anc;     // the back edge (index into the plan's back[l]) whose run is used, -1: a label bucket
     int64_t *off;    // exclusive prefix of len, [cap + 1]
 };
 

@@ -159,7 +159,7 @@ template <int W>
 struct Cand {
     int32_t v[W];        // the partial row (first l entries)
     int32_t c;           // candidate for pattern vertex l
-    int32_t anc;         // pattern vertex whose run produced c (-1: bucket)
+    int32_t anc;         // back edge of vertex l whose run produced c (-1: bucket)
     bool first;          // first candidate of its partial
 };
 
@@ -251,7 +251,7 @@ __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__re
     const int32_t nb = plan->nback[i];
     for (int kk = 0; kk < nb; kk++) {
         int32_t b = plan->back[i][kk];
-        if (b == x.anc) continue;  // the run it came from already matches
+        if (kk == x.anc) continue;  // the run it came from already matches
         uint64_t entry = run_key(vl, plan->bel[i][kk]) | (uint32_t)x.c;
         if (!has_entry<scan_width<W>()>(g, pick(x.v, b), entry, bytes)) return false;
     }
@@ -311,7 +311,7 @@ __device__ __forceinline__ void ref_back_edges(const FxGraphDev &g, const FxPlan
     const uint32_t vl = plan->vl[l];
     for (int kk = 0; kk < nb; kk++) {
         const int32_t a = plan->back[l][kk];
-        if (a == x.anc) continue;
+        if (kk == x.anc) continue;
         const int32_t u = pick(x.v, a);
         int64_t lo;
         int32_t len;
@@ -526,7 +526,7 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
                     dbytes += 20u;
                 } else if (x.first) {  // the anchor's run, or its whole row
                     rbytes += 16u + 6u * (unsigned long long)S.in.len[p];
-                    dbytes += 16u + 6u * degree(g, pick(x.v, x.anc));
+                    dbytes += 16u + 6u * degree(g, pick(x.v, S.plan->back[l][x.anc]));
                 }
             }
             bool ok = true;
@@ -803,7 +803,7 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
                         if (len < best_len) {
                             best_len = len;
                             best_lo = lo;
-                            best_anc = b;
+                            best_anc = kk;
                         }
                     }
                 }

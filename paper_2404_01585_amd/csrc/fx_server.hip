@@ -145,7 +145,7 @@ extern "C" fx_status fx_server_submit(fx_server *S, const fx_pattern *p, int64_t
     if (!(lambda >= 0.0 && lambda <= 1.0)) return fx_fail(FX_EINVAL, "lambda must lie in [0, 1]");
     if (mode != FX_MODE_FULL && mode != FX_MODE_VERDICT && mode != FX_MODE_MNI)
         return fx_fail(FX_EINVAL, "unknown mode %d", mode);
-    FX_TRY(fx_check_pattern(p));
+    FX_TRY(fx_check_pattern(p, S->G->directed));
     auto t = std::make_unique<ServerTicket>();
     t->vl.assign(p->vlabel, p->vlabel + p->n);
     t->ed.assign(p->edges, p->edges + 2 * p->m);

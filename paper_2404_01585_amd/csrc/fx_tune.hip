@@ -78,7 +78,7 @@ extern "C" fx_status fx_autotune(fx_graph *g, int32_t npat, const fx_pattern *pa
     for (int32_t i = 0; i < npat; i++) {
         if (sigma[i] < 1) return fx_fail(FX_EINVAL, "pattern %d: sigma must be >= 1", i);
         if (!(lambda[i] >= 0.0 && lambda[i] <= 1.0)) return fx_fail(FX_EINVAL, "pattern %d: lambda outside [0, 1]", i);
-        FX_TRY(fx_check_pattern(&pats[i]));
+        FX_TRY(fx_check_pattern(&pats[i], g->directed));
     }
     fx_ctx *c = g->ctx;
     FX_HIP(hipSetDevice(c->device));

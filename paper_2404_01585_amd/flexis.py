@@ -68,7 +68,7 @@ class CtxOpts(ctypes.Structure):
 class GraphDesc(ctypes.Structure):
     _fields_ = [("num_vertices", ctypes.c_int64), ("num_adj", ctypes.c_int64), ("offset_bytes", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("vlabel", ctypes.c_void_p),
-                ("elabel", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+                ("elabel", ctypes.c_void_p), ("on_device", ctypes.c_int32), ("directed", ctypes.c_int32)]
 
 
 class PatternC(ctypes.Structure):
@@ -338,7 +338,8 @@ class DeviceGraph:
             self._keep = keep
             ob = keep[0].element_size()
             desc = GraphDesc(self.nv, int(keep[1].numel()), ob, keep[0].data_ptr(), keep[1].data_ptr(),
-                             keep[2].data_ptr(), None if keep[3] is None else keep[3].data_ptr(), 1)
+                             keep[2].data_ptr(), None if keep[3] is None else keep[3].data_ptr(), 1,
+                             1 if getattr(g, "directed", False) else 0)
         else:
             rp = np.ascontiguousarray(g.row_ptr)
             if rp.dtype not in (np.int32, np.int64):
@@ -349,7 +350,8 @@ class DeviceGraph:
             self._keep = [rp, col, vl, el]
             desc = GraphDesc(self.nv, int(col.shape[0]), rp.dtype.itemsize, rp.ctypes.data,
                              col.ctypes.data if col.shape[0] else None, vl.ctypes.data,
-                             el.ctypes.data if (el is not None and el.shape[0]) else None, 0)
+                             el.ctypes.data if (el is not None and el.shape[0]) else None, 0,
+                             1 if getattr(g, "directed", False) else 0)
         self._h = ctypes.c_void_p()
         _check(lib.fx_graph_load(ctx.handle, ctypes.byref(desc), ctypes.byref(self._h)))
         self._keep = None

@@ -30,13 +30,15 @@ import numpy as np
 
 @dataclasses.dataclass
 class Graph:
-    """Symmetric CSR with vertex and edge labels (host numpy arrays)."""
+    """Symmetric CSR with vertex and edge labels (host numpy arrays); with
+    directed=True row u lists the heads of the edges u -> v instead."""
 
     row_ptr: np.ndarray  # int32 or int64 [nv+1]
-    col: np.ndarray  # int32 [2|E|], ascending per row
+    col: np.ndarray  # int32 [2|E|] (directed: [|E|]), ascending per row
     vlabel: np.ndarray  # int32 [nv]
-    elabel: np.ndarray  # int32 [2|E|], equal for (u,v) and (v,u)
+    elabel: np.ndarray  # int32 [2|E|], equal for (u,v) and (v,u) (directed: one per edge)
     name: str = ""
+    directed: bool = False
 
     @property
     def num_vertices(self) -> int:
@@ -97,6 +99,52 @@ def csr_from_edges(nv: int, u: np.ndarray, v: np.ndarray, el: np.ndarray,
     np.cumsum(counts, out=row_ptr[1:])
     return Graph(row_ptr=row_ptr.astype(offset_dtype), col=dst.astype(np.int32),
                  vlabel=np.asarray(vlabel, dtype=np.int32), elabel=lab.astype(np.int32), name=name)
+
+
+def csr_from_arcs(nv: int, u: np.ndarray, v: np.ndarray, el: np.ndarray, vlabel: np.ndarray,
+                  offset_dtype=np.int64, name: str = "") -> Graph:
+    """Builds the directed CSR (row u: heads of the arcs u -> v, ascending) of
+    unique arcs (u_i, v_i, el_i)."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    el = np.asarray(el, dtype=np.int64)
+    order = np.argsort(u * nv + v)
+    u, v, el = u[order], v[order], el[order]
+    counts = np.bincount(u, minlength=nv)
+    row_ptr = np.zeros(nv + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return Graph(row_ptr=row_ptr.astype(offset_dtype), col=v.astype(np.int32),
+                 vlabel=np.asarray(vlabel, dtype=np.int32), elabel=el.astype(np.int32), name=name, directed=True)
+
+
+def tiny_random_digraph(rng: np.random.Generator, nv: int, p: float, n_vlabels: int, n_elabels: int) -> Graph:
+    """Directed G(n, p): each ordered pair an arc with probability p (both
+    directions of a pair may occur, with their own labels), random labels."""
+    ii, jj = np.nonzero(~np.eye(nv, dtype=bool))
+    keep = rng.random(ii.shape[0]) < p
+    u, v = ii[keep], jj[keep]
+    el = rng.integers(0, n_elabels, size=u.shape[0]) if n_elabels > 1 else np.zeros(u.shape[0], dtype=np.int64)
+    vl = rng.integers(0, n_vlabels, size=nv)
+    return csr_from_arcs(nv, u, v, el, vl, name="tiny_directed")
+
+
+def random_directed_pattern(rng: np.random.Generator, n: int, n_vlabels: int, n_elabels: int,
+                            extra_edge_p: float = 0.3, reciprocal_p: float = 0.2,
+                            prefix_connected: bool = True) -> Pattern:
+    """A random weakly connected directed pattern: a random orientation of
+    random_connected_pattern's edges, some made reciprocal (both directions,
+    each with its own label)."""
+    base = random_connected_pattern(rng, n, n_vlabels, n_elabels, extra_edge_p, prefix_connected)
+    edges, labels = [], []
+    for (a, b), l in zip(base.edges, base.elabel):
+        if rng.random() < 0.5:
+            a, b = b, a
+        edges.append((a, b))
+        labels.append(l)
+        if rng.random() < reciprocal_p:
+            edges.append((b, a))
+            labels.append(int(rng.integers(0, n_elabels)) if n_elabels > 1 else 0)
+    return Pattern(vlabel=base.vlabel, edges=edges, elabel=labels)
 
 
 def _unique_edges(nv: int, draw, m: int, rng: np.random.Generator) -> Tuple[np.ndarray, np.ndarray]:

@@ -322,3 +322,86 @@ def test_selection_digest():
         greedy = O.brute_greedy(O.brute_embeddings(g, p))
         got = O.query(g, p, 2, 1.0, O.FULL)["sel_digest"]
         assert got == O.rows_digest(np.asarray(greedy, dtype=np.int32).reshape(-1, p.n), p.n), idx
+
+
+# ---------------------------------------------------------------------------
+# Directed graphs (Section 2.2: the problem is stated for labeled, directed
+# graphs; a pattern edge (a, b) is a -> b)
+# ---------------------------------------------------------------------------
+
+def _directed_cases(n_cases, seed):
+    from paper_2404_01585_amd.synth import random_directed_pattern, tiny_random_digraph
+    rng = np.random.default_rng(seed)
+    for _ in range(n_cases):
+        nv = int(rng.integers(3, 10))
+        g = tiny_random_digraph(rng, nv, float(rng.uniform(0.15, 0.5)), int(rng.integers(1, 3)),
+                                int(rng.integers(1, 3)))
+        n = int(rng.integers(2, 5))
+        p = random_directed_pattern(rng, n, int(g.vlabel.max()) + 1, int(g.elabel.max()) + 1 if g.num_adj else 1,
+                                    prefix_connected=bool(rng.random() < 0.7))
+        yield g, p
+
+
+def test_directed_brute_force_agreement():
+    # brute force over all tuples = the literal form = the streaming matcher,
+    # in embeddings, the greedy selection and the invariants
+    checked = 0
+    for g, p in _directed_cases(250, 31):
+        G = O.OracleGraph.of(g)
+        embs = O.brute_embeddings(g, p)
+        cnt, rows = O.enumerate_embeddings(G, p)
+        assert cnt == len(embs)
+        assert [tuple(int(x) for x in r) for r in rows] == embs
+        k_lit, sel_lit = O.support_literal(G, p)
+        k_str, sel_str = O.support_stream(G, p)
+        greedy = O.brute_greedy(embs)
+        assert k_lit == k_str == len(greedy)
+        assert [tuple(int(x) for x in r) for r in sel_str] == greedy
+        assert O.is_maximal_independent(greedy, embs)
+        if embs:
+            assert len(greedy) <= O.brute_mis(embs) <= len(greedy) * p.n  # Theorem 1
+            assert len(greedy) <= O.brute_mni(embs, p.n)
+        checked += len(embs) > 0
+    assert checked > 50
+
+
+def test_directed_closed_forms():
+    from paper_2404_01585_amd.synth import tiny_random_digraph
+    rng = np.random.default_rng(8)
+    for _ in range(5):
+        g = tiny_random_digraph(rng, 12, 0.3, 1, 1)
+        nv = g.num_vertices
+        a = np.zeros((nv, nv), dtype=np.int64)
+        src = np.repeat(np.arange(nv), g.degree())
+        a[src, g.col] = 1
+        out_d, in_d = a.sum(1), a.sum(0)
+        recip = (a * a.T).sum(1)
+        # directed 3-cycle a -> b -> c -> a: trace(A^3) embeddings
+        cyc = Pattern([0, 0, 0], [(0, 1), (1, 2), (2, 0)], [0, 0, 0])
+        assert O.count(g, cyc, 1 << 40)[0] == int(np.trace(a @ a @ a))
+        # directed 2-path a -> b -> c with a != c
+        path = Pattern([0, 0, 0], [(0, 1), (1, 2)], [0, 0])
+        assert O.count(g, path, 1 << 40)[0] == int((in_d * out_d - recip).sum())
+        # out-star b <- a -> c
+        star = Pattern([0, 0, 0], [(0, 1), (0, 2)], [0, 0])
+        assert O.count(g, star, 1 << 40)[0] == int((out_d * (out_d - 1)).sum())
+        # a reciprocal pair a <-> b
+        pair = Pattern([0, 0], [(0, 1), (1, 0)], [0, 0])
+        assert O.count(g, pair, 1 << 40)[0] == int(recip.sum())
+
+
+def test_directed_reduces_to_undirected():
+    # an undirected graph given as a directed one (both directions, equal
+    # labels) and a pattern whose every edge is reciprocal with equal labels
+    # give the undirected embeddings and support
+    from paper_2404_01585_amd.synth import csr_from_arcs
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        g = tiny_random_graph(rng, 9, 0.4, 2, 2)
+        src = np.repeat(np.arange(g.num_vertices), g.degree())
+        gd = csr_from_arcs(g.num_vertices, src, g.col, g.elabel, g.vlabel)
+        p = random_connected_pattern(rng, int(rng.integers(2, 5)), 2, 2)
+        pd = Pattern(p.vlabel, [e for a, b in p.edges for e in ((a, b), (b, a))],
+                     [l for l in p.elabel for _ in range(2)])
+        assert O.query(g, p, 2, 1.0, O.FULL)["support"] == O.query(gd, pd, 2, 1.0, O.FULL)["support"]
+        assert O.count(g, p, 1 << 40)[:2] == O.count(gd, pd, 1 << 40)[:2]
