@@ -117,10 +117,15 @@ def test_large_unsaturated_digests(torch_cuda):
         g = _graph(name)
         pats = [Pattern(vlabel=c["pattern"]["vlabel"], edges=[tuple(e) for e in c["pattern"]["edges"]],
                         elabel=c["pattern"]["elabel"]) for c in cases]
+        got = []
         with fx.Context(device=0, count_cap=exp["count_cap"]) as ctx:
             with ctx.load_graph(g) as dg:
-                _say(name, "FULL batch with digest, cap", exp["count_cap"], "patterns", len(pats))
-                got = dg.support_batch(pats, [c["sigma"] for c in cases], [c["lam"] for c in cases], fx.MODE_FULL)
+                for b0 in range(0, len(pats), 8):
+                    sl = slice(b0, b0 + 8)
+                    _say(name, "FULL batch with digest, cap", exp["count_cap"], "patterns", b0, "..",
+                         min(b0 + 8, len(pats)), "of", len(pats))
+                    got += dg.support_batch(pats[sl], [c["sigma"] for c in cases[sl]],
+                                            [c["lam"] for c in cases[sl]], fx.MODE_FULL)
         for i, c in enumerate(cases):
             w = c["full"]
             for k in ("embedding_count", "count_saturated"):
