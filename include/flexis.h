@@ -91,9 +91,13 @@ typedef struct fx_server fx_server;
  *                     their projected stack bytes fit.
  *   run_index_bytes   largest label-run index a graph of this context may
  *                     build (0 = 8 GiB, -1 = none): for every vertex and every
- *                     (vertex label, edge label) pair, the offset of that run in
- *                     the vertex's adjacency row, 4 bytes each.  With it a
- *                     candidate run is two loads instead of two binary searches.
+ *                     (vertex label, edge label) pair, the adjacency position
+ *                     where that run starts, 4 bytes each (built only for
+ *                     graphs with fewer than 2^32 adjacency entries), and one
+ *                     presence bit per (vertex, pair).  With it a candidate
+ *                     run is one random access instead of two binary searches,
+ *                     and the neighbour-label filter reads the smaller bit
+ *                     array first.
  *   flags             bitwise or of FX_CTX_KERNEL_TIMING (bracket the kernels of
  *                     every step with HIP events on the context's stream and
  *                     accumulate their durations, see fx_ctx_stats) and

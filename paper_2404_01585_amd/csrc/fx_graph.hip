@@ -271,30 +271,40 @@ extern "C" fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *d, fx_graph
     G->dev.nel = (int32_t)G->el_values.size() * (G->directed ? 2 : 1);  // edge codes
     G->dev.nkeys = G->dev.nvl * G->dev.nel;
     G->dev.runoff = nullptr;
-    // label-run index: one offset per (vertex, key) plus the degree
-    const uint64_t K1 = (uint64_t)G->dev.nkeys + 1;
-    const uint64_t index_bytes = (uint64_t)nv * K1 * 4;
-    int64_t maxdeg = 0;
-    for (int64_t v = 0; v < nv; v++) maxdeg = std::max<int64_t>(maxdeg, rp[v + 1] - rp[v]);
-    if (ctx->run_index_bytes >= 0 && index_bytes <= (uint64_t)ctx->run_index_bytes && maxdeg < 0xffffffffLL) {
-        std::vector<uint32_t> ro(nv * K1);
+    // label-run index: the absolute adjacency position of every (vertex, key)
+    // run, in one flat array (the run of (v, k) is [R[v K + k], R[v K + k + 1]),
+    // the last key of v ending where v + 1 starts); positions are 32-bit, so
+    // the index needs fewer than 2^32 adjacency entries
+    const uint64_t K = (uint64_t)G->dev.nkeys;
+    const uint64_t KW = (K + 31) / 32;
+    const uint64_t index_bytes = ((uint64_t)nv * K + 1) * 4 + (uint64_t)nv * KW * 4;
+    G->dev.kwords = (int32_t)KW;
+    G->dev.keybits = nullptr;
+    if (ctx->run_index_bytes >= 0 && index_bytes <= (uint64_t)ctx->run_index_bytes && nadj < 0xffffffffLL) {
+        std::vector<uint32_t> ro(nv * K + 1);
+        std::vector<uint32_t> kb(nv * KW, 0u);
         const int32_t nel = G->dev.nel;
         parallel_for_chunks(nv, [&](int64_t a, int64_t b) {
             for (int64_t v = a; v < b; v++) {
-                uint32_t *r = ro.data() + v * K1;
-                const int64_t base = rp[v], deg = rp[v + 1] - rp[v];
-                int64_t k = 0;
-                for (int64_t i = 0; i < deg; i++) {  // the row is sorted by key
-                    const uint64_t e = adj[base + i];
+                uint32_t *r = ro.data() + v * K;
+                const int64_t base = rp[v], end = rp[v + 1];
+                uint64_t k = 0;
+                for (int64_t i = base; i < end; i++) {  // the row is sorted by key
+                    const uint64_t e = adj[i];
                     const uint64_t key = (e >> 48) * (uint64_t)nel + ((e >> 32) & 0xffffu);
-                    while ((uint64_t)k <= key) r[k++] = (uint32_t)i;
+                    while (k <= key) r[k++] = (uint32_t)i;
+                    kb[v * KW + key / 32] |= 1u << (key % 32);
                 }
-                while ((uint64_t)k < K1) r[k++] = (uint32_t)deg;
+                while (k < K) r[k++] = (uint32_t)end;
             }
         });
-        if (G->runoff.ensure(ro.size() * 4) == FX_OK &&
-            hipMemcpy(G->runoff.p, ro.data(), ro.size() * 4, hipMemcpyHostToDevice) == hipSuccess)
+        ro[nv * K] = (uint32_t)nadj;
+        if (G->runoff.ensure(ro.size() * 4) == FX_OK && G->keybits.ensure(kb.size() * 4) == FX_OK &&
+            hipMemcpy(G->runoff.p, ro.data(), ro.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(G->keybits.p, kb.data(), kb.size() * 4, hipMemcpyHostToDevice) == hipSuccess) {
             G->dev.runoff = G->runoff.as<uint32_t>();
+            G->dev.keybits = G->keybits.as<uint32_t>();
+        }
     }
     ctx->graphs++;
     *out = G;

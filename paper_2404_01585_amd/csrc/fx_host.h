@@ -192,7 +192,7 @@ struct fx_graph {
     std::vector<int32_t> vl_values, el_values;  // dense id -> caller's label
     std::unordered_map<int32_t, uint32_t> vl_map, el_map;
     std::vector<int64_t> bptr;                  // host copy of the label buckets' offsets
-    DevBuf rowp, adj, bucket, bptr_d, runoff;
+    DevBuf rowp, adj, bucket, bptr_d, runoff, keybits;
     FxGraphDev dev{};
     // directed graphs: each edge u -> v with dense label e is held twice, in
     // u's row with edge code 2e (outgoing) and in v's row with code 2e + 1

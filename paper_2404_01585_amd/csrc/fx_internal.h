@@ -11,12 +11,19 @@
 //                              label) form one contiguous run in ascending id.
 //   bucket int32 [nv]          vertex ids grouped by dense label, ascending id
 //   bptr   int64 [L+1]         start of each label group in bucket
-//   runoff uint32 [nv * (K+1)] label-run index, K = (vertex labels) x (edge labels):
-//                              runoff[v*(K+1) + k] = offset in v's row of the
-//                              first neighbour with key >= k (k = label * nel +
-//                              elabel); runoff[v*(K+1) + K] = degree.  Built when
-//                              it fits the index budget; otherwise runs are
+//   runoff uint32 [nv*K + 1]   label-run index, K = (vertex labels) x (edge labels):
+//                              runoff[v*K + k] = position in adj of the first
+//                              neighbour of v with key >= k (k = label * nel +
+//                              elabel), so the run of (v, k) is
+//                              [runoff[v*K + k], runoff[v*K + k + 1]) and
+//                              runoff[nv*K] = 2|E|.  Built when it fits the
+//                              index budget and 2|E| < 2^32; otherwise runs are
 //                              found by binary search.
+//   keybits uint32 [nv * KW]   with the run index: bit k of v's KW = ceil(K/32)
+//                              words is set when v has a neighbour with key k
+//                              (the neighbour-label filter's common question,
+//                              "at least one", from an array small enough to
+//                              stay in the last-level cache)
 //
 // A pattern plan fixes, for every pattern vertex i (in submitted order), its
 // dense label, its earlier neighbours b < i with the edge label of (b, i),
@@ -66,6 +73,8 @@ struct FxGraphDev {
     int32_t nel;   // dense edge labels
     const uint32_t *runoff;  // label-run index or nullptr
     int32_t nkeys;           // nvl * nel
+    int32_t kwords;          // 32-bit words of keybits per vertex
+    const uint32_t *keybits; // key-presence bits or nullptr (with the run index)
 };
 
 // Device-side counters of one query, read by the host once per step.

@@ -93,20 +93,20 @@ __device__ __forceinline__ bool contains64(const uint64_t *__restrict__ a, int64
     return found;
 }
 
-// The run of neighbours of u with the given (label, elabel) key: two offsets
-// of the label-run index when the graph has one, else two binary searches
-// over u's row.
+// The run of neighbours of u with the given (label, elabel) key: two
+// adjacent positions of the label-run index when the graph has one (one
+// random access), else two binary searches over u's row.
 template <int SCAN>
 __device__ __forceinline__ void run_of(const FxGraphDev &g, int32_t u, uint64_t key, int64_t &lo, int32_t &len,
                                        uint32_t &bytes)
 {
     if (g.runoff) {
         const uint32_t kidx = (uint32_t)(key >> 48) * (uint32_t)g.nel + (uint32_t)((key >> 32) & 0xffffu);
-        const uint32_t *r = g.runoff + (uint64_t)(uint32_t)u * (uint32_t)(g.nkeys + 1) + kidx;
+        const uint32_t *r = g.runoff + (uint64_t)(uint32_t)u * (uint32_t)g.nkeys + kidx;
         const uint32_t a = r[0], b = r[1];
-        lo = g.rowp[u] + a;
+        lo = a;
         len = (int32_t)(b - a);
-        bytes += 16;
+        bytes += 8;
         return;
     }
     int64_t a = g.rowp[u], b = g.rowp[u + 1];
@@ -258,11 +258,19 @@ __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__re
     if (i < n - 1) {  // neighbour-label filter for the later neighbours of i
         const int32_t nf = plan->nnlf[i];
         for (int k = 0; k < nf; k++) {
+            const uint32_t nk = plan->nlf_key[i][k];
+            const int32_t need = plan->nlf_need[i][k];
+            if (g.keybits) {  // presence first: one word of a cache-resident array
+                const uint32_t kidx = (nk >> 16) * (uint32_t)g.nel + (nk & 0xffffu);
+                const uint32_t w = g.keybits[(uint64_t)(uint32_t)x.c * (uint32_t)g.kwords + (kidx >> 5)];
+                bytes += 4;
+                if (!((w >> (kidx & 31u)) & 1u)) return false;
+                if (need <= 1) continue;
+            }
             int64_t lo;
             int32_t len;
-            const uint32_t nk = plan->nlf_key[i][k];
             run_of<scan_width<W>()>(g, x.c, run_key(nk >> 16, nk & 0xffffu), lo, len, bytes);
-            if (len < plan->nlf_need[i][k]) return false;
+            if (len < need) return false;
         }
     }
     return true;
