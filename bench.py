@@ -84,7 +84,7 @@ GRAPH_DESC = {"cl100k": "Chung-Lu 100K vertices / 500K edges (gamma 2.1), 20 Zip
               "rmat22": "R-MAT scale 22 (4,194,304 vertices, 40M edges), 50 Zipf(1.1) vertex labels, 4 edge labels",
               "cl1m": "Chung-Lu 1M vertices / 8M edges (gamma 2.3), 30 Zipf(1.0) vertex labels, 1 edge label"}
 SHAPE_KEYS = ("slice_rows", "step_candidates", "items_per_thread", "last_span_init", "lanes", "max_active")
-ENGINE_KEYS = ("chain_queries", "chain_steps")  # device-scheduled steps (library defaults unless given)
+ENGINE_KEYS = ("chain_queries", "chain_steps", "fused")  # engine choices (library defaults unless given)
 
 
 def log(*a):
@@ -352,6 +352,7 @@ def marker():
 
 
 KERNELS = (("probe", "k_probe"), ("scatter", "k_scatter"), ("greedy", "k_greedy"))
+FUSED_KERNELS = (("probe", "k_expand"), ("greedy", "k_greedy"))  # the single-pass expansion: probe and write
 
 
 def roofline_pass(ctx, dg, batches, mode, repeats: int, count_ref: bool, traffic):
@@ -385,7 +386,8 @@ def roofline_pass(ctx, dg, batches, mode, repeats: int, count_ref: bool, traffic
     ctx.set("lanes", lanes0)
     ctx.set("chain_queries", chain0)
     per = {}
-    for key, name in KERNELS:
+    fused = bool(ctx.get("fused"))
+    for key, name in (FUSED_KERNELS if fused else KERNELS):
         n = st[f"{key}_launches"]
         if not n or st[f"{key}_ms"] <= 0:
             continue
@@ -393,6 +395,8 @@ def roofline_pass(ctx, dg, batches, mode, repeats: int, count_ref: bool, traffic
         d = dict(kernel=name, launches=n, avg_launch_us=round(avg_s * 1e6, 3))
         if ref is not None and ref[f"{key}_launches"] == n:
             rb = ref[f"{key}_ref_bytes"] / n
+            if fused and key == "probe":  # the fused kernel also writes the rows
+                rb += ref["scatter_ref_bytes"] / n
             d.update(ref_bytes_per_launch=round(rb, 1), achieved=round(rb / avg_s / 1e9, 3),
                      frac=round(rb / avg_s / 1e9 / HBM_PEAK_GBS, 6))
             if key == "probe":  # the same model for plain (not label-sorted) rows
@@ -403,13 +407,15 @@ def roofline_pass(ctx, dg, batches, mode, repeats: int, count_ref: bool, traffic
             d.update(ref_launches_differ=ref[f"{key}_launches"])
         if key in ("probe", "scatter"):
             tb = st[f"{key}_alg_bytes"] / n
+            if fused and key == "probe":
+                tb += st["scatter_alg_bytes"] / n
             d.update(touched_bytes_per_launch=round(tb, 1), touched_frac=round(tb / avg_s / 1e9 / HBM_PEAK_GBS, 6))
         per[key] = d
     if "probe" not in per:
         return None
     p = per["probe"]
     return dict(bound="hbm", achieved=p.get("achieved"), peak=HBM_PEAK_GBS, unit="GB/s", frac=p.get("frac"),
-                traffic=traffic, kernel="k_probe", avg_launch_us=p["avg_launch_us"],
+                traffic=traffic, kernel=p["kernel"], avg_launch_us=p["avg_launch_us"],
                 alg_bytes_per_launch=p.get("ref_bytes_per_launch"), launches=p["launches"], per_kernel=per,
                 timing="one-lane pass after the timed region (the same batches, host-scheduled steps, HIP events "
                        "around every launch on the lane's stream); algorithmic bytes = reference bytes counted on "

@@ -267,8 +267,12 @@ fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, co
 
 /* Accumulated device statistics of a context (since creation or the last
  * reset).  Durations are only collected with FX_CTX_KERNEL_TIMING.
- *   probe_*     the expansion test kernel (one launch per step)
- *   scatter_*   the ordered write of surviving candidates (one launch per step)
+ *   probe_*     the expansion test kernel (one launch per step); with the
+ *               fused tunable, the single-pass expansion kernel (test and
+ *               ordered write)
+ *   scatter_*   the ordered write of surviving candidates (one launch per step;
+ *               no launches with the fused tunable, its bytes are still
+ *               counted here)
  *   greedy_*    the greedy mIS kernels (hash build and rounds)
  *   *_alg_bytes algorithmic bytes: bytes the operation must move at minimum
  *               on this layout (8-byte packed adjacency entries, 4-byte ids),
@@ -366,6 +370,13 @@ fx_status fx_ctx_stats(fx_ctx *ctx, fx_stats *out, int32_t reset);
  *                     inside the step's buffers) and the tile map the device
  *                     built after it; a violation fails the call with
  *                     FX_EDEVICE instead of launching (host-scheduled steps)
+ *   fused             0/1: expand with the single-pass kernel (probe, ordered
+ *                     write and run-length offsets in one launch, positions
+ *                     found by a look-back over the preceding workgroups)
+ *                     instead of five launches (probe, block scan, scatter,
+ *                     block scan, offset fix-up); default 0 (the ordered
+ *                     write waits on every earlier workgroup's probe, so a
+ *                     slow tile holds up the writes of all tiles after it)
  * fx_autotune sets the first six.  Errors: FX_EINVAL for an unknown name or a
  * value out of range (the context is unchanged). */
 fx_status fx_ctx_set(fx_ctx *ctx, const char *key, int64_t value);

@@ -192,6 +192,7 @@ extern "C" fx_status fx_ctx_set(fx_ctx *c, const char *key, int64_t value)
     else if (k == "chain_steps" && in(1, 256)) P.chain_steps = (int32_t)value;
     else if (k == "ref_bytes" && in(0, 1)) P.ref_bytes = value != 0;
     else if (k == "check_steps" && in(0, 1)) P.check_steps = value != 0;
+    else if (k == "fused" && in(0, 1)) P.fused = value != 0;
     else return fx_fail(FX_EINVAL, "unknown tunable '%s' or value %lld out of range", key, (long long)value);
     return FX_OK;
 }
@@ -216,6 +217,7 @@ extern "C" fx_status fx_ctx_get(fx_ctx *c, const char *key, int64_t *value)
     else if (k == "chain_steps") *value = P.chain_steps;
     else if (k == "ref_bytes") *value = P.ref_bytes ? 1 : 0;
     else if (k == "check_steps") *value = P.check_steps ? 1 : 0;
+    else if (k == "fused") *value = P.fused ? 1 : 0;
     else return fx_fail(FX_EINVAL, "unknown tunable '%s'", key);
     return FX_OK;
 }

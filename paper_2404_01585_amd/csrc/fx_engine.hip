@@ -775,6 +775,7 @@ fx_status FxEngine::step()
             FX_TRY(L.boff.ensure((max_blocks + 1) * 8));
             FX_TRY(L.lsum.ensure(max_blocks * 8));
             FX_TRY(L.loff.ensure((max_blocks + 1) * 8));
+            FX_TRY(L.sstat.ensure((size_t)scan_state_words((uint32_t)max_blocks) * 8));
             FX_TRY(L.tmap.ensure(max_blocks * sizeof(FxTile)));
             FX_TRY(L.stage_d.ensure(stage_bytes(A, A)));
             FX_TRY(L.stage_h.ensure(stage_bytes(A, A)));
@@ -977,9 +978,10 @@ fx_status FxEngine::launch(int g)
     hipEvent_t *ev = P_.timing ? L.evk : nullptr;
     FX_HIP(fx_launch_step(st, G_->dev, (const FxSeg *)((char *)L.stage_d.p + seg_off), L.stage_d.as<uint32_t>(),
                           nsegs, nblocks, P_.items, maxn, L.tmap.as<FxTile>(), L.cand.as<int32_t>(), L.bcnt.as<uint32_t>(),
-                          L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>(), ev ? ev[0] : nullptr,
+                          L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>(), L.sstat.as<uint64_t>(),
+                          ev ? ev[0] : nullptr,
                           ev ? ev[1] : nullptr, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
-                          ev ? ev[5] : nullptr, any_inner, any_greedy));
+                          ev ? ev[5] : nullptr, any_inner, any_greedy, P_.fused ? 1 : 0));
     int hi = 0;
     for (auto &qp : act) hi = std::max(hi, qp->slot + 1);
     FX_HIP(hipMemcpyAsync(L.sums_h.p, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, st));
@@ -1017,14 +1019,16 @@ fx_status FxEngine::collect(int g, double &waited)
     stats_->steps++;
     stats_->syncs++;
     stats_->probe_launches++;
-    stats_->scatter_launches++;
+    if (!P_.fused) stats_->scatter_launches++;
     if (any_greedy_[g]) stats_->greedy_launches++;
     if (P_.timing) {
         float ms = 0;
         FX_HIP(hipEventElapsedTime(&ms, L.evk[0], L.evk[1]));
         stats_->probe_ms += ms;
-        FX_HIP(hipEventElapsedTime(&ms, L.evk[2], L.evk[3]));
-        stats_->scatter_ms += ms;
+        if (!P_.fused) {
+            FX_HIP(hipEventElapsedTime(&ms, L.evk[2], L.evk[3]));
+            stats_->scatter_ms += ms;
+        }
         FX_HIP(hipEventElapsedTime(&ms, L.evk[4], L.evk[5]));
         stats_->greedy_ms += ms;
     }
@@ -1258,7 +1262,8 @@ fx_status FxEngine::chain_step(double &waited)
     // ends after a few steps does not sit through a long chain's empty steps
     key.steps = chain_k_ = std::min<int32_t>(chain_k_ ? 2 * chain_k_ : 2, std::max<int32_t>(P_.chain_steps, 1));
     key.max_q = max_q;
-    const void *bufs[8] = {hb, db, L.tmap.p, L.cand.p, L.bcnt.p, L.boff.p, L.lsum.p, L.loff.p};
+    key.fused = P_.fused ? 1 : 0;
+    const void *bufs[9] = {hb, db, L.tmap.p, L.cand.p, L.bcnt.p, L.boff.p, L.lsum.p, L.loff.p, L.sstat.p};
     memcpy(key.bufs, bufs, sizeof(bufs));
     key.bytes = bytes;
     EngineWork::ChainGraph &cg = W_->chain_graph(key);
@@ -1271,7 +1276,8 @@ fx_status FxEngine::chain_step(double &waited)
             e = fx_launch_chain(cs, G_->dev, (FxChainQuery *)(db + cq_off), (FxChainCtl *)db, max_q, key.steps,
                                 (FxSeg *)(db + segs_off), (uint32_t *)(db + blk0_off), P_.items, key.width,
                                 L.tmap.as<FxTile>(), L.cand.as<int32_t>(), L.bcnt.as<uint32_t>(),
-                                L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>());
+                                L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>(),
+                                L.sstat.as<uint64_t>(), key.fused);
         if (e == hipSuccess) e = hipMemcpyAsync(hb, db, bytes, hipMemcpyDeviceToHost, cs);
         hipGraph_t graph = nullptr;
         const hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -1304,7 +1310,7 @@ fx_status FxEngine::chain_step(double &waited)
     stats_->steps += ran;
     stats_->syncs++;
     stats_->probe_launches += ran;
-    stats_->scatter_launches += ran;
+    if (!P_.fused) stats_->scatter_launches += ran;
     stats_->greedy_launches += ran;
     bool any_done = false;
     for (size_t i = 0; i < qs.size(); i++) {

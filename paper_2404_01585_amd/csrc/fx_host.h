@@ -101,6 +101,7 @@ struct EngineParams {
     bool no_digest = false;
     bool ref_bytes = false;   // count the reference algorithmic bytes (extra loads: a counting pass)
     bool check_steps = false; // check every step's segment table and tile map on the host (fx_check.h)
+    bool fused = false;       // single-pass expansion kernel (else probe, scans, scatter, offset fix-up)
     bool lone_growth = true;  // long VERDICT queries left nearly alone may grow their support stacks
     int32_t chain_queries = 8;    // at most this many queries left (none waiting): device-scheduled steps
     int32_t chain_steps = 16;     // steps per chain (one host synchronisation each)
@@ -114,6 +115,7 @@ struct EngineParams {
 struct EngineLane {
     DevBuf stage_d, inits_d;           // stage: workgroup starts, then the segment table
     DevBuf cand, bcnt, boff, lsum, loff, tmap;  // per-step scratch of the expansion kernels
+    DevBuf sstat;                               // block-scan state (scan_state_words of the step's workgroups)
     HostBuf stage_h, inits_h, sums_h;
     hipEvent_t done = nullptr;  // recorded after the lane's summary copy
     hipEvent_t evk[6] = {};     // kernel timing
@@ -127,8 +129,8 @@ struct EngineLane {
 struct ChainGraphKey {
     const void *graph;
     FxGraphDev dev;
-    int32_t items, width, steps, max_q;
-    const void *bufs[8];
+    int32_t items, width, steps, max_q, fused;
+    const void *bufs[9];
     size_t bytes;
     bool operator==(const ChainGraphKey &o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
 };

@@ -42,6 +42,13 @@
 #define FX_BS 256            // threads per workgroup for the streaming kernels
 #define FX_MAX_TILE (FX_BS * 8)  // most candidates per expansion workgroup (8 per thread)
 #define FX_LDSP 1024         // partial offsets a workgroup stages in LDS
+
+// Block scans of a step: chunks of kScanChunk per-workgroup values, each
+// chunk's prefix found by look-back; a step's scan state is two scans' status
+// words and tickets.
+constexpr uint32_t kScanChunk = 1024;
+__host__ __device__ inline uint32_t scan_chunks(uint32_t n) { return n ? (n + kScanChunk - 1) / kScanChunk : 1; }
+__host__ __device__ inline uint32_t scan_state_words(uint32_t n) { return 2 * (scan_chunks(n) + 1); }
 #define FX_GREEDY_H 4096     // LDS hash slots of the per-query greedy
 #define FX_GREEDY_VN 2048    // embedding-vertices per greedy chunk (<= H / 2)
 #define FX_FILL 0.8          // a slice aims at this fraction of the rows it may write
@@ -268,21 +275,26 @@ hipError_t fx_launch_init(hipStream_t s, const FxGraphDev &g, const FxInit *init
 // = set bits of bitmap j, then *out = min_j counts[j].
 hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int32_t n,
                          unsigned long long *counts, unsigned long long *out);
-// One step: probe, scan, scatter (+ run-length prefix fix-up), greedy.  items
+// One step: probe, scan, scatter (+ run-length prefix fix-up), greedy -- or,
+// with fused, the single-pass expansion kernel (boff and loff then hold the
+// tiles' status words, lsum the ticket counter) and the greedy.  sstat holds
+// the block scans' state, scan_state_words(nblocks) words.  items
 // (2, 4 or 8) is the number of candidates per thread; segment j owns
 // ceil(span_j / (FX_BS * items)) consecutive workgroups starting at blk0s[j].
 // maxn is the largest pattern size among the segments (it picks the register
 // width of a partial row).
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
                           int32_t nsegs, uint32_t nblocks, int32_t items, int32_t maxn, FxTile *tmap, int32_t *cand,
-                          uint32_t *bcnt,
-                          uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
+                          uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, uint64_t *sstat,
+                          hipEvent_t probe_begin,
                           hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
-                          hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy);
+                          hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy,
+                          int32_t fused);
 // Enqueues `steps` device-scheduled steps over the chained queries in cq
 // (ctl->nq of them, at most max_q), then a final advance, on stream s.  The
 // scratch buffers must hold ceil(ctl->budget / (FX_BS * items)) + max_q
 // tiles; segs and blk0s room for max_q segments.
 hipError_t fx_launch_chain(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
                            int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, int32_t maxn, FxTile *tmap,
-                           int32_t *cand, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff);
+                           int32_t *cand, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff,
+                           uint64_t *sstat, int32_t fused);

@@ -172,7 +172,8 @@ struct TileMap {
     bool staged;
 };
 
-__device__ __forceinline__ TileMap map_tile(const int64_t *__restrict__ off, const FxTile &T, int64_t *s_off)
+// Stages the offsets without the barrier (the caller syncs before reading them).
+__device__ __forceinline__ TileMap map_tile_async(const int64_t *__restrict__ off, const FxTile &T, int64_t *s_off)
 {
     TileMap m;
     m.p0 = T.p0;
@@ -181,6 +182,12 @@ __device__ __forceinline__ TileMap map_tile(const int64_t *__restrict__ off, con
     if (m.staged) {
         for (int64_t k = threadIdx.x; k <= m.np; k += FX_BS) s_off[k] = off[m.p0 + k];  // off[p1 + 1] exists
     }
+    return m;
+}
+
+__device__ __forceinline__ TileMap map_tile(const int64_t *__restrict__ off, const FxTile &T, int64_t *s_off)
+{
+    const TileMap m = map_tile_async(off, T, s_off);
     __syncthreads();
     return m;
 }
@@ -385,24 +392,46 @@ __device__ __forceinline__ void tile_map_one(const FxSeg *__restrict__ segs, con
     tmap[b] = t;
 }
 
+// For the single-pass expansion (cstat non-null) it also clears the tiles'
+// status words and the ticket counter; with sstat, the two block scans'
+// status words and tickets.
 template <int ITEMS>
 __global__ __launch_bounds__(FX_BS) void k_tile_map(const FxSeg *__restrict__ segs, const uint32_t *__restrict__ blk0s,
-                                                    int32_t nsegs, uint32_t nblocks, FxTile *tmap)
+                                                    int32_t nsegs, uint32_t nblocks, FxTile *tmap, uint64_t *cstat,
+                                                    uint64_t *lstat, uint32_t *ticket, uint64_t *sstat)
 {
     const uint32_t b = blockIdx.x * FX_BS + threadIdx.x;
-    if (b < nblocks) tile_map_one<ITEMS>(segs, blk0s, nsegs, b, tmap);
+    if (sstat && b < scan_state_words(nblocks)) sstat[b] = 0;
+    if (b < nblocks) {
+        tile_map_one<ITEMS>(segs, blk0s, nsegs, b, tmap);
+        if (cstat) {
+            cstat[b] = 0;
+            lstat[b] = 0;
+            if (b == 0) *ticket = 0;
+        }
+    }
 }
 
 // The same over a fixed grid, with the step's size from the scheduler.
 template <int ITEMS>
 __global__ __launch_bounds__(FX_BS) void k_tile_map_chain(const FxSeg *__restrict__ segs,
                                                           const uint32_t *__restrict__ blk0s, const FxChainCtl *ctl,
-                                                          FxTile *tmap)
+                                                          FxTile *tmap, uint64_t *cstat, uint64_t *lstat,
+                                                          uint32_t *ticket, uint64_t *sstat)
 {
     const uint32_t nb = ctl->nblocks;
     const int32_t ns = (int32_t)ctl->nsegs;
-    for (uint32_t b = blockIdx.x * FX_BS + threadIdx.x; b < nb; b += gridDim.x * FX_BS)
+    if (sstat)
+        for (uint32_t b = blockIdx.x * FX_BS + threadIdx.x; b < scan_state_words(nb); b += gridDim.x * FX_BS)
+            sstat[b] = 0;
+    for (uint32_t b = blockIdx.x * FX_BS + threadIdx.x; b < nb; b += gridDim.x * FX_BS) {
         tile_map_one<ITEMS>(segs, blk0s, ns, b, tmap);
+        if (cstat) {
+            cstat[b] = 0;
+            lstat[b] = 0;
+        }
+    }
+    if (cstat && blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
 }
 
 template <int W>
@@ -463,11 +492,13 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
     return (uint64_t)c;
 }
 
-// Test every candidate of every segment (ITEMS per thread, strided by
-// the workgroup size so each item pass covers consecutive candidates).
-// Writes, per candidate, its vertex id when it passes (-1 when not), so the
-// scatter never reads the candidate's adjacency entry again, and the number
-// of passes per workgroup.
+// Test every candidate of a workgroup's tile (ITEMS per thread, strided by
+// the workgroup size so each item pass covers consecutive candidates).  Per
+// item, the wave's ballot of the candidates that pass (bal); per candidate,
+// at cv[it * FX_BS + threadIdx.x], its vertex id (-1 when it does not pass)
+// and, when pi is given, its partial relative to the tile's first.
+// Counting segments count (and hash) here; the per-query counters and byte
+// tallies are added with one atomic per wave.
 struct ProbeLds {
     int64_t s_off[FX_LDSP + 1];
     uint8_t s_dead[FX_LDSP];
@@ -475,16 +506,12 @@ struct ProbeLds {
 };
 
 template <int ITEMS, int W>
-__device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__restrict__ segs,
-                                           const FxTile *__restrict__ tmap, int32_t *cand, uint32_t *bcnt,
-                                           const uint32_t blk, ProbeLds &lds)
+__device__ __forceinline__ TileMap probe_core(const FxGraphDev &g, const FxSeg &S, const FxTile &T, const uint32_t blk,
+                                              ProbeLds &lds, uint64_t (&bal)[ITEMS], int32_t *cv, int32_t *pi)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
     int64_t *s_off = lds.s_off;
     uint8_t *s_dead = lds.s_dead;
-    uint32_t *wcnt = lds.wcnt;
-    const FxTile T = tmap[blk];
-    const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
     const int32_t l = S.l, n = S.n, flags = S.flags;
     const uint32_t tile0 = (blk - S.blk0) * TILE;
     const TileMap m = map_tile(S.in.off, T, s_off);
@@ -509,7 +536,7 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
     const bool images = (flags & FX_PROBE_IMAGES) != 0;
     const bool sym = (flags & FX_PROBE_SYM) != 0;
     const bool ref = (flags & FX_PROBE_REF) != 0;
-    uint32_t passed = 0, uout = 0;
+    uint32_t uout = 0;
     unsigned long long cnt = 0;
     unsigned long long rbytes = 0, dbytes = 0;  // reference algorithmic bytes (counting pass): run, row model
     uint64_t h1 = 0, h2 = 0;
@@ -522,6 +549,7 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
             Cand<W> x;
             const int64_t p = tile_part(m, S.in.off, s_off, t);
             load_cand(g, S.in, l, p, t, x);
+            if (pi) pi[it * FX_BS + threadIdx.x] = (int32_t)(p - m.p0);
             // candidate entry + the pass word; the partial row and its run descriptor once
             bytes += (x.anc >= 0 ? 8u : 4u) + 4u;
             if (x.first || tl == tile0) bytes += 4u * (uint32_t)l + 21u;
@@ -574,9 +602,9 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
                 if (leaf) cnt += leaf_count(g, S.plan, l, x, bytes);
                 mat = S.kind != FX_SEG_COUNT;
             }
-            cand[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x] = mat ? x.c : -1;
+            cv[it * FX_BS + threadIdx.x] = mat ? x.c : -1;
         }
-        passed += mat ? 1u : 0u;
+        bal[it] = __ballot(mat);
     }
     if (count || leaf) {  // uniform across the workgroup
         unsigned long long c = cnt;
@@ -595,17 +623,15 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
     }
     {
         unsigned long long b = bytes;
-        uint32_t pc = passed, uo = uout;
+        uint32_t uo = uout;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             b += __shfl_xor(b, o);
-            pc += __shfl_xor(pc, o);
             uo += __shfl_xor(uo, o);
         }
         if (__lane_id() == 0) {
             if (b) atomicAdd(&S.sum->alg_probe, b);
             if (uo) atomicAdd(&S.sum->ufiltered, (unsigned long long)uo);
-            wcnt[threadIdx.x >> 6] = pc;
         }
     }
     if (ref) {  // uniform across the workgroup
@@ -618,8 +644,28 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
         if (__lane_id() == 0 && r) atomicAdd(&S.sum->ref_probe, r);
         if (__lane_id() == 0 && d) atomicAdd(&S.sum->ref_probe_row, d);
     }
+    return m;
+}
+
+// Probe pass of the multi-kernel expansion: per candidate its vertex id when
+// it passes (-1 when not), so the scatter never reads the candidate's
+// adjacency entry again, and the number of passes per workgroup.
+template <int ITEMS, int W>
+__device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__restrict__ segs,
+                                           const FxTile *__restrict__ tmap, int32_t *cand, uint32_t *bcnt,
+                                           const uint32_t blk, ProbeLds &lds)
+{
+    constexpr uint32_t TILE = FX_BS * ITEMS;
+    const FxTile T = tmap[blk];
+    const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
+    uint64_t bal[ITEMS];
+    probe_core<ITEMS, W>(g, S, T, blk, lds, bal, cand + (uint64_t)blk * TILE, nullptr);
+    uint32_t passed = 0;
+#pragma unroll
+    for (int it = 0; it < ITEMS; it++) passed += (uint32_t)__popcll(bal[it]);
+    if (__lane_id() == 0) lds.wcnt[threadIdx.x >> 6] = passed;
     __syncthreads();
-    if (threadIdx.x == 0) bcnt[blk] = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (threadIdx.x == 0) bcnt[blk] = lds.wcnt[0] + lds.wcnt[1] + lds.wcnt[2] + lds.wcnt[3];
 }
 
 template <int ITEMS, int W>
@@ -643,59 +689,151 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     }
 }
 
-// Exclusive scan of per-workgroup values over the whole launch (one
-// workgroup of 16 waves); boff[nblocks] receives the total.  Wave w owns a
-// contiguous range of the values: it sums the range with coalesced loads, the
-// 16 totals give each wave its starting offset, then the wave scans its range
-// 64 values at a time (a shuffle scan per chunk plus a running carry).
-template <class T>
-__device__ __forceinline__ void scan_blocks(const T *__restrict__ bcnt, uint32_t nblocks, uint64_t *boff)
+// Decoupled look-back over ordered workgroups (the block scans and the
+// single-pass expansion).  Status word of a tile: bits 63..62 the state (0 not
+// ready, 1 the tile's own total, 2 the inclusive prefix of its segment up to
+// the tile), bits 61..0 the value.  k_tile_map clears the words of a step's
+// tiles before the launch.
+constexpr uint64_t kStatAgg = 1ull << 62;
+constexpr uint64_t kStatPre = 2ull << 62;
+constexpr uint64_t kStatVal = (1ull << 62) - 1;
+
+__device__ __forceinline__ void stat_put(uint64_t *st, uint32_t b, uint64_t w)
 {
-    constexpr uint32_t W = 1024 / 64;
-    __shared__ unsigned long long wtot[W];
-    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
-    const uint32_t per = (nblocks + W * 64 - 1) / (W * 64) * 64;  // a multiple of 64
-    const uint32_t beg = wave * per;
-    const uint32_t end = beg < nblocks ? min(beg + per, nblocks) : beg;
-    unsigned long long s = 0;
-#pragma unroll 8
-    for (uint32_t k = beg + lane; k < end; k += 64) s += (unsigned long long)bcnt[k];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) wtot[wave] = s;
-    __syncthreads();
-    unsigned long long carry = 0, total = 0;
-    for (uint32_t w = 0; w < W; w++) {
-        carry += w < wave ? wtot[w] : 0ULL;
-        total += wtot[w];
-    }
-#pragma unroll 4
-    for (uint32_t k0 = beg; k0 < end; k0 += 64) {
-        const uint32_t k = k0 + lane;
-        const unsigned long long v = k < end ? (unsigned long long)bcnt[k] : 0ULL;
-        unsigned long long inc = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned long long u = __shfl_up(inc, o);
-            if (lane >= (uint32_t)o) inc += u;
+    __hip_atomic_store(st + b, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of the values of tiles s0..b-1 (b > s0), called by one whole wave.  The
+// wave reads the status words of up to 64 preceding tiles at once; if a tile
+// nearer than the nearest inclusive prefix is not ready it reads the window
+// again after a short sleep, else it adds the totals down to that prefix (or
+// all 64 and moves on).  The wait ends: every tile s0..b-1 got its ticket
+// before b, so it is running or done, and it publishes its total before it
+// waits on anything itself; tile s0 publishes an inclusive prefix.
+__device__ uint64_t look_back(const uint64_t *st, uint32_t b, uint32_t s0)
+{
+    const uint32_t lane = __lane_id();
+    uint64_t sum = 0;
+    int64_t top = (int64_t)b - 1;  // nearest tile not yet added
+    while (top >= (int64_t)s0) {   // uniform across the wave
+        const int64_t j = top - (int64_t)lane;
+        const uint64_t w = j >= (int64_t)s0 ? __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                            : kStatPre;  // lanes before the segment: never reached
+        const uint32_t state = (uint32_t)(w >> 62);
+        const uint64_t pm = __ballot(state == 2), xm = __ballot(state == 0);
+        const uint64_t upto = pm ? (((pm & (~pm + 1)) << 1) - 1) : ~0ull;  // lanes down to the nearest prefix
+        if (xm & upto) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
         }
-        if (k < end) boff[k] = carry + inc - v;
-        carry += __shfl(inc, 63);
+        unsigned long long v = ((upto >> lane) & 1ull) ? (w & kStatVal) : 0ull;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        sum += v;
+        if (pm) break;
+        top -= 64;
     }
-    if (threadIdx.x == 0) boff[nblocks] = total;
+    return sum;
+}
+
+// Exclusive prefix of a tile's value within its segment, published on the
+// way: the tile's total first, then its inclusive prefix.  Called by wave 0.
+__device__ __forceinline__ uint64_t tile_prefix(uint64_t *st, uint32_t blk, uint32_t s0, uint64_t agg)
+{
+    const bool lead = __lane_id() == 0;
+    if (blk == s0) {
+        if (lead) stat_put(st, blk, kStatPre | agg);
+        return 0;
+    }
+    if (lead) stat_put(st, blk, kStatAgg | agg);
+    const uint64_t excl = look_back(st, blk, s0);
+    if (lead) stat_put(st, blk, kStatPre | (excl + agg));
+    return excl;
+}
+
+// Exclusive scan of per-workgroup values (n of them; out[n] receives the
+// total): chunks of kScanChunk values, one workgroup each, taken by ticket;
+// each workgroup scans its chunk (4 values per thread, a shuffle scan per
+// wave, the wave totals in LDS) and finds the chunk's prefix by look-back.
+// A step's scan state (sstat, cleared by k_tile_map) holds, per scan (which =
+// 0, 1), scan_chunks(n) status words and the ticket counter after them.  Every chunk is the same small amount of work, so the
+// look-back rarely waits.
+struct ScanLds {
+    unsigned long long wt[FX_BS / 64];
+    unsigned long long excl;
+    uint32_t chunk;
+};
+
+template <class T>
+__device__ __forceinline__ void scan_chunk(const T *__restrict__ vals, uint32_t n, uint64_t *out, uint64_t *st,
+                                           uint32_t c, uint32_t nch, ScanLds &lds)
+{
+    constexpr uint32_t PER = kScanChunk / FX_BS;
+    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
+    const uint32_t base = c * kScanChunk + threadIdx.x * PER;
+    unsigned long long v[PER], sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < PER; k++) {
+        v[k] = base + k < n ? (unsigned long long)vals[base + k] : 0ull;
+        sum += v[k];
+    }
+    unsigned long long inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long u = __shfl_up(inc, o);
+        if (lane >= (uint32_t)o) inc += u;
+    }
+    if (lane == 63) lds.wt[wave] = inc;
+    __syncthreads();
+    unsigned long long agg = 0, woff = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < FX_BS / 64; w++) {
+        agg += lds.wt[w];
+        woff += w < wave ? lds.wt[w] : 0ull;
+    }
+    if (wave == 0) {
+        const uint64_t e = tile_prefix(st, c, 0, agg);
+        if (lane == 0) lds.excl = e;
+    }
+    __syncthreads();
+    unsigned long long run = lds.excl + woff + inc - sum;
+#pragma unroll
+    for (uint32_t k = 0; k < PER; k++) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (c == nch - 1 && threadIdx.x == 0) out[n] = lds.excl + agg;
 }
 
 template <class T>
-__global__ __launch_bounds__(1024) void k_scan_blocks(const T *__restrict__ bcnt, uint32_t nblocks, uint64_t *boff)
+__global__ __launch_bounds__(FX_BS) void k_scan_blocks(const T *__restrict__ vals, uint32_t n, uint64_t *out,
+                                                       uint64_t *sstat, uint32_t which)
 {
-    scan_blocks<T>(bcnt, nblocks, boff);
+    __shared__ ScanLds lds;
+    const uint32_t nch = scan_chunks(n);
+    uint64_t *st = sstat + which * (nch + 1);  // the step's first or second scan
+    if (threadIdx.x == 0) lds.chunk = atomicAdd(reinterpret_cast<uint32_t *>(st + nch), 1u);
+    __syncthreads();
+    scan_chunk<T>(vals, n, out, st, lds.chunk, nch, lds);
 }
 
+// The same over a fixed grid, with the count from the scheduler.
 template <class T>
-__global__ __launch_bounds__(1024) void k_scan_blocks_chain(const T *__restrict__ bcnt, const FxChainCtl *ctl,
-                                                            uint64_t *boff)
+__global__ __launch_bounds__(FX_BS) void k_scan_blocks_chain(const T *__restrict__ vals, const FxChainCtl *ctl,
+                                                             uint64_t *out, uint64_t *sstat, uint32_t which)
 {
-    scan_blocks<T>(bcnt, ctl->nblocks, boff);
+    __shared__ ScanLds lds;
+    const uint32_t n = ctl->nblocks;
+    const uint32_t nch = scan_chunks(n);
+    uint64_t *st = sstat + which * (nch + 1);
+    for (;;) {
+        if (threadIdx.x == 0) lds.chunk = atomicAdd(reinterpret_cast<uint32_t *>(st + nch), 1u);
+        __syncthreads();
+        const uint32_t c = lds.chunk;
+        if (c >= nch) break;  // uniform across the workgroup
+        scan_chunk<T>(vals, n, out, st, c, nch, lds);
+        __syncthreads();  // LDS reused by the next chunk
+    }
 }
 
 // Ordered write of the passing candidates of each segment into its level l+1
@@ -726,6 +864,13 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
     auto &wcnt = lds.wcnt;
     auto &ltot = lds.ltot;
     const FxTile T = tmap[blk];
+    // loads that do not depend on the segment first, so their latencies
+    // overlap the segment's: the tile's probe results (the buffer holds whole
+    // tiles; entries past the span are masked below) and its pass offsets
+    int32_t cv[ITEMS];  // the passing candidates' vertex ids (from the probe)
+#pragma unroll
+    for (int it = 0; it < ITEMS; it++) cv[it] = cand[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x];
+    const uint64_t b_lo = boff[blk], b_hi = boff[blk + 1];
     const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
     const int32_t l = S.l, n = S.n;
     const uint64_t seg_base = boff[S.blk0];
@@ -741,24 +886,25 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
     if (S.kind == FX_SEG_COUNT) return;  // nothing is written for a counting segment
     // a tile without passing candidates, or whose passes all fall past the row
     // cap, writes nothing (its run-length total is 0); uniform per workgroup
-    if (boff[blk + 1] == boff[blk] || boff[blk] - seg_base >= cap) {
+    if (b_hi == b_lo || b_lo - seg_base >= cap) {
         if (threadIdx.x == 0) lsum[blk] = 0;
         return;
     }
     const uint32_t tile0 = (blk - S.blk0) * TILE;
     const uint32_t wave = threadIdx.x >> 6;
+    // the partials' offsets are staged before the ballots wait for cv
+    const TileMap m = map_tile_async(S.in.off, T, s_off);
     uint64_t bal[ITEMS];
     bool f[ITEMS];
-    int32_t cv[ITEMS];  // the passing candidates' vertex ids (from the probe)
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
-        cv[it] = tl < S.span ? cand[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x] : -1;
+        if (tl >= S.span) cv[it] = -1;
         f[it] = cv[it] >= 0;
         bal[it] = __ballot(f[it]);
         if (__lane_id() == 0) wcnt[it][wave] = (uint32_t)__popcll(bal[it]);
     }
-    const TileMap m = map_tile(S.in.off, T, s_off);
+    __syncthreads();  // the staged offsets and the wave counts
     const int32_t w1 = l + 1;
     uint32_t bytes = 0;
     uint64_t pos = boff[blk] - seg_base;
@@ -929,6 +1075,231 @@ __global__ __launch_bounds__(FX_BS) void k_fix_off_chain(const FxSeg *__restrict
 {
     const uint32_t nb = ctl->nblocks;
     for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) fix_off_tile<ITEMS>(segs, tmap, boff, loff, b);
+}
+
+// ---------------------------------------------------------------------------
+// Single-pass expansion: probe, ordered write and run-length offsets of a
+// step in one kernel.  Each workgroup takes a ticket (tiles are handed out in
+// tile order), probes its tile, and finds the passes before it in its segment
+// by a decoupled look-back over the status words of the preceding tiles; it
+// then writes its rows and, for inner segments, finds the run lengths before
+// them the same way.  Replaces the probe, the two block scans, the scatter and
+// the offset fix-up of the multi-kernel form, with the same output.
+// ---------------------------------------------------------------------------
+
+template <int ITEMS>
+struct ExpandLds {
+    ProbeLds probe;
+    int32_t cv[FX_BS * ITEMS];  // candidate ids (-1: did not pass)
+    int32_t pi[FX_BS * ITEMS];  // their partials, relative to the tile's first
+    uint32_t wc[ITEMS][FX_BS / 64];
+    unsigned long long lt[ITEMS][FX_BS / 64];
+    unsigned long long excl, lexcl;
+    uint32_t tile;
+};
+
+template <int ITEMS, int W>
+__device__ __forceinline__ void expand_tile(const FxGraphDev &g, const FxSeg *__restrict__ segs,
+                                            const FxTile *__restrict__ tmap, uint64_t *cstat, uint64_t *lstat,
+                                            const uint32_t blk, ExpandLds<ITEMS> &lds)
+{
+    constexpr uint32_t TILE = FX_BS * ITEMS;
+    const FxTile T = tmap[blk];
+    const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
+    uint64_t bal[ITEMS];
+    const TileMap m = probe_core<ITEMS, W>(g, S, T, blk, lds.probe, bal, lds.cv, lds.pi);
+    const int32_t l = S.l, n = S.n;
+    const uint32_t tile0 = (blk - S.blk0) * TILE;
+    const uint32_t nblk = (S.span + TILE - 1) / TILE;
+    const bool last = blk == S.blk0 + nblk - 1;
+    if (S.kind == FX_SEG_COUNT) {  // nothing is written; no tile of the segment waits on another
+        if (blk == S.blk0 && threadIdx.x == 0) {
+            S.sum->passes = 0;
+            S.sum->total_out = 0;
+            S.sum->consumed = S.span;
+        }
+        return;
+    }
+    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
+#pragma unroll
+    for (int it = 0; it < ITEMS; it++)
+        if (lane == 0) lds.wc[it][wave] = (uint32_t)__popcll(bal[it]);
+    __syncthreads();
+    uint64_t agg = 0;
+#pragma unroll
+    for (int it = 0; it < ITEMS; it++)
+        for (uint32_t w = 0; w < FX_BS / 64; w++) agg += lds.wc[it][w];
+    if (wave == 0) {
+        const uint64_t e = tile_prefix(cstat, blk, S.blk0, agg);
+        if (lane == 0) lds.excl = e;
+    }
+    __syncthreads();
+    const uint64_t excl = lds.excl;
+    const uint64_t cap = S.out_cap;
+    const int32_t w1 = l + 1;
+    uint32_t bytes = 0;
+    uint64_t pos = excl;
+    // row of each item in the segment's output (written when < out_cap); kept
+    // as the wave's ballot plus counts, and recomputed where needed
+    auto row_of = [&](int it, uint64_t base) -> uint64_t {
+        uint64_t po = base + (uint64_t)__popcll(bal[it] & lanemask_lt());
+        for (uint32_t w = 0; w < wave; w++) po += lds.wc[it][w];
+        return po;
+    };
+    int32_t lens[ITEMS];
+    uint32_t written = 0;  // rows this thread wrote (the reference byte tally)
+#pragma unroll
+    for (int it = 0; it < ITEMS; it++) {
+        const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
+        const bool mat = (bal[it] >> lane) & 1ull;
+        lens[it] = 0;
+        const uint64_t po = row_of(it, pos);
+        // the first pass past the row cap: it and the candidates after it are
+        // probed again in a later step
+        if (mat && po == cap) S.sum->consumed = tl;
+        const bool f = mat && po < cap;
+        const uint32_t p_out = (uint32_t)po;
+        bytes += f ? 4u * (uint32_t)(l + w1) + (w1 < n ? 21u : 0u) : 0u;
+        written += f ? 1u : 0u;
+        if (f) {
+            Cand<W> x;
+            const int32_t *row = S.in.rows + (m.p0 + lds.pi[it * FX_BS + threadIdx.x]) * l;
+#pragma unroll
+            for (int k = 0; k < W; k++) x.v[k] = (k < l) ? row[k] : -1;
+            x.c = lds.cv[it * FX_BS + threadIdx.x];
+            int32_t *dst = S.out.rows + (uint64_t)p_out * (uint32_t)w1;
+#pragma unroll
+            for (int k = 0; k < W; k++)
+                if (k < l) dst[k] = x.v[k];
+            dst[l] = x.c;
+            if (w1 < n) {
+                // candidate run of the next pattern vertex i2 = l + 1: the
+                // shortest run among its earlier neighbours, or its label bucket
+                const FxPlan *plan = S.plan;
+                const int32_t i2 = w1;
+                const uint32_t vl = plan->vl[i2];
+                const int32_t nb = plan->nback[i2];
+                int64_t best_lo = 0;
+                int32_t best_len = 0;
+                int32_t best_anc = -1;
+                if (nb == 0) {
+                    best_lo = g.bptr[vl];
+                    best_len = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
+                } else {
+                    best_len = 0x7fffffff;
+                    for (int kk = 0; kk < nb; kk++) {
+                        const int32_t b = plan->back[i2][kk];
+                        const int32_t u = (b == l) ? x.c : pick(x.v, b);
+                        int64_t lo;
+                        int32_t len;
+                        run_of<scan_width<W>()>(g, u, run_key(vl, plan->bel[i2][kk]), lo, len, bytes);
+                        if (len < best_len) {
+                            best_len = len;
+                            best_lo = lo;
+                            best_anc = kk;
+                        }
+                    }
+                }
+                S.out.lo[p_out] = best_lo;
+                S.out.len[p_out] = best_len;
+                S.out.anc[p_out] = (int8_t)best_anc;
+                lens[it] = best_len;
+            }
+        }
+        for (uint32_t w = 0; w < FX_BS / 64; w++) pos += lds.wc[it][w];
+    }
+    const uint64_t seg_pass = excl + agg;  // meaningful in the segment's last tile
+    const uint64_t nout = seg_pass < cap ? seg_pass : cap;
+    if (last && threadIdx.x == 0) {
+        S.sum->passes = seg_pass;
+        S.sum->total_out = nout;
+        if (seg_pass <= cap) S.sum->consumed = S.span;
+    }
+    if (S.kind == FX_SEG_INNER) {  // uniform across the workgroup
+        // run lengths before each new row: wave totals per item, the tile's
+        // prefix in its segment by look-back, then each lane's scan in its wave
+#pragma unroll
+        for (int it = 0; it < ITEMS; it++) {
+            unsigned long long tot = (unsigned long long)lens[it];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o);
+            if (lane == 0) lds.lt[it][wave] = tot;
+        }
+        __syncthreads();
+        uint64_t lagg = 0;
+#pragma unroll
+        for (int it = 0; it < ITEMS; it++)
+            for (uint32_t w = 0; w < FX_BS / 64; w++) lagg += lds.lt[it][w];
+        if (wave == 0) {
+            const uint64_t e = tile_prefix(lstat, blk, S.blk0, lagg);
+            if (lane == 0) lds.lexcl = e;
+        }
+        __syncthreads();
+        uint64_t before = lds.lexcl;
+        uint64_t rows = excl;
+#pragma unroll
+        for (int it = 0; it < ITEMS; it++) {
+            long long inc = lens[it];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const long long u = __shfl_up(inc, o);
+                if (lane >= (uint32_t)o) inc += u;
+            }
+            uint64_t mine = before;
+            for (uint32_t w = 0; w < wave; w++) mine += lds.lt[it][w];
+            const uint64_t po = row_of(it, rows);
+            if (((bal[it] >> lane) & 1ull) && po < cap) S.out.off[po] = (int64_t)(mine + (uint64_t)(inc - lens[it]));
+            for (uint32_t w = 0; w < FX_BS / 64; w++) {
+                before += lds.lt[it][w];
+                rows += lds.wc[it][w];
+            }
+        }
+        if (last && threadIdx.x == 0) {  // close the level: off[N] and its candidate total
+            S.out.off[nout] = (int64_t)before;
+            S.sum->t_next = before;
+        }
+    }
+    unsigned long long b = bytes;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) b += __shfl_xor(b, o);
+    if (lane == 0 && b) atomicAdd(&S.sum->alg_scatter, b);
+    if (S.flags & FX_PROBE_REF) {  // reference bytes: the rows written, 4 (l + 1) each
+        unsigned long long r = 4ull * written * (uint32_t)w1;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) r += __shfl_xor(r, o);
+        if (lane == 0 && r) atomicAdd(&S.sum->ref_scatter, r);
+    }
+}
+
+// One workgroup per tile; the tile is the workgroup's ticket, not its index.
+template <int ITEMS, int W>
+__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_expand(
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, uint64_t *cstat, uint64_t *lstat,
+    uint32_t *ticket)
+{
+    __shared__ ExpandLds<ITEMS> lds;
+    if (threadIdx.x == 0) lds.tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    expand_tile<ITEMS, W>(g, segs, tmap, cstat, lstat, lds.tile, lds);
+}
+
+// The same over a fixed grid: each workgroup takes tickets until they pass
+// the step's tile count from the scheduler.
+template <int ITEMS, int W>
+__global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_expand_chain(
+    FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, uint64_t *cstat, uint64_t *lstat,
+    uint32_t *ticket, const FxChainCtl *ctl)
+{
+    __shared__ ExpandLds<ITEMS> lds;
+    const uint32_t nb = ctl->nblocks;
+    for (;;) {
+        if (threadIdx.x == 0) lds.tile = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t b = lds.tile;
+        if (b >= nb) break;  // uniform across the workgroup
+        expand_tile<ITEMS, W>(g, segs, tmap, cstat, lstat, b, lds);
+        __syncthreads();  // the tile's LDS (and its ticket) is reused by the next
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1655,23 +2026,37 @@ hipError_t fx_launch_mni(hipStream_t s, const uint32_t *img, uint64_t words, int
 template <int ITEMS, int W>
 hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
                              int32_t nsegs, uint32_t nblocks, FxTile *tmap, int32_t *cand, uint32_t *bcnt, uint64_t *boff,
-                             uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
+                             uint64_t *lsum, uint64_t *loff, uint64_t *sstat, hipEvent_t probe_begin,
                              hipEvent_t probe_end,
                              hipEvent_t scatter_begin, hipEvent_t scatter_end, hipEvent_t greedy_begin,
-                             hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
+                             hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy, int32_t fused)
 {
     hipError_t e;
-    hipLaunchKernelGGL(k_tile_map<ITEMS>, dim3((nblocks + FX_BS - 1) / FX_BS), dim3(FX_BS), 0, s, segs, blk0s, nsegs,
-                       nblocks, tmap);
+    if (fused) {  // single pass: boff / loff hold the tiles' status words, lsum the ticket counter
+        uint32_t *ticket = reinterpret_cast<uint32_t *>(lsum);
+        hipLaunchKernelGGL(k_tile_map<ITEMS>, dim3((nblocks + FX_BS - 1) / FX_BS), dim3(FX_BS), 0, s, segs, blk0s,
+                           nsegs, nblocks, tmap, boff, loff, ticket, nullptr);
+        if (probe_begin && (e = hipEventRecord(probe_begin, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_expand<ITEMS, W>), dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, boff, loff, ticket);
+        if (probe_end && (e = hipEventRecord(probe_end, s)) != hipSuccess) return e;
+        if (greedy_begin && (e = hipEventRecord(greedy_begin, s)) != hipSuccess) return e;
+        if (any_greedy) hipLaunchKernelGGL(k_greedy<false>, dim3(nsegs), dim3(FX_BS), 0, s, segs, nullptr);
+        if (greedy_end && (e = hipEventRecord(greedy_end, s)) != hipSuccess) return e;
+        return hipGetLastError();
+    }
+    const uint32_t nch = scan_chunks(nblocks);
+    const uint32_t nmap = max(nblocks, scan_state_words(nblocks));
+    hipLaunchKernelGGL(k_tile_map<ITEMS>, dim3((nmap + FX_BS - 1) / FX_BS), dim3(FX_BS), 0, s, segs, blk0s, nsegs,
+                       nblocks, tmap, nullptr, nullptr, nullptr, sstat);
     if (probe_begin && (e = hipEventRecord(probe_begin, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_probe<ITEMS, W>), dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, cand, bcnt);
     if (probe_end && (e = hipEventRecord(probe_end, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_blocks<uint32_t>, dim3(1), dim3(1024), 0, s, bcnt, nblocks, boff);
+    hipLaunchKernelGGL(k_scan_blocks<uint32_t>, dim3(nch), dim3(FX_BS), 0, s, bcnt, nblocks, boff, sstat, 0u);
     if (scatter_begin && (e = hipEventRecord(scatter_begin, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_scatter<ITEMS, W>), dim3(nblocks), dim3(FX_BS), 0, s, g, segs, tmap, cand, boff, lsum);
     if (scatter_end && (e = hipEventRecord(scatter_end, s)) != hipSuccess) return e;
     if (any_inner) {
-        hipLaunchKernelGGL(k_scan_blocks<uint64_t>, dim3(1), dim3(1024), 0, s, lsum, nblocks, loff);
+        hipLaunchKernelGGL(k_scan_blocks<uint64_t>, dim3(nch), dim3(FX_BS), 0, s, lsum, nblocks, loff, sstat, 1u);
         hipLaunchKernelGGL(k_fix_off<ITEMS>, dim3(nblocks), dim3(FX_BS), 0, s, segs, tmap, boff, loff);
     }
     if (greedy_begin && (e = hipEventRecord(greedy_begin, s)) != hipSuccess) return e;
@@ -1683,21 +2068,36 @@ hipError_t launch_step_items(hipStream_t s, const FxGraphDev &g, const FxSeg *se
 template <int ITEMS, int W>
 hipError_t launch_chain_items(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
                               int32_t steps, FxSeg *segs, uint32_t *blk0s, FxTile *tmap, int32_t *cand, uint32_t *bcnt,
-                              uint64_t *boff, uint64_t *lsum, uint64_t *loff)
+                              uint64_t *boff, uint64_t *lsum, uint64_t *loff, uint64_t *sstat, int32_t fused)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
     // enough workgroups to fill the chip at the expansion kernels' occupancy
     // (8 waves per SIMD, 4 waves per workgroup: 8 per CU on 256 CUs); each
     // loops over the tiles the scheduler announced
-    constexpr uint32_t kGrid = 2048, kMapGrid = 64;
+    constexpr uint32_t kGrid = 2048, kMapGrid = 64, kScanGrid = 128;
+    if (fused) {
+        uint32_t *ticket = reinterpret_cast<uint32_t *>(lsum);
+        for (int32_t k = 0; k < steps; k++) {
+            hipLaunchKernelGGL(k_sched, dim3(1), dim3(64), 0, s, cq, ctl, segs, blk0s, TILE, 0);
+            hipLaunchKernelGGL(k_tile_map_chain<ITEMS>, dim3(kMapGrid), dim3(FX_BS), 0, s, segs, blk0s, ctl, tmap,
+                               boff, loff, ticket, nullptr);
+            hipLaunchKernelGGL((k_expand_chain<ITEMS, W>), dim3(kGrid), dim3(FX_BS), 0, s, g, segs, tmap, boff, loff,
+                               ticket, ctl);
+            hipLaunchKernelGGL(k_greedy<true>, dim3(max_q), dim3(FX_BS), 0, s, segs, ctl);
+        }
+        hipLaunchKernelGGL(k_sched, dim3(1), dim3(64), 0, s, cq, ctl, segs, blk0s, TILE, 1);
+        return hipGetLastError();
+    }
     for (int32_t k = 0; k < steps; k++) {
         hipLaunchKernelGGL(k_sched, dim3(1), dim3(64), 0, s, cq, ctl, segs, blk0s, TILE, 0);
-        hipLaunchKernelGGL(k_tile_map_chain<ITEMS>, dim3(kMapGrid), dim3(FX_BS), 0, s, segs, blk0s, ctl, tmap);
+        hipLaunchKernelGGL(k_tile_map_chain<ITEMS>, dim3(kMapGrid), dim3(FX_BS), 0, s, segs, blk0s, ctl, tmap, nullptr,
+                           nullptr, nullptr, sstat);
         hipLaunchKernelGGL((k_probe_chain<ITEMS, W>), dim3(kGrid), dim3(FX_BS), 0, s, g, segs, tmap, cand, bcnt, ctl);
-        hipLaunchKernelGGL(k_scan_blocks_chain<uint32_t>, dim3(1), dim3(1024), 0, s, bcnt, ctl, boff);
+        hipLaunchKernelGGL(k_scan_blocks_chain<uint32_t>, dim3(kScanGrid), dim3(FX_BS), 0, s, bcnt, ctl, boff, sstat, 0u);
         hipLaunchKernelGGL((k_scatter_chain<ITEMS, W>), dim3(kGrid), dim3(FX_BS), 0, s, g, segs, tmap, cand, boff,
                            lsum, ctl);
-        hipLaunchKernelGGL(k_scan_blocks_chain<uint64_t>, dim3(1), dim3(1024), 0, s, lsum, ctl, loff);
+        hipLaunchKernelGGL(k_scan_blocks_chain<uint64_t>, dim3(kScanGrid), dim3(FX_BS), 0, s, lsum, ctl, loff, sstat,
+                           1u);
         hipLaunchKernelGGL(k_fix_off_chain<ITEMS>, dim3(kGrid), dim3(FX_BS), 0, s, segs, tmap, boff, loff, ctl);
         hipLaunchKernelGGL(k_greedy<true>, dim3(max_q), dim3(FX_BS), 0, s, segs, ctl);
     }
@@ -1708,74 +2108,83 @@ hipError_t launch_chain_items(hipStream_t s, const FxGraphDev &g, FxChainQuery *
 template <int W>
 hipError_t launch_chain_width(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
                               int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, FxTile *tmap, int32_t *cand,
-                              uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff)
+                              uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, uint64_t *sstat,
+                              int32_t fused)
 {
     switch (items) {
     case 2:
-        return launch_chain_items<2, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, cand, bcnt, boff, lsum, loff);
+        return launch_chain_items<2, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, cand, bcnt, boff, lsum, loff,
+                                        sstat, fused);
     case 8:
-        return launch_chain_items<8, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, cand, bcnt, boff, lsum, loff);
+        return launch_chain_items<8, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, cand, bcnt, boff, lsum, loff,
+                                        sstat, fused);
     default:
-        return launch_chain_items<4, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, cand, bcnt, boff, lsum, loff);
+        return launch_chain_items<4, W>(s, g, cq, ctl, max_q, steps, segs, blk0s, tmap, cand, bcnt, boff, lsum, loff,
+                                        sstat, fused);
     }
 }
 
 template <int W>
 hipError_t launch_step_width(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
                              int32_t nsegs, uint32_t nblocks, int32_t items, FxTile *tmap, int32_t *cand,
-                             uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff,  hipEvent_t probe_begin,
+                             uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, uint64_t *sstat,
+                             hipEvent_t probe_begin,
                              hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
-                             hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
+                             hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy,
+                             int32_t fused)
 {
     switch (items) {
     case 2:
         return launch_step_items<2, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, cand, bcnt, boff, lsum, loff,
-                                       probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
-                                       any_inner, any_greedy);
+                                       sstat, probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                       any_inner, any_greedy, fused);
     case 8:
         return launch_step_items<8, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, cand, bcnt, boff, lsum, loff,
-                                       probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
-                                       any_inner, any_greedy);
+                                       sstat, probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                       any_inner, any_greedy, fused);
     default:
         return launch_step_items<4, W>(s, g, segs, blk0s, nsegs, nblocks, tmap, cand, bcnt, boff, lsum, loff,
-                                       probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
-                                       any_inner, any_greedy);
+                                       sstat, probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                       any_inner, any_greedy, fused);
     }
 }
 
 hipError_t fx_launch_step(hipStream_t s, const FxGraphDev &g, const FxSeg *segs, const uint32_t *blk0s,
                           int32_t nsegs, uint32_t nblocks, int32_t items, int32_t maxn, FxTile *tmap, int32_t *cand,
-                          uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, hipEvent_t probe_begin,
+                          uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff, uint64_t *sstat,
+                          hipEvent_t probe_begin,
                           hipEvent_t probe_end, hipEvent_t scatter_begin, hipEvent_t scatter_end,
-                          hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy)
+                          hipEvent_t greedy_begin, hipEvent_t greedy_end, int32_t any_inner, int32_t any_greedy,
+                          int32_t fused)
 {
     if (maxn < 1 || maxn > FX_MAXN) return hipErrorInvalidValue;
     if (maxn <= 4)
         return launch_step_width<4>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, cand, bcnt, boff, lsum, loff,
-                                    probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
-                                    any_inner, any_greedy);
+                                    sstat, probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                    any_inner, any_greedy, fused);
     if (maxn <= 8)
         return launch_step_width<8>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, cand, bcnt, boff, lsum, loff,
-                                    probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
-                                    any_inner, any_greedy);
+                                    sstat, probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                    any_inner, any_greedy, fused);
     return launch_step_width<FX_MAXN>(s, g, segs, blk0s, nsegs, nblocks, items, tmap, cand, bcnt, boff, lsum, loff,
-                                      probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
-                                      any_inner, any_greedy);
+                                      sstat, probe_begin, probe_end, scatter_begin, scatter_end, greedy_begin, greedy_end,
+                                      any_inner, any_greedy, fused);
 }
 
 hipError_t fx_launch_chain(hipStream_t s, const FxGraphDev &g, FxChainQuery *cq, FxChainCtl *ctl, int32_t max_q,
                            int32_t steps, FxSeg *segs, uint32_t *blk0s, int32_t items, int32_t maxn, FxTile *tmap,
-                           int32_t *cand, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff)
+                           int32_t *cand, uint32_t *bcnt, uint64_t *boff, uint64_t *lsum, uint64_t *loff,
+                           uint64_t *sstat, int32_t fused)
 {
     if (maxn < 1 || maxn > FX_MAXN || max_q < 1 || steps < 1) return hipErrorInvalidValue;
     if (maxn <= 4)
         return launch_chain_width<4>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, cand, bcnt, boff, lsum,
-                                     loff);
+                                     loff, sstat, fused);
     if (maxn <= 8)
         return launch_chain_width<8>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, cand, bcnt, boff, lsum,
-                                     loff);
+                                     loff, sstat, fused);
     return launch_chain_width<FX_MAXN>(s, g, cq, ctl, max_q, steps, segs, blk0s, items, tmap, cand, bcnt, boff, lsum,
-                                       loff);
+                                       loff, sstat, fused);
 }
 
 hipError_t fx_launch_mis(hipStream_t s, int32_t *rows, int32_t count, int32_t n, uint64_t *hash_scratch,

@@ -88,6 +88,7 @@ fx_status fx_noalloc_setup(fx_ctx *c)
     carve(L.boff, (max_blocks + 1) * 8);
     carve(L.lsum, max_blocks * 8);
     carve(L.loff, (max_blocks + 1) * 8);
+    carve(L.sstat, (size_t)scan_state_words((uint32_t)max_blocks) * 8);
     carve(L.tmap, max_blocks * sizeof(FxTile));
     carve(L.stage_d, 4096);
     carve(L.inits_d, sizeof(FxInit));

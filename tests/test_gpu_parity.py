@@ -843,3 +843,49 @@ def test_directed_graphs(ctx, ctx_small):
     with pytest.raises(fx.FxError) as e:
         ctx.load_graph(bad)
     assert e.value.status == fx.FX_EGRAPH
+
+
+def test_both_expansion_forms(torch_cuda, er1k):
+    """The single-pass expansion (one kernel per step, positions by look-back)
+    and the multi-kernel form (probe, block scans, scatter, offset fix-up, the
+    default) give the oracle's results: tiny graphs with 64-row slices (every
+    level cut at its row cap many times), a mining batch, and device-scheduled
+    chains; the launch counts show which form ran."""
+    g = er1k
+    cands = _mining_candidates(g, 20, 1.0, 3)
+    pats = sample_patterns(g, 12, seed=909, kmin=2, kmax=6)
+    for fused in (1, 0):
+        small = fx.Context(device=0, slice_rows=64, run_index_bytes=-1)
+        small.set("fused", fused)
+        assert small.get("fused") == fused
+        small.stats(reset=True)
+        for idx, gt, p in _tiny_cases(40, 97):
+            _say("forms fused", fused, "tiny", idx)
+            with small.load_graph(gt) as dg:
+                full_match(dg, gt, p, 2, 1.0)
+                list_match(dg, gt, p)
+                verdict_match(dg, gt, p, 3, 0.5)
+        st = small.stats(reset=True)
+        assert st["probe_launches"] > 0
+        assert (st["scatter_launches"] == 0) if fused else (st["scatter_launches"] == st["probe_launches"])
+        big = fx.Context(device=0)
+        big.set("fused", fused)
+        with big.load_graph(g) as dg:
+            _say("forms fused", fused, "batch", len(cands))
+            got = dg.support_batch(cands, [20] * len(cands), [1.0] * len(cands), fx.MODE_FULL)
+            for p, r in zip(cands, got):
+                want = O.query(g, p, 20, 1.0, O.FULL)
+                for k in FULL_KEYS:
+                    assert r[k] == want[k], (fused, p, k, r[k], want[k])
+        small.set("chain_queries", 64)
+        small.set("chain_steps", 8)
+        with small.load_graph(g) as dg:
+            _say("forms fused", fused, "chains", len(pats))
+            got = dg.support_batch(pats, [20] * len(pats), [1.0] * len(pats), fx.MODE_FULL)
+            for p, r in zip(pats, got):
+                want = O.query(g, p, 20, 1.0, O.FULL)
+                for k in FULL_KEYS:
+                    assert r[k] == want[k], (fused, p, k, r[k], want[k])
+        assert small.stats()["chains"] > 0
+        small.close()
+        big.close()
