@@ -873,6 +873,9 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
     const uint64_t b_lo = boff[blk], b_hi = boff[blk + 1];
     const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
     const int32_t l = S.l, n = S.n;
+    // the partials' offsets are staged (for a counting segment or a tile that
+    // writes nothing, needlessly) while the segment's pass offsets load
+    const TileMap m = map_tile_async(S.in.off, T, s_off);
     const uint64_t seg_base = boff[S.blk0];
     const uint64_t seg_pass = boff[S.blk0 + (S.span + TILE - 1) / TILE] - seg_base;
     const uint64_t cap = S.kind == FX_SEG_COUNT ? seg_pass : (uint64_t)S.out_cap;
@@ -892,8 +895,6 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
     }
     const uint32_t tile0 = (blk - S.blk0) * TILE;
     const uint32_t wave = threadIdx.x >> 6;
-    // the partials' offsets are staged before the ballots wait for cv
-    const TileMap m = map_tile_async(S.in.off, T, s_off);
     uint64_t bal[ITEMS];
     bool f[ITEMS];
 #pragma unroll
