@@ -258,11 +258,13 @@ def run_served(srv, queries, rate: float, mode: int, seed: int):
         if wait > 0:
             time.sleep(wait)
         tickets.append(srv.submit(pats[i], sig[i], lam[i], mode))
+        if (i + 1) % 2000 == 0 and i + 1 < n:
+            log(f"[serve] {i + 1}/{n} submitted at {rate} q/s")
     log(f"[serve] {n} submitted at {rate} q/s")
     res = []
     for k, t in enumerate(tickets):
         res.append(srv.wait(t))
-        if (k + 1) % 250 == 0:
+        if (k + 1) % 1000 == 0:
             log(f"[serve] {k + 1}/{n} answered")
     wall = time.perf_counter() - t0
     return _lat_summary([r["device_ms"] for r in res], n, wall), res
@@ -283,7 +285,7 @@ def run_fifo(dg, queries, rate: float, mode: int, seed: int):
             time.sleep(wait)
         res.append(dg.support(pats[i], sig[i], lam[i], mode))
         lat.append((time.perf_counter() - (t0 + arr[i])) * 1e3)
-        if (i + 1) % 100 == 0:
+        if (i + 1) % 500 == 0:
             log(f"[fifo] {i + 1}/{n} answered")
     wall = time.perf_counter() - t0
     return _lat_summary(lat, n, wall), res
