@@ -276,13 +276,13 @@ extern "C" fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *d, fx_graph
     // the last key of v ending where v + 1 starts); positions are 32-bit, so
     // the index needs fewer than 2^32 adjacency entries
     const uint64_t K = (uint64_t)G->dev.nkeys;
-    const uint64_t KW = (K + 31) / 32;
-    const uint64_t index_bytes = ((uint64_t)nv * K + 1) * 4 + (uint64_t)nv * KW * 4;
-    G->dev.kwords = (int32_t)KW;
+    const uint64_t VW = ((uint64_t)nv + 31) / 32;  // words of one key's vertex bitmap
+    const uint64_t index_bytes = ((uint64_t)nv * K + 1) * 4 + K * VW * 4;
+    G->dev.vwords = (int32_t)VW;
     G->dev.keybits = nullptr;
     if (ctx->run_index_bytes >= 0 && index_bytes <= (uint64_t)ctx->run_index_bytes && nadj < 0xffffffffLL) {
         std::vector<uint32_t> ro(nv * K + 1);
-        std::vector<uint32_t> kb(nv * KW, 0u);
+        std::vector<uint32_t> kb(K * VW, 0u);
         const int32_t nel = G->dev.nel;
         parallel_for_chunks(nv, [&](int64_t a, int64_t b) {
             for (int64_t v = a; v < b; v++) {
@@ -293,7 +293,8 @@ extern "C" fx_status fx_graph_load(fx_ctx *ctx, const fx_graph_desc *d, fx_graph
                     const uint64_t e = adj[i];
                     const uint64_t key = (e >> 48) * (uint64_t)nel + ((e >> 32) & 0xffffu);
                     while (k <= key) r[k++] = (uint32_t)i;
-                    kb[v * KW + key / 32] |= 1u << (key % 32);
+                    // neighbouring vertices share a word across chunks: an atomic or
+                    __atomic_fetch_or(&kb[key * VW + (uint64_t)v / 32], 1u << (v % 32), __ATOMIC_RELAXED);
                 }
                 while (k < K) r[k++] = (uint32_t)end;
             }

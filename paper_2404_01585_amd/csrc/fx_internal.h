@@ -19,11 +19,12 @@
 //                              runoff[nv*K] = 2|E|.  Built when it fits the
 //                              index budget and 2|E| < 2^32; otherwise runs are
 //                              found by binary search.
-//   keybits uint32 [nv * KW]   with the run index: bit k of v's KW = ceil(K/32)
-//                              words is set when v has a neighbour with key k
-//                              (the neighbour-label filter's common question,
-//                              "at least one", from an array small enough to
-//                              stay in the last-level cache)
+//   keybits uint32 [K * VW]    with the run index: key-major vertex bitmaps,
+//                              VW = ceil(nv/32); bit v of key k's bitmap is set
+//                              when v has a neighbour with key k (the
+//                              neighbour-label filter's common question, "at
+//                              least one").  The workgroups of a segment test
+//                              one key, so its |V|/8-byte bitmap stays in L2.
 //
 // A pattern plan fixes, for every pattern vertex i (in submitted order), its
 // dense label, its earlier neighbours b < i with the edge label of (b, i),
@@ -80,7 +81,7 @@ struct FxGraphDev {
     int32_t nel;   // dense edge labels
     const uint32_t *runoff;  // label-run index or nullptr
     int32_t nkeys;           // nvl * nel
-    int32_t kwords;          // 32-bit words of keybits per vertex
+    int32_t vwords;          // 32-bit words of one key's vertex bitmap in keybits
     const uint32_t *keybits; // key-presence bits or nullptr (with the run index)
 };
 

@@ -267,11 +267,11 @@ __device__ __forceinline__ bool feasible(const FxGraphDev &g, const FxPlan *__re
         for (int k = 0; k < nf; k++) {
             const uint32_t nk = plan->nlf_key[i][k];
             const int32_t need = plan->nlf_need[i][k];
-            if (g.keybits) {  // presence first: one word of a cache-resident array
+            if (g.keybits) {  // presence first: one word of the key's vertex bitmap
                 const uint32_t kidx = (nk >> 16) * (uint32_t)g.nel + (nk & 0xffffu);
-                const uint32_t w = g.keybits[(uint64_t)(uint32_t)x.c * (uint32_t)g.kwords + (kidx >> 5)];
+                const uint32_t w = g.keybits[(uint64_t)kidx * (uint64_t)g.vwords + ((uint32_t)x.c >> 5)];
                 bytes += 4;
-                if (!((w >> (kidx & 31u)) & 1u)) return false;
+                if (!((w >> ((uint32_t)x.c & 31u)) & 1u)) return false;
                 if (need <= 1) continue;
             }
             int64_t lo;
