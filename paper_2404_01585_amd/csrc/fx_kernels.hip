@@ -164,46 +164,103 @@ struct Cand {
 };
 
 // The partials a workgroup's tile of candidates [tfirst, tlast] touches:
-// [p0, p0 + np).  When they are few, their offsets are staged in LDS so each
-// thread finds its partial with an LDS search.  Called by every thread.
+// [p0, p0 + np).  When they are few, their offsets are staged in LDS and a
+// map from each of the tile's candidates to its partial is built there (see
+// map_tile_parts), so a thread finds its partial with one LDS read.  Called
+// by every thread.
 struct TileMap {
     int64_t p0;
     int64_t np;
     bool staged;
+    uint64_t t0;            // flattened index of the tile's first candidate
+    const uint32_t *pk;     // partial of each of the tile's candidates, from p0 (staged tiles)
 };
 
-// Stages the offsets without the barrier (the caller syncs before reading them).
-__device__ __forceinline__ TileMap map_tile_async(const int64_t *__restrict__ off, const FxTile &T, int64_t *s_off)
+// LDS of the tile map: the staged offsets and the candidate-to-partial map
+// of a tile of up to TILE candidates.
+template <int TILE>
+struct TileLds {
+    int64_t s_off[FX_LDSP + 1];
+    uint32_t pk[TILE];
+    uint32_t wmax[FX_BS / 64];
+};
+
+// Stages the offsets (and clears the partial map) without the barrier; the
+// caller syncs, then calls map_tile_parts.
+template <int TILE>
+__device__ __forceinline__ TileMap map_tile_async(const int64_t *__restrict__ off, const FxTile &T, uint64_t t0,
+                                                  TileLds<TILE> &L)
 {
     TileMap m;
     m.p0 = T.p0;
     m.np = T.np;
     m.staged = m.np + 1 <= FX_LDSP;
+    m.t0 = t0;
+    m.pk = L.pk;
     if (m.staged) {
-        for (int64_t k = threadIdx.x; k <= m.np; k += FX_BS) s_off[k] = off[m.p0 + k];  // off[p1 + 1] exists
+        for (int64_t k = threadIdx.x; k <= m.np; k += FX_BS) L.s_off[k] = off[m.p0 + k];  // off[p1 + 1] exists
+        if (m.np > 1)
+            for (uint32_t i = threadIdx.x; i < (uint32_t)TILE; i += FX_BS) L.pk[i] = 0;
     }
     return m;
 }
 
-__device__ __forceinline__ TileMap map_tile(const int64_t *__restrict__ off, const FxTile &T, int64_t *s_off)
+// After the barrier that follows map_tile_async: every partial k >= 1 whose
+// first candidate lies in the tile marks that slot with k (an LDS atomic max:
+// partials without candidates start where the next one does, and the last of
+// them owns the slot), then a workgroup-wide prefix max over the slots gives
+// every candidate its partial.  One LDS read per candidate afterwards instead
+// of a binary search over the staged offsets.  Ends with a barrier.
+template <int TILE>
+__device__ __forceinline__ void map_tile_parts(const TileMap &m, TileLds<TILE> &L)
 {
-    const TileMap m = map_tile_async(off, T, s_off);
+    if (!m.staged || m.np <= 1) return;  // uniform: one partial needs no map
+    constexpr int PER = TILE / FX_BS;
+    for (int64_t k = 1 + threadIdx.x; k <= m.np; k += FX_BS) {
+        const uint64_t rel = (uint64_t)L.s_off[k] - m.t0;  // > 0: p0 is the last partial starting at or before t0
+        if (rel < (uint64_t)TILE) atomicMax(&L.pk[rel], (uint32_t)k);
+    }
     __syncthreads();
+    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
+    uint32_t v[PER], run = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        run = max(run, L.pk[threadIdx.x * PER + j]);
+        v[j] = run;
+    }
+    uint32_t inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o);
+        if (lane >= (uint32_t)o) inc = max(inc, u);
+    }
+    uint32_t before = __shfl_up(inc, 1);
+    if (lane == 0) before = 0;
+    if (lane == 63) L.wmax[wave] = inc;
+    __syncthreads();
+    for (uint32_t w = 0; w < wave; w++) before = max(before, L.wmax[w]);
+#pragma unroll
+    for (int j = 0; j < PER; j++) L.pk[threadIdx.x * PER + j] = max(before, v[j]);
+    __syncthreads();
+}
+
+template <int TILE>
+__device__ __forceinline__ TileMap map_tile(const int64_t *__restrict__ off, const FxTile &T, uint64_t t0,
+                                            TileLds<TILE> &L)
+{
+    const TileMap m = map_tile_async<TILE>(off, T, t0, L);
+    __syncthreads();
+    map_tile_parts<TILE>(m, L);
     return m;
 }
 
 // Partial of flattened candidate t (t inside the tile of m).
-__device__ __forceinline__ int64_t tile_part(const TileMap &m, const int64_t *__restrict__ off, const int64_t *s_off,
-                                             uint64_t t)
+__device__ __forceinline__ int64_t tile_part(const TileMap &m, const int64_t *__restrict__ off, uint64_t t)
 {
+    if (m.np <= 1) return m.p0;
+    if (m.staged) return m.p0 + (int64_t)m.pk[t - m.t0];
     int64_t lo = 0, hi = m.np;  // largest k with offset[p0 + k] <= t
-    if (m.staged) {
-        while (hi - lo > 1) {
-            int64_t mid = (lo + hi) >> 1;
-            if ((uint64_t)s_off[mid] <= t) lo = mid;
-            else hi = mid;
-        }
-    } else {
+    {
         while (hi - lo > 1) {
             int64_t mid = (lo + hi) >> 1;
             if ((uint64_t)off[m.p0 + mid] <= t) lo = mid;
@@ -499,22 +556,23 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
 // and, when pi is given, its partial relative to the tile's first.
 // Counting segments count (and hash) here; the per-query counters and byte
 // tallies are added with one atomic per wave.
+template <int TILE>
 struct ProbeLds {
-    int64_t s_off[FX_LDSP + 1];
+    TileLds<TILE> map;
     uint8_t s_dead[FX_LDSP];
     uint32_t wcnt[FX_BS / 64];
 };
 
 template <int ITEMS, int W>
 __device__ __forceinline__ TileMap probe_core(const FxGraphDev &g, const FxSeg &S, const FxTile &T, const uint32_t blk,
-                                              ProbeLds &lds, uint64_t (&bal)[ITEMS], int32_t *cv, int32_t *pi)
+                                              ProbeLds<FX_BS * ITEMS> &lds, uint64_t (&bal)[ITEMS], int32_t *cv,
+                                              int32_t *pi)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
-    int64_t *s_off = lds.s_off;
     uint8_t *s_dead = lds.s_dead;
     const int32_t l = S.l, n = S.n, flags = S.flags;
     const uint32_t tile0 = (blk - S.blk0) * TILE;
-    const TileMap m = map_tile(S.in.off, T, s_off);
+    const TileMap m = map_tile<TILE>(S.in.off, T, S.t0 + tile0, lds.map);
     const bool ufilter = (flags & FX_PROBE_UFILTER) != 0;
     uint32_t bytes = 0;
     // The used-set test of a partial's own vertices, once per partial of the
@@ -547,7 +605,7 @@ __device__ __forceinline__ TileMap probe_core(const FxGraphDev &g, const FxSeg &
         if (tl < S.span) {
             const uint64_t t = S.t0 + tl;
             Cand<W> x;
-            const int64_t p = tile_part(m, S.in.off, s_off, t);
+            const int64_t p = tile_part(m, S.in.off, t);
             load_cand(g, S.in, l, p, t, x);
             if (pi) pi[it * FX_BS + threadIdx.x] = (int32_t)(p - m.p0);
             // candidate entry + the pass word; the partial row and its run descriptor once
@@ -653,7 +711,7 @@ __device__ __forceinline__ TileMap probe_core(const FxGraphDev &g, const FxSeg &
 template <int ITEMS, int W>
 __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__restrict__ segs,
                                            const FxTile *__restrict__ tmap, int32_t *cand, uint32_t *bcnt,
-                                           const uint32_t blk, ProbeLds &lds)
+                                           const uint32_t blk, ProbeLds<FX_BS * ITEMS> &lds)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
     const FxTile T = tmap[blk];
@@ -672,7 +730,7 @@ template <int ITEMS, int W>
 __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe(
     FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, int32_t *cand, uint32_t *bcnt)
 {
-    __shared__ ProbeLds lds;
+    __shared__ ProbeLds<FX_BS * ITEMS> lds;
     probe_tile<ITEMS, W>(g, segs, tmap, cand, bcnt, blockIdx.x, lds);
 }
 
@@ -681,7 +739,7 @@ __global__ __launch_bounds__(FX_BS) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     FxGraphDev g, const FxSeg *__restrict__ segs, const FxTile *__restrict__ tmap, int32_t *cand, uint32_t *bcnt,
     const FxChainCtl *ctl)
 {
-    __shared__ ProbeLds lds;
+    __shared__ ProbeLds<FX_BS * ITEMS> lds;
     const uint32_t nb = ctl->nblocks;
     for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
         probe_tile<ITEMS, W>(g, segs, tmap, cand, bcnt, b, lds);
@@ -848,7 +906,7 @@ __global__ __launch_bounds__(FX_BS) void k_scan_blocks_chain(const T *__restrict
 // than the level holds rows.
 template <int ITEMS>
 struct ScatterLds {
-    int64_t s_off[FX_LDSP + 1];
+    TileLds<FX_BS * ITEMS> map;
     uint32_t wcnt[ITEMS][FX_BS / 64];
     unsigned long long ltot[ITEMS][FX_BS / 64];
 };
@@ -860,7 +918,6 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
                                              ScatterLds<ITEMS> &lds)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
-    int64_t *s_off = lds.s_off;
     auto &wcnt = lds.wcnt;
     auto &ltot = lds.ltot;
     const FxTile T = tmap[blk];
@@ -875,7 +932,7 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
     const int32_t l = S.l, n = S.n;
     // the partials' offsets are staged (for a counting segment or a tile that
     // writes nothing, needlessly) while the segment's pass offsets load
-    const TileMap m = map_tile_async(S.in.off, T, s_off);
+    const TileMap m = map_tile_async<TILE>(S.in.off, T, S.t0 + (blk - S.blk0) * TILE, lds.map);
     const uint64_t seg_base = boff[S.blk0];
     const uint64_t seg_pass = boff[S.blk0 + (S.span + TILE - 1) / TILE] - seg_base;
     const uint64_t cap = S.kind == FX_SEG_COUNT ? seg_pass : (uint64_t)S.out_cap;
@@ -906,6 +963,7 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
         if (__lane_id() == 0) wcnt[it][wave] = (uint32_t)__popcll(bal[it]);
     }
     __syncthreads();  // the staged offsets and the wave counts
+    map_tile_parts<TILE>(m, lds.map);
     const int32_t w1 = l + 1;
     uint32_t bytes = 0;
     uint64_t pos = boff[blk] - seg_base;
@@ -925,7 +983,7 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
         if (f[it]) {
             const uint64_t t = S.t0 + tl;
             Cand<W> x;
-            const int32_t *row = S.in.rows + tile_part(m, S.in.off, s_off, t) * l;
+            const int32_t *row = S.in.rows + tile_part(m, S.in.off, t) * l;
 #pragma unroll
             for (int k = 0; k < W; k++) x.v[k] = (k < l) ? row[k] : -1;
             x.c = cv[it];
@@ -1090,7 +1148,7 @@ __global__ __launch_bounds__(FX_BS) void k_fix_off_chain(const FxSeg *__restrict
 
 template <int ITEMS>
 struct ExpandLds {
-    ProbeLds probe;
+    ProbeLds<FX_BS * ITEMS> probe;
     int32_t cv[FX_BS * ITEMS];  // candidate ids (-1: did not pass)
     int32_t pi[FX_BS * ITEMS];  // their partials, relative to the tile's first
     uint32_t wc[ITEMS][FX_BS / 64];
