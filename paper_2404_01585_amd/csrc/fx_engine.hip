@@ -410,7 +410,7 @@ EngineWork::ChainGraph &EngineWork::chain_graph(const ChainGraphKey &key)
     return *lru;
 }
 
-fx_status EngineWork::init_events()
+fx_status EngineWork::init_events(int lanes)
 {
     for (auto &L : lane) {
         if (!L.done) FX_HIP(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
@@ -418,8 +418,13 @@ fx_status EngineWork::init_events()
             if (!e) FX_HIP(hipEventCreate(&e));
     }
     if (!start_ev) FX_HIP(hipEventCreateWithFlags(&start_ev, hipEventDisableTiming));
-    for (auto &st : own_stream)
-        if (!st) FX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (int g = 0; g + 1 < lanes && g < FX_MAX_LANES - 1; g++)
+        if (!own_stream[g]) FX_HIP(hipStreamCreateWithFlags(&own_stream[g], hipStreamNonBlocking));
+    return FX_OK;
+}
+
+fx_status EngineWork::init_chain_stream()
+{
     if (!chain_stream) FX_HIP(hipStreamCreateWithFlags(&chain_stream, hipStreamNonBlocking));
     return FX_OK;
 }
@@ -783,7 +788,7 @@ fx_status FxEngine::step()
             FX_TRY(L.inits_h.ensure((size_t)A * sizeof(FxInit)));
             FX_TRY(L.sums_h.ensure((size_t)A * sizeof(FxSummary)));
         }
-        FX_TRY(W_->init_events());
+        FX_TRY(W_->init_events(P_.lanes));
         if (P_.lanes > 1) {
             // lanes 1.. start after whatever the caller queued on the engine's stream
             FX_HIP(hipEventRecord(W_->start_ev, s_));
@@ -1247,6 +1252,7 @@ fx_status FxEngine::chain_step(double &waited)
         c.seg_l = -1;
     }
     // the chain runs on its own stream, after everything queued on the lanes
+    FX_TRY(W_->init_chain_stream());
     hipStream_t cs = W_->chain_stream;
     for (int g = 0; g < P_.lanes; g++) {
         FX_HIP(hipEventRecord(W_->lane[g].done, ls_[g]));

@@ -158,7 +158,14 @@ struct EngineWork {
     ChainGraph chain[kChainGraphs];
     uint64_t chain_clock = 0;
     ~EngineWork();
-    fx_status init_events();
+    // Events of every lane, and streams for lanes 1 .. lanes-1 only.  The
+    // hardware queues of a process are few (four by default) and streams are
+    // mapped onto them in creation order, so a stream that is never used can
+    // make two lanes share a queue, which serialises their kernels: the chain
+    // stream is created on first use, and an engine with one lane (the
+    // allocation-free path) creates none.
+    fx_status init_events(int lanes);
+    fx_status init_chain_stream();
     // the captured chain for `key`, or a free (least recently used) entry
     // for it after destroying what it held
     ChainGraph &chain_graph(const ChainGraphKey &key);

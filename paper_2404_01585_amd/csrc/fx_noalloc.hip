@@ -107,7 +107,7 @@ fx_status fx_noalloc_setup(fx_ctx *c)
     FX_TRY(L.stage_h.ensure(4096));
     FX_TRY(L.inits_h.ensure(sizeof(FxInit)));
     FX_TRY(L.sums_h.ensure(sizeof(FxSummary)));
-    FX_TRY(W->init_events());
+    FX_TRY(W->init_events(1));  // one lane: no streams of its own
     c->na_work = std::move(W);
     return FX_OK;
 }
