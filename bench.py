@@ -222,8 +222,8 @@ def cpu_baseline(pool, threads: int, g, cands, sigmas, lams, seconds: float):
                        f"(leaf-ended patterns in closed form)")
 
 
-def serving_queries(g, count: int, seed: int):
-    """Support queries of the serving workload: patterns of 3-8 vertices
+def serving_queries(g, count: int, seed: int, kmax: int = 8):
+    """Support queries of the serving workload: patterns of 3-kmax vertices
     sampled from the graph, sigma log-uniform in [50, 5000], lambda uniform in
     {0.1, 0.5, 1.0}."""
     import numpy as np
@@ -231,7 +231,7 @@ def serving_queries(g, count: int, seed: int):
     from paper_2404_01585_amd.synth import sample_patterns
 
     rng = np.random.default_rng(seed)
-    pats = sample_patterns(g, count, seed=seed, kmin=3, kmax=8)
+    pats = sample_patterns(g, count, seed=seed, kmin=3, kmax=kmax)
     sig = np.floor(np.exp(rng.uniform(np.log(50), np.log(5001), size=count))).astype(np.int64)
     lam = rng.choice([0.1, 0.5, 1.0], size=count)
     return pats, [int(x) for x in sig], [float(x) for x in lam]
@@ -262,8 +262,17 @@ def run_served(srv, queries, rate: float, mode: int, seed: int):
             log(f"[serve] {i + 1}/{n} submitted at {rate} q/s")
     log(f"[serve] {n} submitted at {rate} q/s")
     res = []
+    last = time.perf_counter()
     for k, t in enumerate(tickets):
-        res.append(srv.wait(t))
+        while True:  # a long query: report the server's device steps meanwhile
+            r = srv.poll(t)
+            if r is not None:
+                break
+            time.sleep(0.0005)
+            if time.perf_counter() - last > 15.0:
+                last = time.perf_counter()
+                log(f"[serve] {k}/{n} answered, {srv.stats()['steps']} server device steps so far")
+        res.append(r)
         if (k + 1) % 1000 == 0:
             log(f"[serve] {k + 1}/{n} answered")
     wall = time.perf_counter() - t0
@@ -304,7 +313,7 @@ def serve_sweep(args):
     torch.cuda.set_device(0)
     ctx = fx.Context(device=0, no_digest=True, count_cap=args.serve_count_cap)
     dg = ctx.load_graph(g)
-    queries = serving_queries(g, args.serve_queries, seed=4)
+    queries = serving_queries(g, args.serve_queries, seed=4, kmax=args.serve_kmax)
     log(f"[serve] {len(queries[0])} queries sampled from {args.serve_graph}")
     out = []
     plan = (("verdict", fx.MODE_VERDICT, args.serve_rates, queries),
@@ -327,7 +336,7 @@ def serve_sweep(args):
     line = {"metric": "p50/p99 support-query latency and throughput at 1 GPU (served, continuous batching)",
             "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
             "config": {"workload": f"{args.serve_graph}-serve: {GRAPH_DESC[args.serve_graph]} resident; Poisson "
-                                   "arrivals; patterns of 3-8 vertices sampled from the graph; sigma log-uniform "
+                                   f"arrivals; patterns of 3-{args.serve_kmax} vertices sampled from the graph; sigma log-uniform "
                                    "[50, 5000]; lambda in {0.1, 0.5, 1.0}", "queries_per_rate_verdict": args.serve_queries,
                        "queries_per_rate_full": args.serve_full_queries, "count_cap_full": args.serve_count_cap,
                        "step_candidates": args.serve_step},
@@ -462,6 +471,7 @@ def main():
     ap.add_argument("--serve-count-cap", type=int, default=10 ** 9)
     ap.add_argument("--serve-step", type=int, default=1 << 22, help="candidates per device step of the server")
     ap.add_argument("--no-fifo", action="store_true")
+    ap.add_argument("--serve-kmax", type=int, default=8, help="largest pattern size of the serving queries")
     ap.add_argument("--serve-probe-rate", type=float, default=1000.0,
                     help="rate of the short serving probe in the default run (0: skip)")
     ap.add_argument("--serve-probe-queries", type=int, default=1000)
