@@ -84,7 +84,7 @@ GRAPH_DESC = {"cl100k": "Chung-Lu 100K vertices / 500K edges (gamma 2.1), 20 Zip
               "rmat22": "R-MAT scale 22 (4,194,304 vertices, 40M edges), 50 Zipf(1.1) vertex labels, 4 edge labels",
               "cl1m": "Chung-Lu 1M vertices / 8M edges (gamma 2.3), 30 Zipf(1.0) vertex labels, 1 edge label"}
 SHAPE_KEYS = ("slice_rows", "step_candidates", "items_per_thread", "last_span_init", "lanes", "max_active")
-ENGINE_KEYS = ("chain_queries", "chain_steps", "fused")  # engine choices (library defaults unless given)
+ENGINE_KEYS = ("chain_queries", "chain_steps", "fused", "fused_below")  # engine choices (library defaults unless given)
 
 
 def log(*a):
@@ -372,9 +372,10 @@ def roofline_pass(ctx, dg, batches, mode, repeats: int, count_ref: bool, traffic
     events around every launch; then, when count_ref, again with the same
     launches and the reference algorithmic bytes counted on the device (extra
     loads, so never in the timed pass)."""
-    lanes0, chain0 = ctx.get("lanes"), ctx.get("chain_queries")
+    lanes0, chain0, below0 = ctx.get("lanes"), ctx.get("chain_queries"), ctx.get("fused_below")
     ctx.set("lanes", 1)
     ctx.set("chain_queries", 0)  # both passes host-scheduled, so their launches are the same
+    ctx.set("fused_below", 0)    # and every step of one form
     marker()
     ctx.set("kernel_timing", 1)
     ctx.stats(reset=True)
@@ -396,6 +397,7 @@ def roofline_pass(ctx, dg, batches, mode, repeats: int, count_ref: bool, traffic
         log("[bench] roofline counting pass done")
     ctx.set("lanes", lanes0)
     ctx.set("chain_queries", chain0)
+    ctx.set("fused_below", below0)
     per = {}
     fused = bool(ctx.get("fused"))
     for key, name in (FUSED_KERNELS if fused else KERNELS):

@@ -193,6 +193,7 @@ extern "C" fx_status fx_ctx_set(fx_ctx *c, const char *key, int64_t value)
     else if (k == "ref_bytes" && in(0, 1)) P.ref_bytes = value != 0;
     else if (k == "check_steps" && in(0, 1)) P.check_steps = value != 0;
     else if (k == "fused" && in(0, 1)) P.fused = value != 0;
+    else if (k == "fused_below" && in(0, INT32_MAX)) P.fused_below = (int32_t)value;
     else return fx_fail(FX_EINVAL, "unknown tunable '%s' or value %lld out of range", key, (long long)value);
     return FX_OK;
 }
@@ -218,6 +219,7 @@ extern "C" fx_status fx_ctx_get(fx_ctx *c, const char *key, int64_t *value)
     else if (k == "ref_bytes") *value = P.ref_bytes ? 1 : 0;
     else if (k == "check_steps") *value = P.check_steps ? 1 : 0;
     else if (k == "fused") *value = P.fused ? 1 : 0;
+    else if (k == "fused_below") *value = P.fused_below;
     else return fx_fail(FX_EINVAL, "unknown tunable '%s'", key);
     return FX_OK;
 }

@@ -981,12 +981,16 @@ fx_status FxEngine::launch(int g)
     FX_HIP(hipMemcpyAsync(L.stage_d.p, L.stage_h.p, seg_off + (size_t)nsegs * sizeof(FxSeg), hipMemcpyHostToDevice,
                           st));
     hipEvent_t *ev = P_.timing ? L.evk : nullptr;
+    // small steps (a lone query, a single call) take the single-pass form:
+    // two launches fewer per step, and few tiles to wait on in its ordered write
+    const int fused = (P_.fused || nblocks <= (uint32_t)std::max<int32_t>(P_.fused_below, 0)) ? 1 : 0;
+    fused_[g] = fused;
     FX_HIP(fx_launch_step(st, G_->dev, (const FxSeg *)((char *)L.stage_d.p + seg_off), L.stage_d.as<uint32_t>(),
                           nsegs, nblocks, P_.items, maxn, L.tmap.as<FxTile>(), L.cand.as<int32_t>(), L.bcnt.as<uint32_t>(),
                           L.boff.as<uint64_t>(), L.lsum.as<uint64_t>(), L.loff.as<uint64_t>(), L.sstat.as<uint64_t>(),
                           ev ? ev[0] : nullptr,
                           ev ? ev[1] : nullptr, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
-                          ev ? ev[5] : nullptr, any_inner, any_greedy, P_.fused ? 1 : 0));
+                          ev ? ev[5] : nullptr, any_inner, any_greedy, fused));
     int hi = 0;
     for (auto &qp : act) hi = std::max(hi, qp->slot + 1);
     FX_HIP(hipMemcpyAsync(L.sums_h.p, sums_d, (size_t)hi * sizeof(FxSummary), hipMemcpyDeviceToHost, st));
@@ -1024,13 +1028,13 @@ fx_status FxEngine::collect(int g, double &waited)
     stats_->steps++;
     stats_->syncs++;
     stats_->probe_launches++;
-    if (!P_.fused) stats_->scatter_launches++;
+    if (!fused_[g]) stats_->scatter_launches++;
     if (any_greedy_[g]) stats_->greedy_launches++;
     if (P_.timing) {
         float ms = 0;
         FX_HIP(hipEventElapsedTime(&ms, L.evk[0], L.evk[1]));
         stats_->probe_ms += ms;
-        if (!P_.fused) {
+        if (!fused_[g]) {
             FX_HIP(hipEventElapsedTime(&ms, L.evk[2], L.evk[3]));
             stats_->scatter_ms += ms;
         }

@@ -102,6 +102,7 @@ struct EngineParams {
     bool ref_bytes = false;   // count the reference algorithmic bytes (extra loads: a counting pass)
     bool check_steps = false; // check every step's segment table and tile map on the host (fx_check.h)
     bool fused = false;       // single-pass expansion kernel (else probe, scans, scatter, offset fix-up)
+    int32_t fused_below = 64; // ... also for host-scheduled steps of at most this many workgroups
     bool lone_growth = true;  // long VERDICT queries left nearly alone may grow their support stacks
     int32_t chain_queries = 8;    // at most this many queries left (none waiting): device-scheduled steps
     int32_t chain_steps = 16;     // steps per chain (one host synchronisation each)
@@ -293,6 +294,7 @@ private:
     size_t rot_[FX_MAX_LANES] = {};
     bool in_flight_[FX_MAX_LANES] = {};
     int any_greedy_[FX_MAX_LANES] = {};
+    int fused_[FX_MAX_LANES] = {};  // the lane's last step ran the single-pass expansion
     uint64_t nopen_[FX_MAX_LANES] = {};  // queries with candidates left, per lane, at its last launch
     int lane_ = 0;  // the lane the next step() serves
     int32_t chain_k_ = 0;  // steps of the last device-scheduled chain

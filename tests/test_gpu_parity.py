@@ -846,9 +846,10 @@ def test_directed_graphs(ctx, ctx_small):
 
 
 def test_both_expansion_forms(torch_cuda, er1k):
-    """The single-pass expansion (one kernel per step, positions by look-back)
-    and the multi-kernel form (probe, block scans, scatter, offset fix-up, the
-    default) give the oracle's results: tiny graphs with 64-row slices (every
+    """The single-pass expansion (one kernel per step, positions by look-back;
+    the default for steps of at most 64 workgroups) and the multi-kernel form
+    (probe, block scans, scatter, offset fix-up; the default for larger steps)
+    each give the oracle's results when every step takes it: tiny graphs with 64-row slices (every
     level cut at its row cap many times), a mining batch, and device-scheduled
     chains; the launch counts show which form ran."""
     g = er1k
@@ -857,7 +858,8 @@ def test_both_expansion_forms(torch_cuda, er1k):
     for fused in (1, 0):
         small = fx.Context(device=0, slice_rows=64, run_index_bytes=-1)
         small.set("fused", fused)
-        assert small.get("fused") == fused
+        small.set("fused_below", 0)  # every step in the form under test (small steps default to the single pass)
+        assert small.get("fused") == fused and small.get("fused_below") == 0
         small.stats(reset=True)
         for idx, gt, p in _tiny_cases(40, 97):
             _say("forms fused", fused, "tiny", idx)
@@ -870,6 +872,7 @@ def test_both_expansion_forms(torch_cuda, er1k):
         assert (st["scatter_launches"] == 0) if fused else (st["scatter_launches"] == st["probe_launches"])
         big = fx.Context(device=0)
         big.set("fused", fused)
+        big.set("fused_below", 0)
         with big.load_graph(g) as dg:
             _say("forms fused", fused, "batch", len(cands))
             got = dg.support_batch(cands, [20] * len(cands), [1.0] * len(cands), fx.MODE_FULL)
