@@ -775,7 +775,7 @@ fx_status FxEngine::step()
         FX_TRY(W_->sums_d.ensure((size_t)A * sizeof(FxSummary)));
         for (int g = 0; g < P_.lanes; g++) {
             EngineLane &L = W_->lane[g];
-            FX_TRY(L.cand.ensure(max_blocks * tile * 4));
+            FX_TRY(L.cand.ensure(max_blocks * cand_tile_bytes(P_.items)));
             FX_TRY(L.bcnt.ensure(max_blocks * 4));
             FX_TRY(L.boff.ensure((max_blocks + 1) * 8));
             FX_TRY(L.lsum.ensure(max_blocks * 8));

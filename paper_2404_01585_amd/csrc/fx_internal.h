@@ -44,6 +44,13 @@
 #define FX_MAX_TILE (FX_BS * 8)  // most candidates per expansion workgroup (8 per thread)
 #define FX_LDSP 1024         // partial offsets a workgroup stages in LDS
 
+// The probe's output per expansion workgroup (tile of FX_BS * items
+// candidates): the passing candidates' vertex ids, compacted within each
+// (item, wave) region of 64 candidate slots in candidate order; for each, its
+// partial relative to the tile's first with the candidate's lane in the top 6
+// bits; and the passing count of every region (at most 32 regions).
+__host__ __device__ constexpr size_t cand_tile_bytes(int items) { return (size_t)FX_BS * items * 8 + 32; }
+
 // Block scans of a step: chunks of kScanChunk per-workgroup values, each
 // chunk's prefix found by look-back; a step's scan state is two scans' status
 // words and tickets.

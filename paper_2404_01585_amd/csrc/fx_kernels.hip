@@ -551,9 +551,13 @@ __device__ __forceinline__ uint64_t leaf_count(const FxGraphDev &g, const FxPlan
 
 // Test every candidate of a workgroup's tile (ITEMS per thread, strided by
 // the workgroup size so each item pass covers consecutive candidates).  Per
-// item, the wave's ballot of the candidates that pass (bal); per candidate,
-// at cv[it * FX_BS + threadIdx.x], its vertex id (-1 when it does not pass)
-// and, when pi is given, its partial relative to the tile's first.
+// item, the wave's ballot of the candidates that pass (bal).  Per candidate,
+// without COMPACT: at cv[it * FX_BS + threadIdx.x] its vertex id (-1 when it
+// does not pass) and at pi[...] its partial relative to the tile's first.
+// With COMPACT, only the passing candidates, in order within their (item,
+// wave) region of 64 slots: the vertex id, and the partial with the
+// candidate's lane in the top 6 bits (a partial index is below 2^26: the
+// slice capacity is at most 2^26 rows).
 // Counting segments count (and hash) here; the per-query counters and byte
 // tallies are added with one atomic per wave.
 template <int TILE>
@@ -563,7 +567,7 @@ struct ProbeLds {
     uint32_t wcnt[FX_BS / 64];
 };
 
-template <int ITEMS, int W>
+template <int ITEMS, int W, bool COMPACT>
 __device__ __forceinline__ TileMap probe_core(const FxGraphDev &g, const FxSeg &S, const FxTile &T, const uint32_t blk,
                                               ProbeLds<FX_BS * ITEMS> &lds, uint64_t (&bal)[ITEMS], int32_t *cv,
                                               int32_t *pi)
@@ -602,12 +606,15 @@ __device__ __forceinline__ TileMap probe_core(const FxGraphDev &g, const FxSeg &
     for (int it = 0; it < ITEMS; it++) {
         const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
         bool mat = false;
+        int32_t c_out = 0, pk_out = 0;
         if (tl < S.span) {
             const uint64_t t = S.t0 + tl;
             Cand<W> x;
             const int64_t p = tile_part(m, S.in.off, t);
             load_cand(g, S.in, l, p, t, x);
-            if (pi) pi[it * FX_BS + threadIdx.x] = (int32_t)(p - m.p0);
+            c_out = x.c;
+            pk_out = (int32_t)(p - m.p0);
+            if (!COMPACT && pi) pi[it * FX_BS + threadIdx.x] = pk_out;
             // candidate entry + the pass word; the partial row and its run descriptor once
             bytes += (x.anc >= 0 ? 8u : 4u) + 4u;
             if (x.first || tl == tile0) bytes += 4u * (uint32_t)l + 21u;
@@ -660,9 +667,14 @@ __device__ __forceinline__ TileMap probe_core(const FxGraphDev &g, const FxSeg &
                 if (leaf) cnt += leaf_count(g, S.plan, l, x, bytes);
                 mat = S.kind != FX_SEG_COUNT;
             }
-            cv[it * FX_BS + threadIdx.x] = mat ? x.c : -1;
+            if (!COMPACT) cv[it * FX_BS + threadIdx.x] = mat ? x.c : -1;
         }
         bal[it] = __ballot(mat);
+        if (COMPACT && mat) {
+            const uint32_t slot = it * FX_BS + (threadIdx.x & ~63u) + (uint32_t)__popcll(bal[it] & lanemask_lt());
+            cv[slot] = c_out;
+            pi[slot] = (int32_t)(((uint32_t)__lane_id() << 26) | (uint32_t)pk_out);
+        }
     }
     if (count || leaf) {  // uniform across the workgroup
         unsigned long long c = cnt;
@@ -705,9 +717,9 @@ __device__ __forceinline__ TileMap probe_core(const FxGraphDev &g, const FxSeg &
     return m;
 }
 
-// Probe pass of the multi-kernel expansion: per candidate its vertex id when
-// it passes (-1 when not), so the scatter never reads the candidate's
-// adjacency entry again, and the number of passes per workgroup.
+// Probe pass of the multi-kernel expansion: the tile's passing candidates
+// compacted per (item, wave) region with their partials, the regions'
+// counts (cand_tile_bytes per tile), and the number of passes per workgroup.
 template <int ITEMS, int W>
 __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__restrict__ segs,
                                            const FxTile *__restrict__ tmap, int32_t *cand, uint32_t *bcnt,
@@ -716,12 +728,19 @@ __device__ __forceinline__ void probe_tile(const FxGraphDev &g, const FxSeg *__r
     constexpr uint32_t TILE = FX_BS * ITEMS;
     const FxTile T = tmap[blk];
     const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
+    int32_t *crec = (int32_t *)((char *)cand + (size_t)blk * cand_tile_bytes(ITEMS));
     uint64_t bal[ITEMS];
-    probe_core<ITEMS, W>(g, S, T, blk, lds, bal, cand + (uint64_t)blk * TILE, nullptr);
+    probe_core<ITEMS, W, true>(g, S, T, blk, lds, bal, crec, crec + TILE);
     uint32_t passed = 0;
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) passed += (uint32_t)__popcll(bal[it]);
-    if (__lane_id() == 0) lds.wcnt[threadIdx.x >> 6] = passed;
+    if (__lane_id() == 0) {
+        uint8_t *rc = (uint8_t *)(crec + 2 * TILE);
+        const uint32_t wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int it = 0; it < ITEMS; it++) rc[it * (FX_BS / 64) + wave] = (uint8_t)__popcll(bal[it]);
+        lds.wcnt[wave] = passed;
+    }
     __syncthreads();
     if (threadIdx.x == 0) bcnt[blk] = lds.wcnt[0] + lds.wcnt[1] + lds.wcnt[2] + lds.wcnt[3];
 }
@@ -896,19 +915,20 @@ __global__ __launch_bounds__(FX_BS) void k_scan_blocks_chain(const T *__restrict
 
 // Ordered write of the passing candidates of each segment into its level l+1
 // (position = passes before it in the segment, in candidate order), with the
-// candidate run of the next pattern vertex for inner levels.  For inner
-// segments it also writes each new row's prefix of run lengths within this
-// workgroup's rows to off[] and the workgroup's total to lsum[]; k_fix_off
-// adds the workgroup offsets after a scan of lsum.  A segment writes at most
-// out_cap rows: when more candidates pass, writing stops at the out_cap-th
-// and the summary records how many candidates that took (the rest are
-// probed again in a later step), so a slice may span many more candidates
-// than the level holds rows.
+// candidate run of the next pattern vertex for inner levels.  A workgroup
+// takes its tile's passing candidates from the probe's compacted output, one
+// thread each in candidate order (the regions' counts give each one's
+// region).  For inner segments it also writes each new row's prefix of run
+// lengths within this workgroup's rows to off[] and the workgroup's total to
+// lsum[]; k_fix_off adds the workgroup offsets after a scan of lsum.  A
+// segment writes at most out_cap rows: when more candidates pass, writing
+// stops at the out_cap-th and the summary records how many candidates that
+// took (the rest are probed again in a later step), so a slice may span many
+// more candidates than the level holds rows.
 template <int ITEMS>
 struct ScatterLds {
-    TileLds<FX_BS * ITEMS> map;
-    uint32_t wcnt[ITEMS][FX_BS / 64];
-    unsigned long long ltot[ITEMS][FX_BS / 64];
+    uint32_t rpre[FX_BS * ITEMS / 64];     // passes before each (item, wave) region of the tile
+    unsigned long long ltot[FX_BS / 64];   // run-length totals of the waves in a round
 };
 
 template <int ITEMS, int W>
@@ -918,21 +938,16 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
                                              ScatterLds<ITEMS> &lds)
 {
     constexpr uint32_t TILE = FX_BS * ITEMS;
-    auto &wcnt = lds.wcnt;
-    auto &ltot = lds.ltot;
+    constexpr uint32_t NR = TILE / 64;  // regions: (item, wave)
+    static_assert(NR <= 64, "one wave scans the region counts");
+    const int32_t *crec = (const int32_t *)((const char *)cand + (size_t)blk * cand_tile_bytes(ITEMS));
     const FxTile T = tmap[blk];
     // loads that do not depend on the segment first, so their latencies
-    // overlap the segment's: the tile's probe results (the buffer holds whole
-    // tiles; entries past the span are masked below) and its pass offsets
-    int32_t cv[ITEMS];  // the passing candidates' vertex ids (from the probe)
-#pragma unroll
-    for (int it = 0; it < ITEMS; it++) cv[it] = cand[(uint64_t)blk * TILE + it * FX_BS + threadIdx.x];
+    // overlap the segment's
     const uint64_t b_lo = boff[blk], b_hi = boff[blk + 1];
+    const uint32_t rc = threadIdx.x < NR ? (uint32_t)((const uint8_t *)(crec + 2 * TILE))[threadIdx.x] : 0u;
     const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
     const int32_t l = S.l, n = S.n;
-    // the partials' offsets are staged (for a counting segment or a tile that
-    // writes nothing, needlessly) while the segment's pass offsets load
-    const TileMap m = map_tile_async<TILE>(S.in.off, T, S.t0 + (blk - S.blk0) * TILE, lds.map);
     const uint64_t seg_base = boff[S.blk0];
     const uint64_t seg_pass = boff[S.blk0 + (S.span + TILE - 1) / TILE] - seg_base;
     const uint64_t cap = S.kind == FX_SEG_COUNT ? seg_pass : (uint64_t)S.out_cap;
@@ -950,124 +965,120 @@ __device__ __forceinline__ void scatter_tile(const FxGraphDev &g, const FxSeg *_
         if (threadIdx.x == 0) lsum[blk] = 0;
         return;
     }
-    const uint32_t tile0 = (blk - S.blk0) * TILE;
-    const uint32_t wave = threadIdx.x >> 6;
-    uint64_t bal[ITEMS];
-    bool f[ITEMS];
+    const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x < 64) {  // exclusive prefix of the region counts
+        uint32_t inc = rc;
 #pragma unroll
-    for (int it = 0; it < ITEMS; it++) {
-        const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
-        if (tl >= S.span) cv[it] = -1;
-        f[it] = cv[it] >= 0;
-        bal[it] = __ballot(f[it]);
-        if (__lane_id() == 0) wcnt[it][wave] = (uint32_t)__popcll(bal[it]);
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o);
+            if (lane >= (uint32_t)o) inc += u;
+        }
+        if (lane < NR) lds.rpre[lane] = inc - rc;
     }
-    __syncthreads();  // the staged offsets and the wave counts
-    map_tile_parts<TILE>(m, lds.map);
+    __syncthreads();
+    const uint32_t nsurv = (uint32_t)(b_hi - b_lo);  // at most TILE
+    const uint32_t tile0 = (blk - S.blk0) * TILE;
+    const uint64_t row0 = b_lo - seg_base;          // output row of the tile's first pass
     const int32_t w1 = l + 1;
-    uint32_t bytes = 0;
-    uint64_t pos = boff[blk] - seg_base;
-    uint32_t p_out[ITEMS];  // row of the candidate in the segment's output (< out_cap when written)
-    int32_t lens[ITEMS];
+    const int32_t *in_rows = S.in.rows + T.p0 * l;  // the tile's first partial
+    uint32_t bytes = 0, written = 0;
+    uint64_t lbefore = 0;                           // run lengths of the tile's earlier rounds
+    for (uint32_t j0 = 0; j0 < nsurv; j0 += FX_BS) {  // uniform
+        const uint32_t j = j0 + threadIdx.x;          // this thread's pass, in candidate order
+        const uint64_t p_out = row0 + j;
+        bool f = false;
+        int32_t len = 0;
+        if (j < nsurv) {
+            uint32_t lo = 0, hi = NR;  // the last region starting at or before pass j
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (lds.rpre[mid] <= j) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t slot = lo * 64 + (j - lds.rpre[lo]);
+            const int32_t c = crec[slot];
+            const uint32_t pw = (uint32_t)crec[TILE + slot];
+            const int32_t pk = (int32_t)(pw & ((1u << 26) - 1u));
+            const uint32_t tl = tile0 + lo * 64 + (pw >> 26);  // the candidate's index in the segment's span
+            if (overflow && p_out == cap - 1) S.sum->consumed = tl + 1;  // the last row that fits
+            f = p_out < cap;
+            if (f) {
+                const int32_t *row = in_rows + (int64_t)pk * l;
+                int32_t v[W];
 #pragma unroll
-    for (int it = 0; it < ITEMS; it++) {
-        const uint32_t tl = tile0 + it * FX_BS + threadIdx.x;
-        lens[it] = 0;
-        p_out[it] = (uint32_t)(pos + (uint64_t)__popcll(bal[it] & lanemask_lt()));
-        for (uint32_t w = 0; w < wave; w++) p_out[it] += wcnt[it][w];
-        if (f[it] && overflow && p_out[it] == cap - 1) S.sum->consumed = tl + 1;  // the last row that fits
-        f[it] = f[it] && p_out[it] < cap;
-        // pass word read per candidate; the partial's row read, the new row and
-        // its run descriptor written per survivor
-        bytes += (tl < S.span ? 4u : 0u) + (f[it] ? 4u * (uint32_t)(l + w1) : 0u) + ((f[it] && w1 < n) ? 21u : 0u);
-        if (f[it]) {
-            const uint64_t t = S.t0 + tl;
-            Cand<W> x;
-            const int32_t *row = S.in.rows + tile_part(m, S.in.off, t) * l;
+                for (int k = 0; k < W; k++) v[k] = (k < l) ? row[k] : -1;
+                int32_t *dst = S.out.rows + p_out * (uint32_t)w1;
 #pragma unroll
-            for (int k = 0; k < W; k++) x.v[k] = (k < l) ? row[k] : -1;
-            x.c = cv[it];
-            int32_t *dst = S.out.rows + (uint64_t)p_out[it] * (uint32_t)w1;
-#pragma unroll
-            for (int k = 0; k < W; k++)
-                if (k < l) dst[k] = x.v[k];
-            dst[l] = x.c;
-            if (w1 < n) {
-                // candidate run of the next pattern vertex i2 = l + 1: the
-                // shortest run among its earlier neighbours, or its label bucket.
-                const FxPlan *plan = S.plan;
-                const int32_t i2 = w1;
-                const uint32_t vl = plan->vl[i2];
-                const int32_t nb = plan->nback[i2];
-                int64_t best_lo = 0;
-                int32_t best_len = 0;
-                int32_t best_anc = -1;
-                if (nb == 0) {
-                    best_lo = g.bptr[vl];
-                    best_len = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
-                } else {
-                    best_len = 0x7fffffff;
-                    for (int kk = 0; kk < nb; kk++) {
-                        int32_t b = plan->back[i2][kk];
-                        int32_t u = (b == l) ? x.c : pick(x.v, b);
-                        int64_t lo;
-                        int32_t len;
-                        run_of<scan_width<W>()>(g, u, run_key(vl, plan->bel[i2][kk]), lo, len, bytes);
-                        if (len < best_len) {
-                            best_len = len;
-                            best_lo = lo;
-                            best_anc = kk;
+                for (int k = 0; k < W; k++)
+                    if (k < l) dst[k] = v[k];
+                dst[l] = c;
+                bytes += 8u + 4u * (uint32_t)(l + w1) + (w1 < n ? 21u : 0u);
+                written++;
+                if (w1 < n) {
+                    // candidate run of the next pattern vertex i2 = l + 1: the
+                    // shortest run among its earlier neighbours, or its label bucket
+                    const FxPlan *plan = S.plan;
+                    const int32_t i2 = w1;
+                    const uint32_t vl = plan->vl[i2];
+                    const int32_t nb = plan->nback[i2];
+                    int64_t best_lo = 0;
+                    int32_t best_len = 0;
+                    int32_t best_anc = -1;
+                    if (nb == 0) {
+                        best_lo = g.bptr[vl];
+                        best_len = (int32_t)(g.bptr[vl + 1] - g.bptr[vl]);
+                    } else {
+                        best_len = 0x7fffffff;
+                        for (int kk = 0; kk < nb; kk++) {
+                            const int32_t b = plan->back[i2][kk];
+                            const int32_t u = (b == l) ? c : pick(v, b);
+                            int64_t rlo;
+                            int32_t rlen;
+                            run_of<scan_width<W>()>(g, u, run_key(vl, plan->bel[i2][kk]), rlo, rlen, bytes);
+                            if (rlen < best_len) {
+                                best_len = rlen;
+                                best_lo = rlo;
+                                best_anc = kk;
+                            }
                         }
                     }
+                    S.out.lo[p_out] = best_lo;
+                    S.out.len[p_out] = best_len;
+                    S.out.anc[p_out] = (int8_t)best_anc;
+                    len = best_len;
                 }
-                S.out.lo[p_out[it]] = best_lo;
-                S.out.len[p_out[it]] = best_len;
-                S.out.anc[p_out[it]] = (int8_t)best_anc;
-                lens[it] = best_len;
             }
         }
-        for (uint32_t w = 0; w < FX_BS / 64; w++) pos += wcnt[it][w];
-    }
-    if (S.kind == FX_SEG_INNER) {  // uniform across the workgroup
-        // exclusive prefix of the run lengths in output order (item, wave,
-        // lane): wave totals first, then each lane's scan within its wave
-        // (recomputed rather than kept across the barrier: fewer registers)
-        const uint32_t lane = __lane_id();
-#pragma unroll
-        for (int it = 0; it < ITEMS; it++) {
-            unsigned long long tot = (unsigned long long)lens[it];
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o);
-            if (lane == 0) ltot[it][wave] = tot;
-        }
-        __syncthreads();
-        uint64_t before = 0;
-#pragma unroll
-        for (int it = 0; it < ITEMS; it++) {
-            long long inc = lens[it];
+        if (S.kind == FX_SEG_INNER) {  // uniform: run lengths before each new row, in pass order
+            long long inc = len;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 const long long u = __shfl_up(inc, o);
                 if (lane >= (uint32_t)o) inc += u;
             }
-            uint64_t mine = before;
-            for (uint32_t w = 0; w < wave; w++) mine += ltot[it][w];
-            if (f[it]) S.out.off[p_out[it]] = (int64_t)(mine + (uint64_t)(inc - lens[it]));
-            for (uint32_t w = 0; w < FX_BS / 64; w++) before += ltot[it][w];
+            if (lane == 63) lds.ltot[wave] = (unsigned long long)inc;
+            __syncthreads();
+            uint64_t mine = lbefore, tot = 0;
+#pragma unroll
+            for (uint32_t w = 0; w < FX_BS / 64; w++) {
+                tot += lds.ltot[w];
+                mine += w < wave ? lds.ltot[w] : 0ull;
+            }
+            if (f) S.out.off[p_out] = (int64_t)(mine + (uint64_t)(inc - len));
+            lbefore += tot;
+            __syncthreads();  // ltot is reused by the next round
         }
-        if (threadIdx.x == 0) lsum[blk] = before;
     }
+    if (S.kind == FX_SEG_INNER && threadIdx.x == 0) lsum[blk] = lbefore;
     unsigned long long b = bytes;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) b += __shfl_xor(b, o);
-    if (__lane_id() == 0 && b) atomicAdd(&S.sum->alg_scatter, b);
+    if (lane == 0 && b) atomicAdd(&S.sum->alg_scatter, b);
     if (S.flags & FX_PROBE_REF) {  // reference bytes: the rows written, 4 (l + 1) each
-        unsigned long long r = 0;
-#pragma unroll
-        for (int it = 0; it < ITEMS; it++) r += f[it] ? 4u * (uint32_t)w1 : 0u;
+        unsigned long long r = 4ull * written * (uint32_t)w1;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) r += __shfl_xor(r, o);
-        if (__lane_id() == 0 && r) atomicAdd(&S.sum->ref_scatter, r);
+        if (lane == 0 && r) atomicAdd(&S.sum->ref_scatter, r);
     }
 }
 
@@ -1166,7 +1177,7 @@ __device__ __forceinline__ void expand_tile(const FxGraphDev &g, const FxSeg *__
     const FxTile T = tmap[blk];
     const FxSeg &S = segs[__builtin_amdgcn_readfirstlane(T.seg)];
     uint64_t bal[ITEMS];
-    const TileMap m = probe_core<ITEMS, W>(g, S, T, blk, lds.probe, bal, lds.cv, lds.pi);
+    const TileMap m = probe_core<ITEMS, W, false>(g, S, T, blk, lds.probe, bal, lds.cv, lds.pi);
     const int32_t l = S.l, n = S.n;
     const uint32_t tile0 = (blk - S.blk0) * TILE;
     const uint32_t nblk = (S.span + TILE - 1) / TILE;

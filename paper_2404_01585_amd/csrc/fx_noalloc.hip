@@ -75,7 +75,9 @@ fx_status fx_noalloc_setup(fx_ctx *c)
     // gives at the fixed step budget (one query: one segment)
     const uint64_t min_tile = (uint64_t)FX_BS * 2;
     const uint64_t max_blocks = (kStepCandidates + min_tile - 1) / min_tile + 1;
-    const size_t cand_bytes = (size_t)(kStepCandidates + (uint64_t)FX_MAX_TILE * 2) * 4;
+    // the probe's per-tile records: blocks x record bytes is largest for the
+    // smallest tile (a record is 8 bytes per candidate slot plus 32)
+    const size_t cand_bytes = (size_t)max_blocks * cand_tile_bytes(2);
     char *p = (char *)base;
     auto carve = [&](DevBuf &b, size_t bytes) {
         b.borrow(p, bytes);
