@@ -267,12 +267,12 @@ fx_status fx_support_batch(fx_graph *g, int32_t npat, const fx_pattern *pats, co
 
 /* Accumulated device statistics of a context (since creation or the last
  * reset).  Durations are only collected with FX_CTX_KERNEL_TIMING.
- *   probe_*     the expansion test kernel (one launch per step); with the
- *               fused tunable, the single-pass expansion kernel (test and
- *               ordered write)
- *   scatter_*   the ordered write of surviving candidates (one launch per step;
- *               no launches with the fused tunable, its bytes are still
- *               counted here)
+ *   probe_*     the expansion test kernel (one launch per step); for steps
+ *               that take the single-pass expansion (the fused and
+ *               fused_below tunables), that kernel (test and ordered write)
+ *   scatter_*   the ordered write of surviving candidates (one launch per
+ *               step, none for steps that take the single-pass expansion,
+ *               whose write bytes are still counted here)
  *   greedy_*    the greedy mIS kernels (hash build and rounds)
  *   *_alg_bytes algorithmic bytes: bytes the operation must move at minimum
  *               on this layout (8-byte packed adjacency entries, 4-byte ids),
